@@ -1,0 +1,457 @@
+"""Plain FP64 CPU oracle of the 3D skew-Gaussian rasterizer.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import this module.  It shares no code with
+the HIP product path (no kernels, headers, helpers, constants or tables); the
+only module both sides read is ``sgs_synth`` (seeded random inputs).
+
+Everything is computed in float64 with plain PyTorch CPU tensor operations,
+so that gradients are the exact derivatives of the forward definition
+(autograd), and brute force: every Gaussian is evaluated at every requested
+pixel, Gaussians are ordered near to far by camera-space depth (ties by
+ascending index) and composited front to back.  No tiles, extents or radix
+sorts are used.
+
+Paper passages followed (3D Skew Gaussian Splatting):
+  * Sec. "Preliminary of 3D Gaussian Splatting": Gaussian G(x), covariance
+    Sigma = R S S^T R^T from a quaternion and a scale, SH colour, affine
+    (EWA) projection to a 2D covariance Sigma', front-to-back compositing.
+  * Sec. "3D Skew Gaussian Kernel": S(x) = 2 G(x) Phi(beta^T (x - mu)),
+    Phi(z) = (1 + erf(z / sqrt 2)) / 2, zero skew gives 3DGS.
+  * Alg. 1 (forward pass) and the appendix "Forward Pass": 2D opacity
+    alpha = d G'(x) (1 + erf(z)), z = (beta_x dx + beta_y dy) / sqrt 2,
+    d = o sqrt(det Sigma' / det(Sigma' + sI)), (Sigma' + sI)^-1 = [[a,b],[b,c]].
+  * Sec. "3D Skew Gaussian Rasterization and Splatting": compositing equation
+    and the enhanced opacity o(x) = ((a1 + a2) + (a1 - a2) erf((beta + d)^T x
+    / sqrt 2)) / 2.
+  * Alg. 3 and Sec. "Decoupled Interactive Visual Analytics Engine": M_cv =
+    M_gl T_align with T_align = diag(1,-1,-1,1); intrinsics K from (W, H, FoV).
+
+Readings where the paper is silent or inconsistent (each is a parameter or a
+documented convention here):
+  * The 2D skew (beta_x, beta_y) consumed by the rasterizer is the exact
+    skew-normal marginal of the 3D kernel under the same affine map A used for
+    Sigma' and the same isotropic blur sI:
+        v = A Sigma beta, kappa = beta^T Sigma beta, m = v^T Q v,
+        beta_2D = Q v / sqrt(1 + kappa - m),   Q = (Sigma' + sI)^-1.
+    (Selection representation of the multivariate skew-normal; Azzalini &
+    Dalla Valle 1996, Azzalini & Capitanio 1999.)  Zero skew maps to zero.
+  * Enhanced opacity: x is the 2D offset p - mu_2D and (beta + d) is mapped to
+    2D by the same rule; with a1 = a2 it reduces to a scalar opacity.
+  * alpha is clamped to 0.99, pairs with alpha < 1/255 are skipped and a pixel
+    stops before the Gaussian that would take its transmittance below 1e-4.
+  * Low-pass filter s = 0.3 px^2 with opacity compensation; Jacobian evaluated
+    with x/z, y/z clamped to 1.3 tan(half FoV); Gaussians with z <= near are
+    culled; pixel (i, j) is sampled at (i + 0.5, j + 0.5); fy = fx (square
+    pixels, horizontal FoV); background colour defaults to black.
+  * Real spherical harmonics with the Condon-Shortley phase, ordered m = -l..l
+    (sin terms for m < 0), colour = max(0, sum + 0.5).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+F64 = torch.float64
+SQRT2 = math.sqrt(2.0)
+
+ALPHA_MIN = 1.0 / 255.0
+ALPHA_MAX = 0.99
+T_MIN = 1e-4
+
+
+@dataclass
+class Options:
+    filter_s: float = 0.3
+    compensate: bool = True
+    guard: float = 1.3
+    alpha_min: float = ALPHA_MIN
+    alpha_max: float = ALPHA_MAX
+    t_min: float = T_MIN
+    symmetric: bool = False   # drop the skew factor entirely (textbook 3DGS)
+
+
+# ------------------------------------------------------------------ camera
+T_ALIGN = np.diag([1.0, -1.0, -1.0, 1.0])
+
+
+def coord_engine(c2w_gl: np.ndarray) -> np.ndarray:
+    """OpenGL/Blender camera-to-world -> OpenCV camera-to-world,
+    M_cv = M_gl T_align (Alg. 3, Sec. "Decoupled Interactive Visual Analytics
+    Engine", coordinate-alignment equation)."""
+    return np.asarray(c2w_gl, np.float64) @ T_ALIGN
+
+
+def intrinsics(W: int, H: int, fovx_deg: float, fovy_deg: float | None = None) -> np.ndarray:
+    """K = [[W/(2 tan(FoVx/2)), 0, W/2], [0, H/(2 tan(FoVy/2)), H/2], [0,0,1]]
+    (Sec. "Decoupled Interactive Visual Analytics Engine", intrinsic mapping).
+    With one FoV given it is horizontal and pixels are square."""
+    fx = W / (2.0 * math.tan(math.radians(fovx_deg) / 2.0))
+    fy = fx if fovy_deg is None else H / (2.0 * math.tan(math.radians(fovy_deg) / 2.0))
+    return np.array([[fx, 0.0, W / 2.0], [0.0, fy, H / 2.0], [0.0, 0.0, 1.0]])
+
+
+@dataclass
+class Camera:
+    W: int
+    H: int
+    K: np.ndarray       # 3x3
+    w2c: np.ndarray     # 4x4 OpenCV world-to-camera
+    near: float
+    bg: np.ndarray      # [3]
+
+    @property
+    def position(self) -> np.ndarray:
+        return np.linalg.inv(self.w2c)[:3, 3]
+
+
+def camera_from_pose(pose) -> Camera:
+    """Frontend pose (sgs_synth.Pose) -> rasterizer camera via CoordEngine."""
+    m_cv = coord_engine(pose.c2w_gl)
+    return Camera(int(pose.width), int(pose.height),
+                  intrinsics(pose.width, pose.height, pose.fovx_deg),
+                  np.linalg.inv(m_cv), float(pose.near), np.asarray(pose.bg, np.float64))
+
+
+# ---------------------------------------------------------- spherical harm.
+def _legendre_derivative_coeffs(l: int, m: int) -> np.ndarray:
+    """Power-series coefficients of d^m/dz^m P_l(z)."""
+    c = np.polynomial.legendre.leg2poly([0] * l + [1])
+    return np.polynomial.polynomial.polyder(c, m) if m > 0 else c
+
+
+def sh_basis(deg: int, d: torch.Tensor) -> torch.Tensor:
+    """Real SH Y_lm at unit directions d [N,3] -> [N, (deg+1)^2].
+
+    Y_l0 = N_l0 P_l(z); for m > 0 the cos/sin pair is
+    sqrt(2) N_lm P_l^m(cos t) {cos m phi, sin m phi}, where
+    P_l^m(cos t) {cos, sin}(m phi) = (-1)^m P_l^(m)(z) {Re, Im}((x + i y)^m)
+    (Condon-Shortley phase) and N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
+    Order within a band: m = -l..l, sin terms for m < 0."""
+    x, y, z = d[:, 0], d[:, 1], d[:, 2]
+    out = []
+    for l in range(deg + 1):
+        band = [None] * (2 * l + 1)
+        re, im = torch.ones_like(x), torch.zeros_like(x)    # (x + i y)^0
+        for m in range(0, l + 1):
+            if m > 0:
+                re, im = re * x - im * y, re * y + im * x
+            coeffs = _legendre_derivative_coeffs(l, m)
+            poly = torch.zeros_like(z)
+            for k in reversed(range(len(coeffs))):
+                poly = poly * z + float(coeffs[k])
+            nlm = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - m) / math.factorial(l + m))
+            if m == 0:
+                band[l] = nlm * poly
+            else:
+                s = ((-1) ** m) * math.sqrt(2.0) * nlm
+                band[l + m] = s * poly * re
+                band[l - m] = s * poly * im
+        out.extend(band)
+    return torch.stack(out, 1)
+
+
+# ----------------------------------------------------------- per Gaussian
+def quat_to_rotmat(q: torch.Tensor) -> torch.Tensor:
+    """Unit-quaternion rotation matrix, q = (w, x, y, z) normalised first."""
+    q = q / torch.linalg.norm(q, dim=1, keepdim=True)
+    w, x, y, z = q.unbind(1)
+    return torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], 1),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], 1),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1),
+    ], 1)
+
+
+def skew_to_2d(g: torch.Tensor, sigma3: torch.Tensor, A: torch.Tensor, Q: torch.Tensor) -> torch.Tensor:
+    """2D skew of the image of a 3D skew-normal under the affine map A with
+    blur sI (Q = (A Sigma A^T + sI)^-1):  Q v / sqrt(1 + g^T Sigma g - v^T Q v),
+    v = A Sigma g.  g [N,3], sigma3 [N,3,3], A [N,2,3], Q [N,2,2] -> [N,2]."""
+    sg = torch.einsum("nij,nj->ni", sigma3, g)
+    v = torch.einsum("nij,nj->ni", A, sg)
+    qv = torch.einsum("nij,nj->ni", Q, v)
+    kappa = (g * sg).sum(1)
+    m = (v * qv).sum(1)
+    return qv / torch.sqrt(1.0 + kappa - m)[:, None]
+
+
+@dataclass
+class Projected:
+    mu2d: torch.Tensor      # [N,2] pixels
+    conic: torch.Tensor     # [N,3] (a, b, c) of (Sigma' + sI)^-1
+    rho: torch.Tensor       # [N]   sqrt(det Sigma' / det(Sigma' + sI)) (or 1)
+    o1: torch.Tensor        # [N]
+    o2: torch.Tensor        # [N]
+    beta2d: torch.Tensor    # [N,2]
+    w2d: torch.Tensor | None  # [N,2] enhanced-opacity direction in 2D
+    rgb: torch.Tensor       # [N,3]
+    depth: torch.Tensor     # [N] camera-space z
+    valid: torch.Tensor     # [N] bool (not culled)
+
+
+def to_tensors(scene, requires_grad=False) -> dict:
+    """Scene arrays (float32 SoA) -> float64 [N, ...] leaf tensors."""
+    def t(a, shape_fn):
+        if a is None:
+            return None
+        x = torch.from_numpy(np.ascontiguousarray(shape_fn(np.asarray(a, np.float64))))
+        return x.requires_grad_(requires_grad)
+    return {
+        "mean": t(scene.mean, lambda a: a.T),
+        "log_scale": t(scene.log_scale, lambda a: a.T),
+        "quat": t(scene.quat, lambda a: a.T),
+        "skew": t(scene.skew, lambda a: a.T),
+        "opa_logit": t(scene.opa_logit, lambda a: a),
+        "opa2_logit": t(scene.opa2_logit, lambda a: a),
+        "opa_dir": t(scene.opa_dir, lambda a: a.T),
+        "sh": t(scene.sh, lambda a: a.transpose(2, 0, 1)),   # [N, K, 3]
+    }
+
+
+def project(P: dict, sh_degree: int, cam: Camera, opt: Options = Options()) -> Projected:
+    """Per-Gaussian projection (Sec. "Preliminary of 3D Gaussian Splatting";
+    appendix "Forward Pass"; 2D skew and enhanced-opacity readings above)."""
+    mean = P["mean"]
+    n = mean.shape[0]
+    # Sigma = R S S^T R^T
+    s = torch.exp(P["log_scale"])
+    R = quat_to_rotmat(P["quat"])
+    M = R * s[:, None, :]
+    sigma3 = M @ M.transpose(1, 2)
+    # world -> camera (OpenCV)
+    Wr = torch.from_numpy(cam.w2c[:3, :3].copy())
+    tv = torch.from_numpy(cam.w2c[:3, 3].copy())
+    t = mean @ Wr.T + tv
+    tx, ty, tz = t.unbind(1)
+    valid = tz > cam.near
+    fx, fy, cx, cy = cam.K[0, 0], cam.K[1, 1], cam.K[0, 2], cam.K[1, 2]
+    tzs = torch.where(valid, tz, torch.ones_like(tz))      # culled rows: harmless values
+    limx = opt.guard * (cam.W / (2.0 * fx))
+    limy = opt.guard * (cam.H / (2.0 * fy))
+    txc = torch.clamp(tx / tzs, -limx, limx) * tzs
+    tyc = torch.clamp(ty / tzs, -limy, limy) * tzs
+    zero = torch.zeros_like(tzs)
+    J = torch.stack([
+        torch.stack([fx / tzs, zero, -fx * txc / (tzs * tzs)], 1),
+        torch.stack([zero, fy / tzs, -fy * tyc / (tzs * tzs)], 1),
+    ], 1)
+    A = J @ Wr
+    sig2 = A @ sigma3 @ A.transpose(1, 2)
+    eye = torch.eye(2, dtype=F64)
+    sigf = sig2 + opt.filter_s * eye
+    det2 = sig2[:, 0, 0] * sig2[:, 1, 1] - sig2[:, 0, 1] * sig2[:, 1, 0]
+    detf = sigf[:, 0, 0] * sigf[:, 1, 1] - sigf[:, 0, 1] * sigf[:, 1, 0]
+    valid = valid & (detf > 0)
+    detf_s = torch.where(valid, detf, torch.ones_like(detf))
+    Q = torch.linalg.inv(torch.where(valid[:, None, None], sigf, eye.expand(n, 2, 2)))
+    conic = torch.stack([Q[:, 0, 0], Q[:, 0, 1], Q[:, 1, 1]], 1)
+    if opt.compensate:
+        rho = torch.sqrt(torch.clamp(det2, min=0.0) / detf_s)
+    else:
+        rho = torch.ones_like(detf_s)
+    mu2d = torch.stack([fx * tx / tzs + cx, fy * ty / tzs + cy], 1)
+    o1 = torch.sigmoid(P["opa_logit"])
+    o2 = torch.sigmoid(P["opa2_logit"]) if P.get("opa2_logit") is not None else o1
+    if P.get("skew") is not None and not opt.symmetric:
+        beta2d = skew_to_2d(P["skew"], sigma3, A, Q)
+    else:
+        beta2d = torch.zeros((n, 2), dtype=F64)
+    w2d = None
+    if P.get("opa2_logit") is not None:
+        g = P["opa_dir"] if P.get("opa_dir") is not None else torch.zeros((n, 3), dtype=F64)
+        if P.get("skew") is not None:
+            g = g + P["skew"]
+        w2d = skew_to_2d(g, sigma3, A, Q)
+    # view-dependent colour from SH
+    campos = torch.from_numpy(cam.position.copy())
+    dvec = mean - campos
+    dirs = dvec / torch.linalg.norm(dvec, dim=1, keepdim=True)
+    Y = sh_basis(sh_degree, dirs)                           # [N, K]
+    rgb = torch.clamp((Y[:, :, None] * P["sh"]).sum(1) + 0.5, min=0.0)
+    return Projected(mu2d, conic, rho, o1, o2, beta2d, w2d, rgb, tz, valid)
+
+
+# ------------------------------------------------------------ per pixel
+def pixel_centres(cam: Camera, pixels: np.ndarray | None) -> tuple[np.ndarray, torch.Tensor]:
+    if pixels is None:
+        pixels = np.arange(cam.W * cam.H, dtype=np.int64)
+    px = (pixels % cam.W).astype(np.float64) + 0.5
+    py = (pixels // cam.W).astype(np.float64) + 0.5
+    return pixels, torch.from_numpy(np.stack([px, py], 1))
+
+
+def alpha_tilde(pc: torch.Tensor, pr: Projected, idx: torch.Tensor, opt: Options):
+    """Unclamped 2D opacity of Gaussians ``idx`` at pixel centres pc [P,2]:
+    alpha~ = rho o(delta) G'(delta) (1 + erf(beta . delta / sqrt 2)), with
+    G' = exp(-(a dx^2 + c dy^2)/2 - b dx dy) (Alg. 1).  Returns [P, len(idx)]."""
+    mu = pr.mu2d[idx]
+    dx = pc[:, None, 0] - mu[None, :, 0]
+    dy = pc[:, None, 1] - mu[None, :, 1]
+    a, b, c = pr.conic[idx].unbind(1)
+    g = torch.exp(-0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy)
+    bx, by = pr.beta2d[idx].unbind(1)
+    if opt.symmetric:
+        skew = torch.ones_like(g)
+    else:
+        skew = 1.0 + torch.erf((bx * dx + by * dy) / SQRT2)
+    if pr.w2d is not None:
+        wx, wy = pr.w2d[idx].unbind(1)
+        o = 0.5 * ((pr.o1[idx] + pr.o2[idx]) + (pr.o1[idx] - pr.o2[idx]) * torch.erf((wx * dx + wy * dy) / SQRT2))
+    else:
+        o = pr.o1[idx]
+    return pr.rho[idx] * o * g * skew
+
+
+def depth_order(pr: Projected) -> torch.Tensor:
+    """Valid Gaussians sorted near to far by camera z, ties by index."""
+    idx = torch.nonzero(pr.valid).flatten()
+    key = pr.depth.detach()[idx].numpy()
+    order = np.argsort(key, kind="stable")
+    return idx[torch.from_numpy(order)]
+
+
+def inclusion(at: torch.Tensor, opt: Options) -> torch.Tensor:
+    """Which ordered pairs contribute (Alg. 1 loop with the thresholds of the
+    readings): alpha = min(0.99, alpha~) must reach 1/255, and the pixel stops
+    before the first Gaussian whose T_{k+1} = T_k (1 - alpha_k) would fall
+    below t_min.  at [P,K] in depth order -> bool [P,K]."""
+    alpha = torch.clamp(at, max=opt.alpha_max)
+    keep = alpha >= opt.alpha_min
+    a = torch.where(keep, alpha, torch.zeros_like(alpha))
+    t_after = torch.cumprod(1.0 - a, dim=1)
+    # T is non-increasing, so "not yet stopped" is a prefix of the list
+    live = t_after >= opt.t_min
+    return keep & live
+
+
+def composite(at: torch.Tensor, rgb: torch.Tensor, bg: torch.Tensor, include: torch.Tensor,
+              opt: Options):
+    """Front-to-back compositing (compositing equation; Alg. 1 loop):
+    C = sum_k c_k alpha_k T_k + T_final bg with T_k = prod_{j<k} (1 - alpha_j)
+    over the included pairs.  at [P,K] unclamped alpha in depth order,
+    rgb [K,3], include [P,K] fixed decisions.  Returns C [P,3], T_final [P]."""
+    alpha = torch.clamp(at, max=opt.alpha_max)
+    a = torch.where(include, alpha, torch.zeros_like(alpha))
+    t_after = torch.cumprod(1.0 - a, dim=1)
+    t_before = torch.cat([torch.ones_like(t_after[:, :1]), t_after[:, :-1]], 1)
+    C = (a * t_before) @ rgb
+    T_final = t_after[:, -1] if t_after.shape[1] else torch.ones(at.shape[0], dtype=F64)
+    return C + T_final[:, None] * bg[None, :], T_final
+
+
+@dataclass
+class RenderResult:
+    pixels: np.ndarray
+    color: np.ndarray        # [P,3]
+    T: np.ndarray            # [P]
+    last: np.ndarray         # [P] index of the last contributing Gaussian (-1 if none)
+    n_contrib: np.ndarray    # [P]
+    ambiguous: np.ndarray    # [P] bool: a decision within the margins below
+
+
+def _margins(at, order_depth, opt, rel):
+    """Per-pixel flag: some decision of the definition lies within a relative
+    margin of its threshold, where float32 evaluation may legitimately
+    decide the other way (alpha vs 1/255 or vs the 0.99 clamp, T(1-alpha) vs
+    the stop level, two reaching Gaussians at equal depth)."""
+    amb = ((at - opt.alpha_min).abs() <= rel["alpha"] * opt.alpha_min).any(1)
+    amb |= ((at - opt.alpha_max).abs() <= rel["alpha"] * opt.alpha_max).any(1)
+    alpha = torch.clamp(at, max=opt.alpha_max)
+    a = torch.where(alpha >= opt.alpha_min, alpha, torch.zeros_like(alpha))
+    ta = torch.cumprod(1.0 - a, 1)
+    stopped = ta < opt.t_min
+    upto = torch.cumsum(stopped.to(torch.int64), 1) <= 1     # up to the stop point
+    amb |= (((ta - opt.t_min).abs() <= rel["T"] * opt.t_min) & (a > 0) & upto).any(1)
+    # depth ties: runs of consecutive ordered Gaussians with nearly equal z
+    z = order_depth
+    if z.numel() > 1:
+        tie = (z[1:] - z[:-1]).abs() <= rel["depth"] * z[1:].abs()
+        reach = (at >= opt.alpha_min * (1 - rel["alpha"])) & upto
+        for k in torch.nonzero(tie).flatten().tolist():
+            amb |= reach[:, k] & reach[:, k + 1]
+    return amb
+
+
+DEFAULT_MARGINS = {"alpha": 2e-4, "T": 2e-3, "depth": 1e-6}
+
+
+def render(scene, pose_or_cam, pixels: np.ndarray | None = None, opt: Options = Options(),
+           chunk_elems: int = 1 << 19, margins=DEFAULT_MARGINS) -> RenderResult:
+    """Brute-force FP64 render of ``pixels`` (row-major indices; all if None)."""
+    cam = pose_or_cam if isinstance(pose_or_cam, Camera) else camera_from_pose(pose_or_cam)
+    with torch.no_grad():
+        P = to_tensors(scene)
+        pr = project(P, scene.sh_degree, cam, opt)
+        order = depth_order(pr)
+        pixels, pc = pixel_centres(cam, pixels)
+        bg = torch.from_numpy(cam.bg.astype(np.float64))
+        rgb = pr.rgb[order]
+        od = pr.depth[order]
+        n_pix = pc.shape[0]
+        col = np.zeros((n_pix, 3)); Tf = np.ones(n_pix)
+        last = np.full(n_pix, -1, np.int64); ncon = np.zeros(n_pix, np.int64)
+        amb = np.zeros(n_pix, bool)
+        step = max(1, chunk_elems // max(1, order.numel()))
+        for s in range(0, n_pix, step):
+            pcs = pc[s:s + step]
+            at = alpha_tilde(pcs, pr, order, opt)
+            inc = inclusion(at, opt)
+            C, T = composite(at, rgb, bg, inc, opt)
+            col[s:s + step] = C.numpy(); Tf[s:s + step] = T.numpy()
+            cnt = inc.sum(1)
+            ncon[s:s + step] = cnt.numpy()
+            k = inc.shape[1]
+            lastpos = torch.where(inc, torch.arange(k).expand_as(inc), torch.full_like(inc, -1, dtype=torch.int64)).max(1).values if k else torch.full((pcs.shape[0],), -1)
+            last[s:s + step] = np.where(lastpos.numpy() >= 0, order.numpy()[np.maximum(lastpos.numpy(), 0)], -1)
+            amb[s:s + step] = _margins(at, od, opt, margins).numpy()
+    return RenderResult(pixels, col, Tf, last, ncon, amb)
+
+
+def project_numpy(scene, pose_or_cam, opt: Options = Options()) -> dict:
+    """Per-Gaussian projected quantities as float64 numpy arrays."""
+    cam = pose_or_cam if isinstance(pose_or_cam, Camera) else camera_from_pose(pose_or_cam)
+    with torch.no_grad():
+        pr = project(to_tensors(scene), scene.sh_degree, cam, opt)
+    out = {k: (None if v is None else v.numpy()) for k, v in pr.__dict__.items()}
+    return out
+
+
+def render_grad(scene, pose_or_cam, dL_dC: np.ndarray, pixels: np.ndarray | None = None,
+                opt: Options = Options(), chunk_elems: int = 1 << 19) -> dict:
+    """Gradient of L = sum_p dL_dC[p] . C(p) w.r.t. every Gaussian parameter,
+    by reverse-mode differentiation of the FP64 forward definition.  The set
+    of included pairs and the stopping point are held fixed (the function is
+    piecewise smooth); clamped alpha and clamped colour channels have zero
+    derivative.  Returns float64 numpy arrays in the scene's SoA shapes."""
+    cam = pose_or_cam if isinstance(pose_or_cam, Camera) else camera_from_pose(pose_or_cam)
+    P = to_tensors(scene, requires_grad=True)
+    pr = project(P, scene.sh_degree, cam, opt)
+    order = depth_order(pr)
+    pixels, pc = pixel_centres(cam, pixels)
+    g = torch.from_numpy(np.asarray(dL_dC, np.float64).reshape(-1, 3))
+    bg = torch.from_numpy(cam.bg.astype(np.float64))
+    n_pix = pc.shape[0]
+    step = max(1, chunk_elems // max(1, order.numel()))
+    total = torch.zeros((), dtype=F64)
+    for s in range(0, n_pix, step):
+        pcs = pc[s:s + step]
+        with torch.no_grad():     # decisions on the full ordered list
+            inc = inclusion(alpha_tilde(pcs, pr, order, opt), opt)
+            cols = torch.nonzero(inc.any(0)).flatten()
+        # pairs never included have no value and no derivative: keep only the
+        # Gaussians included at some pixel of the chunk, with the same decisions
+        sub = order[cols]
+        at = alpha_tilde(pcs, pr, sub, opt)
+        C, _ = composite(at, pr.rgb[sub], bg, inc[:, cols], opt)
+        total = total + (C * g[s:s + step]).sum()
+    leaves = {k: v for k, v in P.items() if v is not None}
+    grads = torch.autograd.grad(total, list(leaves.values()), allow_unused=True)
+    out = {}
+    for (k, v), gr in zip(leaves.items(), grads):
+        gr = torch.zeros_like(v) if gr is None else gr
+        a = gr.detach().numpy()
+        out[k] = a.transpose(1, 2, 0) if k == "sh" else (a.T if a.ndim == 2 else a)
+    return out

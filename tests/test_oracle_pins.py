@@ -1,0 +1,444 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (tests/golden/), closed forms derived by hand, numerical
+integration of the paper's 3D kernel, textbook/library routines for the
+special cases, invariants of compositing, and central finite differences of
+the forward definition.  No GPU is needed.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.special
+import scipy.stats
+import torch
+
+import sgs_synth as S
+from oracle import sgs_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.split("#")[0].strip()
+        if line:
+            rows.append([float(v) for v in line.split()])
+    return np.array(rows)
+
+
+# ------------------------------------------------------------------ erf / Phi
+def test_erf_matches_paper_taylor_series():
+    """Appendix "Forward Pass": erf(z) = 2/sqrt(pi) sum_n (-1)^n z^(2n+1) /
+    (n! (2n+1)).  The printed leading coefficients pin the general term, the
+    series pins the erf the oracle evaluates."""
+    gold = _golden("erf_taylor.txt")
+    for n, (power, num, den) in enumerate(gold):
+        assert power == 2 * n + 1
+        assert num / den == pytest.approx((-1) ** n / (math.factorial(n) * (2 * n + 1)), rel=0, abs=1e-15)
+    z = torch.linspace(-2.0, 2.0, 81, dtype=torch.float64)
+    series = sum(((-1) ** n) * z ** (2 * n + 1) / (float(math.factorial(n)) * (2 * n + 1)) for n in range(45))
+    series = series * 2.0 / math.sqrt(math.pi)
+    assert torch.max(torch.abs(series - torch.erf(z))).item() < 1e-13
+
+
+def test_phi_zero_is_half_and_erf_derivative():
+    """Sec. "3D Skew Gaussian Kernel": Phi(0) = 1/2 with
+    Phi(z) = (1 + erf(z/sqrt 2))/2; appendix: d erf/dz = 2/sqrt(pi) e^{-z^2}."""
+    z0 = torch.zeros(1, dtype=torch.float64)
+    assert (0.5 * (1 + torch.erf(z0 / math.sqrt(2)))).item() == 0.5
+    z = torch.linspace(-3, 3, 61, dtype=torch.float64)
+    h = 1e-6
+    fd = (torch.erf(z + h) - torch.erf(z - h)) / (2 * h)
+    assert torch.max(torch.abs(fd - 2 / math.sqrt(math.pi) * torch.exp(-z * z))).item() < 1e-9
+
+
+# ------------------------------------------------------------------ camera
+def test_coord_engine_t_align_and_intrinsics():
+    """T_align = diag(1,-1,-1,1) (printed), an involution; K from (W,H,FoV)."""
+    gold = _golden("t_align.txt")
+    np.testing.assert_array_equal(O.T_ALIGN, gold)
+    np.testing.assert_array_equal(O.T_ALIGN @ O.T_ALIGN, np.eye(4))
+    K = O.intrinsics(1280, 720, 60.0)
+    assert K[0, 0] == pytest.approx(1280 / (2 * math.tan(math.radians(30))), rel=1e-15)
+    assert K[1, 1] == K[0, 0]
+    assert (K[0, 2], K[1, 2]) == (640.0, 360.0)
+    K2 = O.intrinsics(1280, 720, 60.0, fovy_deg=40.0)
+    assert K2[1, 1] == pytest.approx(720 / (2 * math.tan(math.radians(20))), rel=1e-15)
+
+
+def test_coord_engine_axis_conventions():
+    """OpenGL (right, up, back) pose -> OpenCV (right, down, forward):
+    the look-at target lands on the principal point, the frontend's right is
+    +x in the image and its up is -y (Sec. "Camera Trajectories and Format
+    Standardization")."""
+    eye = np.array([3.0, -5.0, 4.0])
+    pose = S.Pose(S.look_at_gl(eye, (0.5, 0.2, -0.1)), 640, 480)
+    cam = O.camera_from_pose(pose)
+    K = cam.K
+
+    def proj(x):
+        t = cam.w2c[:3, :3] @ x + cam.w2c[:3, 3]
+        return np.array([K[0, 0] * t[0] / t[2] + K[0, 2], K[1, 1] * t[1] / t[2] + K[1, 2]]), t[2]
+
+    p, z = proj(np.array([0.5, 0.2, -0.1]))
+    np.testing.assert_allclose(p, [320, 240], atol=1e-9)
+    assert z == pytest.approx(np.linalg.norm(eye - [0.5, 0.2, -0.1]), rel=1e-12)
+    right, up = pose.c2w_gl[:3, 0], pose.c2w_gl[:3, 1]
+    pr, _ = proj(np.array([0.5, 0.2, -0.1]) + 0.1 * right)
+    pu, _ = proj(np.array([0.5, 0.2, -0.1]) + 0.1 * up)
+    assert pr[0] > 320 and abs(pr[1] - 240) < 1e-9
+    assert pu[1] < 240 and abs(pu[0] - 320) < 1e-9
+    np.testing.assert_allclose(cam.position, eye, atol=1e-12)
+
+
+# ------------------------------------------------------------------ SH
+def test_sh_orthonormal_by_quadrature():
+    """Real SH are orthonormal on the sphere (Gauss-Legendre x uniform phi)."""
+    nt, nphi = 24, 48
+    xg, wg = np.polynomial.legendre.leggauss(nt)
+    phi = (np.arange(nphi) + 0.5) * 2 * np.pi / nphi
+    ct, ph = np.meshgrid(xg, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    d = torch.from_numpy(np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3))
+    Y = O.sh_basis(3, d).numpy()
+    w = (wg[:, None] * np.full(nphi, 2 * np.pi / nphi)[None, :]).reshape(-1)
+    G = (Y * w[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_matches_library_associated_legendre():
+    """Same basis built from scipy's associated Legendre functions (with the
+    Condon-Shortley phase) and cos/sin of the azimuth; Y00 = 1/(2 sqrt pi)."""
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=(50, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    Y = O.sh_basis(3, torch.from_numpy(v)).numpy()
+    th = np.arccos(v[:, 2])
+    ph = np.arctan2(v[:, 1], v[:, 0])
+    col = 0
+    for l in range(4):
+        for m in range(-l, l + 1):
+            am = abs(m)
+            N = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - am) / math.factorial(l + am))
+            P = scipy.special.lpmv(am, l, np.cos(th))
+            if m == 0:
+                ref = N * P
+            elif m > 0:
+                ref = math.sqrt(2) * N * P * np.cos(am * ph)
+            else:
+                ref = math.sqrt(2) * N * P * np.sin(am * ph)
+            np.testing.assert_allclose(Y[:, col], ref, atol=1e-12)
+            col += 1
+    np.testing.assert_allclose(Y[:, 0], 1 / (2 * math.sqrt(math.pi)), rtol=1e-15)
+
+
+# ------------------------------------------------------------------ kernel
+def _identity_pose(W=64, H=64, fov=60.0):
+    # M_gl = T_align gives M_cv = I: camera at the origin looking down +z
+    return S.Pose(np.diag([1.0, -1.0, -1.0, 1.0]), W, H, fov, 0.2)
+
+
+def _one_gaussian(mean, sigma, skew, opa_logit=2.0, dc=(0.3, -0.1, 0.2)):
+    q = np.array([[1.0], [0.0], [0.0], [0.0]], np.float32)
+    return S.Scene(np.array(mean, np.float32).reshape(3, 1),
+                   np.full((3, 1), math.log(sigma), np.float32), q,
+                   np.array(skew, np.float32).reshape(3, 1),
+                   np.array([opa_logit], np.float32),
+                   np.array(dc, np.float32).reshape(1, 3, 1), 0)
+
+
+def test_single_gaussian_closed_form():
+    """Isotropic Gaussian at (0,0,Z) in front of the camera, no filter, skew
+    (bx, by, 0): by hand, Sigma' = (f sigma/Z)^2 I and the 2D skew is
+    (Z/f)(bx, by), so C(p) = rgb min(0.99, o exp(-|d|^2 / (2 sigma_p^2))
+    (1 + erf((Z/f)(bx dx + by dy)/sqrt 2))), rgb = 0.5 + DC/(2 sqrt pi)."""
+    Z, sig, bx, by = 6.0, 0.05, 7.0, -4.0
+    pose = _identity_pose()
+    sc = _one_gaussian([0.0, 0.0, Z], sig, [bx, by, 0.0])
+    opt = O.Options(filter_s=0.0, compensate=False)
+    r = O.render(sc, pose, opt=opt)
+    f = 64 / (2 * math.tan(math.radians(30)))
+    Zf, bxf, byf = (float(np.float32(v)) for v in (Z, bx, by))
+    sf = math.exp(float(np.float32(math.log(sig))))
+    sp = f * sf / Zf
+    o = 1 / (1 + math.exp(-2.0))
+    rgb = 0.5 + np.array([0.3, -0.1, 0.2], np.float32).astype(np.float64) / (2 * math.sqrt(math.pi))
+    px = (np.arange(64 * 64) % 64) + 0.5 - 32
+    py = (np.arange(64 * 64) // 64) + 0.5 - 32
+    a = o * np.exp(-(px ** 2 + py ** 2) / (2 * sp ** 2)) * (1 + scipy.special.erf((Zf / f) * (bxf * px + byf * py) / math.sqrt(2)))
+    a = np.minimum(a, 0.99)
+    a = np.where(a >= 1 / 255, a, 0.0)
+    np.testing.assert_allclose(r.color, a[:, None] * rgb[None, :], atol=1e-12)
+    np.testing.assert_allclose(r.T, 1 - a, atol=1e-12)
+    pr = O.project_numpy(sc, pose, opt)
+    np.testing.assert_allclose(pr["beta2d"][0], [Zf / f * bxf, Zf / f * byf], rtol=1e-12)
+
+
+def test_skew_along_view_ray_projects_to_zero():
+    """Isotropic Gaussian on the optical axis with skew parallel to the ray:
+    the marginal is symmetric, so the image equals the zero-skew image."""
+    pose = _identity_pose()
+    a = O.render(_one_gaussian([0, 0, 5.0], 0.08, [0, 0, 9.0]), pose)
+    b = O.render(_one_gaussian([0, 0, 5.0], 0.08, [0, 0, 0.0]), pose)
+    np.testing.assert_allclose(a.color, b.color, atol=1e-13)
+
+
+def test_zero_skew_reduces_exactly_to_3dgs():
+    """beta = 0 gives Phi(0) = 1/2, S = G (Sec. "3D Skew Gaussian Kernel"):
+    the image equals the textbook 3DGS image, which drops the skew factor
+    entirely, bit for bit."""
+    sc, pose = S.tiny_config()
+    sc = sc.subset(np.arange(400))
+    sc.skew[:] = 0.0
+    a = O.render(sc, pose)
+    b = O.render(sc, pose, opt=O.Options(symmetric=True))
+    np.testing.assert_array_equal(a.color, b.color)
+    np.testing.assert_array_equal(a.T, b.T)
+
+
+def test_gaussian_falloff_matches_library_normal_pdf():
+    """G'(delta) = exp(-delta^T (Sigma'+sI)^-1 delta / 2) equals the bivariate
+    normal density with covariance Sigma'+sI times 2 pi sqrt(det)."""
+    sc, pose = S.tiny_config()
+    sc = sc.subset(np.arange(5))
+    cam = O.camera_from_pose(pose)
+    with torch.no_grad():
+        pr = O.project(O.to_tensors(sc), 0, cam, O.Options(symmetric=True))
+    pix, pc = O.pixel_centres(cam, np.arange(0, 128 * 128, 97))
+    idx = torch.arange(5)
+    at = O.alpha_tilde(pc, pr, idx, O.Options(symmetric=True)).numpy()
+    for i in range(5):
+        a, b, c = pr.conic[i].numpy()
+        cov = np.linalg.inv(np.array([[a, b], [b, c]]))
+        g = scipy.stats.multivariate_normal(pr.mu2d[i].numpy(), cov).pdf(pc.numpy()) * 2 * math.pi * math.sqrt(np.linalg.det(cov))
+        d = (pr.rho[i] * pr.o1[i]).item()
+        np.testing.assert_allclose(at[:, i], d * g, rtol=1e-10, atol=1e-300)
+
+
+def _rand_spd(rng, n, scale=1.0):
+    B = rng.normal(size=(n, n)) * scale
+    return B @ B.T + 0.3 * np.eye(n)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_skew_projection_equals_line_integral_of_3d_kernel(seed):
+    """The 2D skew used by the rasterizer is pinned to the paper's 3D kernel
+    S(x) = 2 G(x) Phi(beta^T x): integrating the normalised 3D density along
+    the null direction n of the affine map A gives, for every image point y,
+    |det[A; n^T]|^-1 times the integral, which must equal
+    2 N(y; A Sigma A^T) Phi(beta_2D . y) (no blur)."""
+    rng = np.random.default_rng(seed)
+    Sig = _rand_spd(rng, 3, 0.8)
+    beta = rng.normal(size=3) * 1.5
+    A = rng.normal(size=(2, 3))
+    n = np.cross(A[0], A[1]); n /= np.linalg.norm(n)
+    Sig2 = A @ Sig @ A.T
+    Q = np.linalg.inv(Sig2)
+    b2 = O.skew_to_2d(torch.from_numpy(beta[None]), torch.from_numpy(Sig[None]),
+                      torch.from_numpy(A[None]), torch.from_numpy(Q[None]))[0].numpy()
+    mvn3 = scipy.stats.multivariate_normal(np.zeros(3), Sig)
+    mvn2 = scipy.stats.multivariate_normal(np.zeros(2), Sig2)
+    jac = abs(np.linalg.det(np.vstack([A, n])))
+    pinv = A.T @ np.linalg.inv(A @ A.T)
+    for y in rng.normal(size=(6, 2)) * 1.2:
+        x0 = pinv @ y
+        f = lambda t: 2 * mvn3.pdf(x0 + t * n) * scipy.stats.norm.cdf(beta @ (x0 + t * n))
+        num, _ = scipy.integrate.quad(f, -np.inf, np.inf, epsabs=0, epsrel=1e-12, limit=200)
+        closed = 2 * mvn2.pdf(y) * scipy.stats.norm.cdf(b2 @ y)
+        assert num / jac == pytest.approx(closed, rel=1e-8)
+
+
+def test_skew_projection_with_blur_equals_convolution():
+    """With the low-pass filter the 2D density is the (no-blur) marginal
+    convolved with N(0, sI); 2D Gauss-Hermite quadrature of that convolution
+    must equal 2 N(y; A Sigma A^T + sI) Phi(beta_2D . y) with beta_2D from
+    Q = (A Sigma A^T + sI)^-1."""
+    rng = np.random.default_rng(7)
+    Sig = _rand_spd(rng, 3, 0.9)
+    beta = rng.normal(size=3) * 2.0
+    A = rng.normal(size=(2, 3))
+    s = 0.3
+    Sig2 = A @ Sig @ A.T
+    Q0 = np.linalg.inv(Sig2)
+    Qf = np.linalg.inv(Sig2 + s * np.eye(2))
+    tb = lambda Q: O.skew_to_2d(torch.from_numpy(beta[None]), torch.from_numpy(Sig[None]),
+                                torch.from_numpy(A[None]), torch.from_numpy(Q[None]))[0].numpy()
+    b0, bf = tb(Q0), tb(Qf)
+    h, w = np.polynomial.hermite.hermgauss(60)
+    E = np.sqrt(2 * s) * np.stack(np.meshgrid(h, h, indexing="ij"), -1).reshape(-1, 2)
+    W = (w[:, None] * w[None, :]).reshape(-1) / math.pi
+    mvn0 = scipy.stats.multivariate_normal(np.zeros(2), Sig2)
+    mvnf = scipy.stats.multivariate_normal(np.zeros(2), Sig2 + s * np.eye(2))
+    for y in rng.normal(size=(5, 2)):
+        pts = y[None, :] - E
+        conv = np.sum(W * 2 * mvn0.pdf(pts) * scipy.stats.norm.cdf(pts @ b0))
+        closed = 2 * mvnf.pdf(y) * scipy.stats.norm.cdf(bf @ y)
+        assert conv == pytest.approx(closed, rel=1e-9)
+
+
+def test_dalpha_dbeta_matches_paper_closed_form():
+    """Eq. for dS/dbeta (Sec. "3D Skew Gaussian Kernel"), in 2D with the
+    opacity factor: d alpha~/d beta = d G'(x) (2/sqrt pi) e^{-(beta.delta/
+    sqrt2)^2} delta / sqrt 2."""
+    sc, pose = S.tiny_config()
+    sc = sc.subset(np.arange(40))
+    cam = O.camera_from_pose(pose)
+    with torch.no_grad():
+        pr = O.project(O.to_tensors(sc), 0, cam)
+    beta = pr.beta2d.clone().requires_grad_(True)
+    pr.beta2d = beta
+    pix, pc = O.pixel_centres(cam, np.arange(0, 128 * 128, 211))
+    idx = torch.arange(40)
+    at = O.alpha_tilde(pc, pr, idx, O.Options())
+    gx, = torch.autograd.grad(at.sum(), beta)
+    with torch.no_grad():
+        dx = pc[:, None, 0] - pr.mu2d[None, :, 0]
+        dy = pc[:, None, 1] - pr.mu2d[None, :, 1]
+        a, b, c = pr.conic.unbind(1)
+        G = torch.exp(-0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy)
+        z = (beta[:, 0] * dx + beta[:, 1] * dy) / math.sqrt(2)
+        common = (pr.rho * pr.o1) * G * (2 / math.sqrt(math.pi)) * torch.exp(-z * z) / math.sqrt(2)
+        ref = torch.stack([(common * dx).sum(0), (common * dy).sum(0)], 1)
+    np.testing.assert_allclose(gx.numpy(), ref.numpy(), rtol=1e-12, atol=1e-300)
+
+
+# ------------------------------------------------------------------ compositing
+def test_compositing_hand_expanded_and_rules():
+    """Compositing equation expanded by hand for three Gaussians, plus the
+    skip (alpha < 1/255), clamp (0.99) and stop (T < 1e-4) rules."""
+    opt = O.Options()
+    rgb = torch.tensor([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.2, 0.3, 0.4]], dtype=torch.float64)
+    bg = torch.tensor([0.1, 0.2, 0.3], dtype=torch.float64)
+    at = torch.tensor([[0.3, 0.5, 0.25]], dtype=torch.float64)
+    C, T = O.composite(at, rgb, bg, O.inclusion(at, opt), opt)
+    a1, a2, a3 = 0.3, 0.5, 0.25
+    ref = (a1 * rgb[0] + a2 * (1 - a1) * rgb[1] + a3 * (1 - a1) * (1 - a2) * rgb[2]
+           + (1 - a1) * (1 - a2) * (1 - a3) * bg)
+    np.testing.assert_allclose(C[0].numpy(), ref.numpy(), atol=1e-15)
+    at = torch.tensor([[0.003, 1.7, 0.5]], dtype=torch.float64)  # skip, clamp, stop
+    inc = O.inclusion(at, opt)
+    assert inc.tolist() == [[False, True, True]]
+    C, T = O.composite(at, rgb, bg, inc, opt)
+    np.testing.assert_allclose(C[0].numpy(), (0.99 * rgb[1] + 0.5 * 0.01 * rgb[2] + 0.005 * bg).numpy(), atol=1e-15)
+    at = torch.tensor([[0.99, 0.99, 0.6, 0.9]], dtype=torch.float64)
+    inc = O.inclusion(at, opt)   # T: 1 -> .01 -> 1e-4 (kept, not below) -> stop
+    assert inc.tolist() == [[True, True, False, False]]
+
+
+def test_compositing_partition_of_unity_and_monotone_T():
+    """sum_k alpha_k T_k + T_final = 1, 0 <= T <= 1 and T non-increasing."""
+    sc, pose = S.tiny_config()
+    sc.sh[:] = 0.0
+    sc.sh[0] = 0.5 * 2 * math.sqrt(math.pi)     # rgb = 1 exactly on all channels
+    r = O.render(sc, pose)
+    np.testing.assert_allclose(r.color[:, 0] + r.T, 1.0, atol=1e-12)
+    assert (r.T >= 0).all() and (r.T <= 1).all()
+    cam = O.camera_from_pose(pose)
+    with torch.no_grad():
+        pr = O.project(O.to_tensors(sc), 0, cam)
+        order = O.depth_order(pr)
+        _, pc = O.pixel_centres(cam, np.arange(0, 128 * 128, 53))
+        at = O.alpha_tilde(pc, pr, order, O.Options())
+        inc = O.inclusion(at, O.Options())
+        a = torch.where(inc, torch.clamp(at, max=0.99), torch.zeros_like(at))
+        T = torch.cumprod(1 - a, 1)
+    assert bool((T[:, 1:] <= T[:, :-1]).all())
+
+
+def test_equal_depth_ties_break_by_index():
+    """Two Gaussians at the same depth: the lower index is composited first."""
+    pose = _identity_pose()
+    sc = _one_gaussian([0, 0, 5.0], 0.1, [0, 0, 0])
+    sc2 = _one_gaussian([0, 0, 5.0], 0.1, [0, 0, 0], dc=(-1.0, 1.0, 0.0))
+    both = S.Scene(*(np.concatenate([getattr(sc, f), getattr(sc2, f)], -1) for f in
+                     ("mean", "log_scale", "quat", "skew", "opa_logit", "sh")), 0)
+    r = O.render(both, pose, pixels=np.array([32 * 64 + 32]))
+    assert r.last[0] == 1 and r.n_contrib[0] == 2
+    cam = O.camera_from_pose(pose)
+    pr = O.project_numpy(both, cam)
+    ca, cb, cc = pr["conic"][0]
+    dx = dy = 0.5                # pixel centre (32.5, 32.5), mean at (32, 32)
+    a = min(0.99, pr["rho"][0] * pr["o1"][0] * math.exp(-0.5 * (ca * dx * dx + cc * dy * dy) - cb * dx * dy))
+    ref = a * pr["rgb"][0] + a * (1 - a) * pr["rgb"][1]
+    np.testing.assert_allclose(r.color[0], ref, atol=1e-12)
+
+
+# ------------------------------------------------------------------ enhanced opacity
+def test_enhanced_opacity_reduces_to_scalar_when_equal():
+    """o(x) = ((a1+a2) + (a1-a2) erf(...))/2 equals a1 when a1 = a2."""
+    sc = S.blobs_scene(11, 300, 1, enhanced=True)
+    sc.opa2_logit[:] = sc.opa_logit
+    pose = S.tiny_config()[1]
+    a = O.render(sc, pose)
+    sc2 = S.Scene(sc.mean, sc.log_scale, sc.quat, sc.skew, sc.opa_logit, sc.sh, sc.sh_degree)
+    b = O.render(sc2, pose)
+    np.testing.assert_allclose(a.color, b.color, atol=1e-15)
+
+
+# ------------------------------------------------------------------ gradients
+def _param_list(sc):
+    names = ["mean", "log_scale", "quat", "skew", "opa_logit", "sh", "opa2_logit", "opa_dir"]
+    return [n for n in names if getattr(sc, n) is not None]
+
+
+def _fd_check(sc, pose, pix, g, n_coords, seed, h=1e-6, rtol=1e-6):
+    import copy
+    grads = O.render_grad(sc, pose, g, pix)
+    rng = np.random.default_rng(seed)
+    cam = O.camera_from_pose(pose)
+
+    def loss(s):
+        with torch.no_grad():
+            P = O.to_tensors(s)
+            pr = O.project(P, s.sh_degree, cam)
+            order = O.depth_order(pr)
+            _, pc = O.pixel_centres(cam, pix)
+            at = O.alpha_tilde(pc, pr, order, O.Options())
+            inc = O.inclusion(at, O.Options())
+            C, _ = O.composite(at, pr.rgb[order], torch.zeros(3, dtype=torch.float64), inc, O.Options())
+            return float((C.numpy() * g).sum()), (order.numpy().tobytes(), inc.numpy().tobytes(),
+                                                  (pr.rgb > 0).numpy().tobytes(), (at < 0.99).numpy().tobytes())
+    checked = 0
+    for _ in range(n_coords * 3):
+        if checked >= n_coords:
+            break
+        name = _param_list(sc)[rng.integers(0, len(_param_list(sc)))]
+        arr = getattr(sc, name)
+        flat = int(rng.integers(0, arr.size))
+        vals = []
+        for sgn in (1, -1):
+            s2 = copy.deepcopy(sc)
+            a64 = np.array(getattr(s2, name), dtype=np.float64, order="C")
+            a64.reshape(-1)[flat] += sgn * h
+            setattr(s2, name, a64)
+            vals.append(loss(s2))
+        if vals[0][1] != vals[1][1]:
+            continue   # a decision flips within +-h: the derivative is not defined there
+        fd = (vals[0][0] - vals[1][0]) / (2 * h)
+        an = grads[name].reshape(-1)[flat]
+        scale = max(1e-6, np.abs(grads[name]).max())
+        assert abs(fd - an) <= rtol * scale + 1e-6 * abs(an) + 1e-9, (name, flat, fd, an)
+        checked += 1
+    assert checked >= n_coords // 2
+
+
+def test_gradient_matches_central_differences_subscene():
+    """64-Gaussian subscene (blobs generator, SH3) on a 64x64 view: FP64
+    central differences (h = 1e-6) of L = sum dL/dC . C agree with the
+    oracle's reverse-mode gradient for every parameter kind."""
+    sc = S.blobs_scene(4, 64, 3)
+    pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 64, 64)
+    g = np.random.default_rng(1).normal(size=(64 * 64, 3))
+    _fd_check(sc, pose, None, g, n_coords=60, seed=5)
+
+
+def test_gradient_matches_central_differences_enhanced():
+    sc = S.blobs_scene(9, 24, 1, enhanced=True)
+    pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 48, 48)
+    g = np.random.default_rng(2).normal(size=(48 * 48, 3))
+    _fd_check(sc, pose, None, g, n_coords=40, seed=6)
