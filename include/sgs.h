@@ -1,0 +1,240 @@
+/*
+ * sgs.h -- C ABI of the MI355X (gfx950) rasterizer for 3D skew Gaussians.
+ *
+ * The library renders scenes of 3D skew Gaussians (paper: "3D Skew Gaussian
+ * Splatting", Sec. "3D Skew Gaussian Kernel" S(x) = 2 G(x) Phi(beta^T(x-mu)))
+ * with a tile-based pipeline, forward and backward:
+ *
+ *   sgs_preprocess  per (view, Gaussian): covariance, EWA projection, 2D skew,
+ *                   SH colour, skew-aware screen extent, tile count, and the
+ *                   prefix sum of tile counts (instance count on the device).
+ *   sgs_bin_sort    one (tile, depth) key per covered tile, stable LSD radix
+ *                   sort, per-tile ranges of the sorted list.
+ *   sgs_render_fwd  per-tile front-to-back compositing (Alg. 1).
+ *   sgs_render_bwd  reverse-order blend backward (Alg. 2) and the chain rule
+ *                   back to the 3D parameters (Sec. "3D Skew Gaussian
+ *                   Rasterization and Splatting", gradient of the loss w.r.t.
+ *                   beta; appendix "Backward Pass").
+ *
+ * Conventions (all calls):
+ *  - Every pointer named *_dev or documented as "device" is device memory on
+ *    the current HIP device; everything else is host memory.  Device arrays are
+ *    float32 structure-of-arrays unless stated: a field "[k][n]" stores
+ *    component j of element i at index j*n + i.
+ *  - The caller allocates and owns all memory, including scratch; the library
+ *    allocates nothing, keeps no global state and may be called concurrently
+ *    on distinct streams with distinct buffers.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Calls only enqueue
+ *    work and return; no call synchronises.  Kernel launch errors are reported
+ *    as SGS_EHIP by the call that launched them.
+ *  - Gradient outputs are accumulated (+=); the caller zeroes them.
+ *  - Degenerate Gaussians (behind the near plane, singular 2D covariance,
+ *    non-finite values, too faint to reach alpha_min anywhere) are culled
+ *    silently: zero tiles, no output, zero gradient.  Never an error.
+ */
+#ifndef SGS_H
+#define SGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SGS_OK = 0,
+  SGS_EINVAL = 1,      /* null required pointer, bad size or option        */
+  SGS_ECAPACITY = 2,   /* caller buffer smaller than the size helper asks  */
+  SGS_EHIP = 3,        /* HIP runtime / launch error                       */
+  SGS_EUNSUPPORTED = 4 /* valid but not implemented (e.g. tile shape)      */
+} sgs_status;
+
+/* Gaussian parameters, device pointers (Sec. "Preliminary of 3D Gaussian
+ * Splatting": mean, scale, rotation quaternion, opacity, SH colour; Sec. "3D
+ * Skew Gaussian Kernel": skew vector beta in R^3; Sec. "3D Skew Gaussian
+ * Rasterization and Splatting": enhanced opacity with two base opacities and
+ * a direction). */
+typedef struct {
+  int64_t n;               /* number of Gaussians N >= 0                    */
+  int32_t sh_degree;       /* 0..3, K = (sh_degree+1)^2 coefficients        */
+  int32_t _pad;
+  const float* mean;       /* [3][N] world position                         */
+  const float* log_scale;  /* [3][N] log of the per-axis scale              */
+  const float* quat;       /* [4][N] rotation (w,x,y,z), any non-zero norm  */
+  const float* skew;       /* [3][N] beta, or NULL: symmetric 3DGS path     */
+  const float* opa_logit;  /* [N]    logit of base opacity alpha_1          */
+  const float* opa2_logit; /* [N]    logit of alpha_2, or NULL (alpha_2 = alpha_1,
+                                     enhanced opacity off)                  */
+  const float* opa_dir;    /* [3][N] direction d of the enhanced opacity, or
+                                     NULL (d = 0); used only with opa2_logit */
+  const float* sh;         /* [K][3][N] SH coefficients                     */
+} sgs_params;
+
+/* Accumulated (+=) gradients, device pointers, same shapes as sgs_params.
+ * A pointer may be NULL when the matching parameter is NULL. */
+typedef struct {
+  float* mean;
+  float* log_scale;
+  float* quat;
+  float* skew;
+  float* opa_logit;
+  float* opa2_logit;
+  float* opa_dir;
+  float* sh;
+} sgs_params_grad;
+
+/* One pinhole view in the OpenCV convention (+x right, +y down, +z forward;
+ * Sec. "Camera Trajectories and Format Standardization").  Build it from a
+ * frontend (OpenGL/Blender) pose with sgs_camera_from_gl; lay a batch out
+ * with sgs_camera_layout.  The same array is passed to the library twice:
+ * in host memory (sizes, grids) and as an identical copy in device memory
+ * (read by the kernels). */
+typedef struct {
+  int32_t width, height;   /* pixels, > 0                                   */
+  float fx, fy, cx, cy;    /* intrinsics K                                  */
+  float w2c[12];           /* row-major 3x4 world-to-camera [R|t]           */
+  float campos[3];         /* camera centre in world coordinates            */
+  float near_z;            /* Gaussians with camera z <= near_z are culled  */
+  float bg[3];             /* background colour                             */
+  int32_t tiles_x, tiles_y;/* set by sgs_camera_layout                      */
+  int32_t tile_base;       /* first global tile id of this view             */
+  int64_t pix_base;        /* first pixel of this view in the output planes */
+} sgs_camera;
+
+/* Pipeline options; sgs_default_options fills the values in brackets. */
+typedef struct {
+  int32_t tile_w, tile_h;  /* [16, 16]; also 16x8 and 8x8                  */
+  float filter_s;          /* [0.3] low-pass filter added to Sigma' (px^2)  */
+  int32_t compensate;      /* [1] opacity compensation sqrt(det S'/det(S'+sI)) */
+  float guard;             /* [1.3] Jacobian clamp of x/z, y/z in tan(fov/2) */
+  float alpha_min;         /* [1/255] pairs below are skipped               */
+  float alpha_max;         /* [0.99] alpha clamp                            */
+  float t_min;             /* [1e-4] a pixel stops before T drops below     */
+  int32_t sort_mode;       /* [1] 0: 64-bit (tile<<32 | depth) keys, one LSD
+                              sort; 1: stable depth presort of the records,
+                              duplicate in depth order, LSD sort of 32-bit
+                              tile keys.  Both give the identical order.    */
+  int32_t blend_batch;     /* [256] records staged in LDS per batch: 64, 128, 256 */
+} sgs_options;
+
+/* Projected per-record data written by sgs_preprocess, record m = v*N + i for
+ * view v and Gaussian i (M = n_views * N records).  Device pointers; sizes
+ * from sgs_geom_floats.  `rec` holds R float4 planes of M entries:
+ *   plane 0: (mu_x, mu_y, a, b)   2D mean in pixels, conic (Sigma'+sI)^-1 = [[a,b],[b,c]]
+ *   plane 1: (c, beta_x, beta_y, d)  2D skew; d = rho*alpha_1 (rho with enhanced opacity)
+ *   plane 2: (r, g, b, log_thr)   colour; log_thr: below this exponent a pair is skipped
+ *   plane 3: (alpha_1, alpha_2, w_x, w_y)  only with enhanced opacity (R = 4)
+ */
+typedef struct {
+  float* rec;              /* [R][M][4]                                     */
+  float* depth;            /* [M] camera-space z (the sort key)             */
+  uint32_t* rect;          /* [M][2] tile rect: (x0 | y0<<16, x1 | y1<<16), half-open */
+  uint32_t* tiles;         /* [M] number of tiles covered (0 = culled)      */
+  uint32_t* block_off;     /* [sgs_geom_block_entries(N, V)] exclusive prefix of the
+                              tile counts per block of 256 records of one view
+                              (view-major); the last entry is the total      */
+} sgs_geom;
+
+/* Accumulated (+=) gradient of the loss w.r.t. the projected records, same
+ * [R][M][4] layout as sgs_geom.rec (plane 2 .w unused).  Device pointer. */
+typedef struct {
+  float* rec;
+} sgs_geom_grad;
+
+/* ---------------------------------------------------------------- helpers */
+void sgs_default_options(sgs_options* opt);
+
+/* sizeof of the ABI structs, for bindings to check their mirrors:
+ * 0 sgs_params, 1 sgs_params_grad, 2 sgs_camera, 3 sgs_options, 4 sgs_geom,
+ * 5 sgs_geom_grad; 0 for any other value. */
+size_t sgs_struct_size(int32_t which);
+const char* sgs_status_string(sgs_status s);
+
+/* CoordEngine and intrinsic mapping (Alg. 3; Sec. "Decoupled Interactive
+ * Visual Analytics Engine"): M_cv = M_gl T_align, T_align = diag(1,-1,-1,1);
+ * w2c = M_cv^-1; K = [[W/(2tan(fovx/2)),0,W/2],[0,H/(2tan(fovy/2)),H/2]].
+ * c2w_gl: row-major 4x4 OpenGL camera-to-world (host).  fovy_rad <= 0 means
+ * square pixels (fy = fx).  Fills every field except the layout fields.
+ * EINVAL for non-finite input, W or H <= 0, fov outside (0, pi). */
+sgs_status sgs_camera_from_gl(const double c2w_gl[16], int32_t width, int32_t height,
+                              double fovx_rad, double fovy_rad, float near_z,
+                              const float bg[3], sgs_camera* out);
+
+/* Lays n_views cameras (host array) out in one global tile and pixel space:
+ * sets tiles_x, tiles_y, tile_base, pix_base; returns the totals. */
+sgs_status sgs_camera_layout(sgs_camera* cams, int32_t n_views, const sgs_options* opt,
+                             int64_t* total_tiles, int64_t* total_pixels);
+
+/* Float counts of the buffers of sgs_geom / sgs_geom_grad for M records. */
+int64_t sgs_geom_rec_floats(int64_t m, int32_t enhanced);
+int64_t sgs_geom_block_entries(int64_t n, int32_t n_views);
+
+/* Scratch bytes sgs_bin_sort needs for M records, an instance capacity and a
+ * number of tiles (same options). */
+size_t sgs_bin_sort_scratch_bytes(int64_t m, int64_t inst_capacity, int64_t total_tiles,
+                                  const sgs_options* opt);
+
+/* ------------------------------------------------------------------ calls */
+
+/* Projects every Gaussian into every view (see sgs_geom) and computes
+ * block_off (scan of the tile counts), so that *block_off[last] is the
+ * number of instances.  cams_host / cams_dev: the same n_views laid-out
+ * cameras.  EINVAL: null pointers, n < 0, sh_degree > 3, bad options. */
+sgs_status sgs_preprocess(const sgs_params* p, const sgs_camera* cams_host,
+                          const sgs_camera* cams_dev, int32_t n_views,
+                          const sgs_options* opt, const sgs_geom* g, void* stream);
+
+/* Writes, for each record with tiles > 0 and each tile of its rect in
+ * row-major order, one instance, sorts them stably by (global tile, depth)
+ * (ties keep record order) and extracts tile_ranges[t] = [start, end).
+ *  keys          [inst_capacity] u64 (tile<<32 | float bits of depth), sorted;
+ *                may be NULL (then not written) in sort_mode 1.
+ *  vals          [inst_capacity] u32 record index m, sorted.
+ *  tile_ranges   [total_tiles][2] u32.
+ *  n_inst_dev    [1] u32 device: receives the instance count.  Instances past
+ *                inst_capacity are dropped; the caller compares the count with
+ *                the capacity after the fact (graph-friendly, no host sync).
+ *  scratch       device, >= sgs_bin_sort_scratch_bytes(...).
+ * EINVAL / ECAPACITY for bad sizes. */
+sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_host,
+                        const sgs_camera* cams_dev, int32_t n_views,
+                        const sgs_options* opt, int64_t inst_capacity,
+                        uint64_t* keys, uint32_t* vals, uint32_t* tile_ranges,
+                        uint32_t* n_inst_dev, void* scratch, size_t scratch_bytes,
+                        void* stream);
+
+/* Alg. 1 per pixel: alpha = min(alpha_max, d G'(x) (1 + erf(beta.delta/sqrt2)))
+ * (times the enhanced-opacity factor), pairs below alpha_min skipped, stop
+ * before T falls below t_min; C += c alpha T.  vals / tile_ranges as written
+ * by sgs_bin_sort with the same inst_capacity (ranges are clamped to it).  Outputs (device, per view at
+ * its pix_base): out_rgb planes [3][P] (colour + T_final*bg), out_T [P]
+ * (final transmittance), out_last [P] (number of range entries up to and
+ * including the last contributor, 0 if none), out_count [P] (optional, NULL to
+ * skip: number of pairs composited into the pixel). */
+sgs_status sgs_render_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals,
+                          int64_t inst_capacity, const uint32_t* tile_ranges, const sgs_camera* cams_host,
+                          const sgs_camera* cams_dev, int32_t n_views, int32_t enhanced,
+                          const sgs_options* opt, float* out_rgb, float* out_T,
+                          uint32_t* out_last, uint32_t* out_count, int64_t total_pixels,
+                          void* stream);
+
+/* Alg. 2 and the chain rule.  Re-walks each pixel's list from its last
+ * contributor to the front, rebuilding T from out_T (nothing per pair is
+ * stored), accumulates the 2D record gradients g2d (reduced per tile in
+ * registers/LDS before one atomic add per record and tile), then chains them
+ * to the 3D parameters (grad, +=).  dL_drgb has the layout of out_rgb.
+ * g2d must be zeroed by the caller before the call. */
+sgs_status sgs_render_bwd(const sgs_params* p, const sgs_geom* g, int64_t m,
+                          const uint32_t* vals, int64_t inst_capacity,
+                          const uint32_t* tile_ranges,
+                          const sgs_camera* cams_host, const sgs_camera* cams_dev,
+                          int32_t n_views, const sgs_options* opt, const float* out_T,
+                          const uint32_t* out_last, const float* dL_drgb,
+                          int64_t total_pixels, const sgs_geom_grad* g2d,
+                          const sgs_params_grad* grad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGS_H */

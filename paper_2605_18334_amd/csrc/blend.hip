@@ -1,0 +1,391 @@
+// Per-tile compositing of projected skew Gaussians, forward and backward.
+//
+// One workgroup per screen tile (TW x TH pixels, one pixel per thread, each
+// wave64 owns an 8x8 block so that a wave's pixels are compact and its
+// per-pair skips tend to be uniform).  The tile's sorted list is walked in
+// batches of B records staged in LDS; every lane of a wave reads the same
+// record at the same time, so per-record branches (symmetric record: no
+// erf) never diverge.
+//
+// Forward (Alg. 1): alpha = min(alpha_max, d G' (1 + erf z)) per pair, pairs
+// below alpha_min skipped, a pixel stops before T would drop below t_min,
+// C += c alpha T.  Backward (Alg. 2): each pixel walks its list from its last
+// contributor to the front, rebuilding T_k = T_{k+1} / (1 - alpha_k) from the
+// final transmittance (nothing per pair is stored), with the colour behind k
+// kept as a running sum.  Per-pair partial derivatives are summed over the
+// wave with DPP, over the waves in LDS, and written with one set of global
+// atomics per (record, tile).
+#include "sgs_dev.h"
+
+namespace sgs {
+
+struct BlendArgs {
+  const float4* rec0;
+  const float4* rec1;
+  const float4* rec2;
+  const float4* rec3;
+  const uint32_t* vals;
+  const uint2* ranges;
+  const sgs_camera* cams;
+  int32_t n_views;
+  int32_t total_tiles;
+  uint32_t n_vals;         // length of vals (instance capacity)
+  uint32_t m;              // number of records
+  float alpha_min, alpha_max, t_min;
+  int64_t P;               // pixels of all views (plane stride)
+  float* out_rgb;
+  float* out_T;
+  uint32_t* out_last;
+  uint32_t* out_count;     // optional: contributing pairs per pixel
+  // backward
+  const float* cT;
+  const uint32_t* clast;
+  const float* dL;
+  float4* g0;
+  float4* g1;
+  float4* g2;
+  float4* g3;
+};
+
+struct TileSetup {
+  int tile, view;
+  int px, py;
+  bool inside;
+  const sgs_camera* cam;
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ bool setup_tile(const BlendArgs& a, TileSetup& s) {
+  s.tile = xcd_tile(blockIdx.x, a.total_tiles, gridDim.x);
+  if (s.tile >= a.total_tiles) return false;
+  s.view = find_view(a.cams, a.n_views, s.tile);
+  s.cam = a.cams + s.view;
+  const int lt = s.tile - s.cam->tile_base;
+  const int tx = lt % s.cam->tiles_x, ty = lt / s.cam->tiles_x;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  s.px = tx * TW + (w % (TW / 8)) * 8 + (l & 7);
+  s.py = ty * TH + (w / (TW / 8)) * 8 + (l >> 3);
+  s.inside = s.px < s.cam->width && s.py < s.cam->height;
+  return true;
+}
+
+template <int TW, int TH, int B, bool ENH>
+__global__ void __launch_bounds__(TW * TH) k_blend_fwd(BlendArgs a) {
+  constexpr int NT = TW * TH;
+  __shared__ float4 s0[B], s1[B], s2[B];
+  __shared__ float4 s3[ENH ? B : 1];
+  TileSetup ts;
+  if (!setup_tile<TW, TH>(a, ts)) return;
+  const int t = threadIdx.x;
+  const float fx = (float)ts.px + 0.5f, fy = (float)ts.py + 0.5f;
+  uint2 rg = a.ranges[ts.tile];
+  rg.y = min(rg.y, a.n_vals);
+  rg.x = min(rg.x, rg.y);
+  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  uint32_t last = 0, count = 0;
+  bool done = !ts.inside;
+  for (uint32_t base = rg.x; base < rg.y; base += B) {
+    if (__syncthreads_and(done)) break;
+    for (int k = t; k < B; k += NT) {
+      const uint32_t idx = base + k;
+      if (idx < rg.y) {
+        uint32_t m = a.vals[idx];
+        if (m >= a.m) m = 0;
+        s0[k] = a.rec0[m];
+        s1[k] = a.rec1[m];
+        s2[k] = a.rec2[m];
+        if (ENH) s3[k] = a.rec3[m];
+      }
+    }
+    __syncthreads();
+    const int cnt = (int)min((uint32_t)B, rg.y - base);
+    for (int j = 0; j < cnt; ++j) {
+      if (done) break;
+      const float4 r0 = s0[j];
+      const float4 r1 = s1[j];
+      const float dx = fx - r0.x, dy = fy - r0.y;
+      const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
+      const float4 r2 = s2[j];
+      if (power < r2.w) continue;
+      Pair p;
+      pair_eval(power, r1.w, r1.y, r1.z, dx, dy, (r1.y != 0.0f) || (r1.z != 0.0f), p);
+      float at = p.at;
+      if (ENH) {
+        const float4 r3 = s3[j];
+        float u, eu;
+        at *= enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, u, eu);
+      }
+      const float alpha = fminf(a.alpha_max, at);
+      if (alpha < a.alpha_min) continue;
+      const float Tn = T * (1.0f - alpha);
+      if (Tn < a.t_min) {
+        done = true;
+        break;
+      }
+      const float wgt = alpha * T;
+      C0 = fmaf(r2.x, wgt, C0);
+      C1 = fmaf(r2.y, wgt, C1);
+      C2 = fmaf(r2.z, wgt, C2);
+      T = Tn;
+      last = base - rg.x + (uint32_t)j + 1u;
+      ++count;
+    }
+  }
+  if (ts.inside) {
+    const int64_t pix = ts.cam->pix_base + (int64_t)ts.py * ts.cam->width + ts.px;
+    a.out_rgb[pix] = fmaf(T, ts.cam->bg[0], C0);
+    a.out_rgb[a.P + pix] = fmaf(T, ts.cam->bg[1], C1);
+    a.out_rgb[2 * a.P + pix] = fmaf(T, ts.cam->bg[2], C2);
+    a.out_T[pix] = T;
+    a.out_last[pix] = last;
+    if (a.out_count) a.out_count[pix] = count;
+  }
+}
+
+template <int TW, int TH, int B, bool ENH>
+__global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
+  constexpr int NT = TW * TH;
+  constexpr int NG = ENH ? 15 : 11;   // values per record: see the flush below
+  __shared__ float4 s0[B], s1[B], s2[B];
+  __shared__ float4 s3[ENH ? B : 1];
+  __shared__ uint32_t sm[B];
+  __shared__ float sg[NG][B];
+  __shared__ uint32_t smax;
+  TileSetup ts;
+  if (!setup_tile<TW, TH>(a, ts)) return;
+  const int t = threadIdx.x, lane = t & 63;
+  const float fx = (float)ts.px + 0.5f, fy = (float)ts.py + 0.5f;
+  uint2 rg = a.ranges[ts.tile];
+  rg.y = min(rg.y, a.n_vals);
+  rg.x = min(rg.x, rg.y);
+  float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+  uint32_t last = 0;
+  if (ts.inside) {
+    const int64_t pix = ts.cam->pix_base + (int64_t)ts.py * ts.cam->width + ts.px;
+    T = a.cT[pix];
+    last = a.clast[pix];
+    g0 = a.dL[pix];
+    g1 = a.dL[a.P + pix];
+    g2 = a.dL[2 * a.P + pix];
+  }
+  const float bgdot = ts.cam->bg[0] * g0 + ts.cam->bg[1] * g1 + ts.cam->bg[2] * g2;
+  const float Tfinal = T;
+  float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;   // colour behind, normalised
+  if (t == 0) smax = 0;
+  __syncthreads();
+  if (last) atomicMax(&smax, last);
+  __syncthreads();
+  const int nmax = (int)smax;
+  for (int end = nmax; end > 0; end -= B) {
+    const int start = end > B ? end - B : 0;
+    const int cnt = end - start;
+    __syncthreads();
+    for (int k = t; k < cnt; k += NT) {
+      const uint32_t idx = rg.x + start + k;
+      uint32_t m = idx < rg.y ? a.vals[idx] : 0u;
+      if (m >= a.m) m = 0;
+      sm[k] = m;
+      s0[k] = a.rec0[m];
+      s1[k] = a.rec1[m];
+      s2[k] = a.rec2[m];
+      if (ENH) s3[k] = a.rec3[m];
+    }
+    for (int k = t; k < NG * B; k += NT) (&sg[0][0])[k] = 0.0f;
+    __syncthreads();
+    for (int j = cnt - 1; j >= 0; --j) {
+      float gv[NG];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) gv[q] = 0.0f;
+      bool hit = false;
+      if ((uint32_t)(start + j) < last) {
+        const float4 r0 = s0[j];
+        const float4 r1 = s1[j];
+        const float dx = fx - r0.x, dy = fy - r0.y;
+        const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
+        const float4 r2 = s2[j];
+        if (power >= r2.w) {
+          Pair p;
+          pair_eval(power, r1.w, r1.y, r1.z, dx, dy, (r1.y != 0.0f) || (r1.z != 0.0f), p);
+          float at = p.at, o = 1.0f, u = 0.0f, eu = 0.0f;
+          float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (ENH) {
+            r3 = s3[j];
+            o = enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, u, eu);
+            at *= o;
+          }
+          const float alpha = fminf(a.alpha_max, at);
+          if (alpha >= a.alpha_min) {
+            hit = true;
+            T = T / (1.0f - alpha);           // transmittance in front of this pair
+            const float wgt = alpha * T;
+            gv[8] = wgt * g0;
+            gv[9] = wgt * g1;
+            gv[10] = wgt * g2;
+            float dLda = ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) * T;
+            dLda -= Tfinal / (1.0f - alpha) * bgdot;
+            if (at <= a.alpha_max) {
+              const float dd = r1.w * o;              // d, times o(delta) with enhanced opacity
+              const float ez = __expf(-p.z * p.z);    // e^{-z^2}, 1 when z = 0
+              const float s2pi = SGS_SQRT_2_OVER_PI * ez;
+              const float common = dLda * dd * p.G;
+              const float qa = fmaf(r0.z, dx, r0.w * dy), qc = fmaf(r0.w, dx, r1.x * dy);
+              gv[0] = common * (qa * p.E - s2pi * r1.y);
+              gv[1] = common * (qc * p.E - s2pi * r1.z);
+              gv[2] = -0.5f * dx * dx * dLda * at;
+              gv[3] = -dx * dy * dLda * at;
+              gv[4] = -0.5f * dy * dy * dLda * at;
+              gv[5] = common * s2pi * dx;
+              gv[6] = common * s2pi * dy;
+              gv[7] = dLda * p.G * p.E * o;
+              if (ENH) {
+                const float base = p.at;             // rho G' (1 + erf z)
+                const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * __expf(-u * u);
+                gv[0] -= dLda * base * dodw * r3.z;
+                gv[1] -= dLda * base * dodw * r3.w;
+                gv[11] = dLda * base * 0.5f * (1.0f + eu);
+                gv[12] = dLda * base * 0.5f * (1.0f - eu);
+                gv[13] = dLda * base * dodw * dx;
+                gv[14] = dLda * base * dodw * dy;
+              }
+            }
+            S0 = fmaf(alpha, r2.x - S0, S0);
+            S1 = fmaf(alpha, r2.y - S1, S1);
+            S2 = fmaf(alpha, r2.z - S2, S2);
+          }
+        }
+      }
+      if (__ballot(hit)) {
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+          const float s = wave_sum_to_lane63(gv[q]);
+          if (lane == 63 && s != 0.0f) atomicAdd(&sg[q][j], s);
+        }
+      }
+    }
+    __syncthreads();
+    for (int k = t; k < cnt; k += NT) {
+      float v[NG];
+      bool any = false;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        v[q] = sg[q][k];
+        any |= v[q] != 0.0f;
+      }
+      if (!any) continue;
+      const uint32_t m = sm[k];
+      float* p0 = reinterpret_cast<float*>(a.g0 + m);
+      float* p1 = reinterpret_cast<float*>(a.g1 + m);
+      float* p2 = reinterpret_cast<float*>(a.g2 + m);
+      atomicAdd(p0 + 0, v[0]);   // mu_x
+      atomicAdd(p0 + 1, v[1]);   // mu_y
+      atomicAdd(p0 + 2, v[2]);   // a
+      atomicAdd(p0 + 3, v[3]);   // b
+      atomicAdd(p1 + 0, v[4]);   // c
+      atomicAdd(p1 + 1, v[5]);   // beta_x
+      atomicAdd(p1 + 2, v[6]);   // beta_y
+      atomicAdd(p1 + 3, v[7]);   // d (rho with enhanced opacity)
+      atomicAdd(p2 + 0, v[8]);   // r
+      atomicAdd(p2 + 1, v[9]);   // g
+      atomicAdd(p2 + 2, v[10]);  // b
+      if (ENH) {
+        float* p3 = reinterpret_cast<float*>(a.g3 + m);
+        atomicAdd(p3 + 0, v[11]);  // alpha_1
+        atomicAdd(p3 + 1, v[12]);  // alpha_2
+        atomicAdd(p3 + 2, v[13]);  // w_x
+        atomicAdd(p3 + 3, v[14]);  // w_y
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <int TW, int TH, int B, bool ENH>
+static void launch_fwd_t(const BlendArgs& a, unsigned grid, hipStream_t s) {
+  k_blend_fwd<TW, TH, B, ENH><<<grid, TW * TH, 0, s>>>(a);
+}
+template <int TW, int TH, int B, bool ENH>
+static void launch_bwd_t(const BlendArgs& a, unsigned grid, hipStream_t s) {
+  k_blend_bwd<TW, TH, B, ENH><<<grid, TW * TH, 0, s>>>(a);
+}
+
+template <bool BWD, int TW, int TH, bool ENH>
+static sgs_status dispatch_b(const BlendArgs& a, int batch, unsigned grid, hipStream_t s) {
+  switch (batch) {
+    case 64: BWD ? launch_bwd_t<TW, TH, 64, ENH>(a, grid, s) : launch_fwd_t<TW, TH, 64, ENH>(a, grid, s); break;
+    case 128: BWD ? launch_bwd_t<TW, TH, 128, ENH>(a, grid, s) : launch_fwd_t<TW, TH, 128, ENH>(a, grid, s); break;
+    case 256: BWD ? launch_bwd_t<TW, TH, 256, ENH>(a, grid, s) : launch_fwd_t<TW, TH, 256, ENH>(a, grid, s); break;
+    default: return SGS_EUNSUPPORTED;
+  }
+  SGS_LAUNCH_CHECK();
+  return SGS_OK;
+}
+
+template <bool BWD, bool ENH>
+static sgs_status dispatch_tile(const BlendArgs& a, const sgs_options* opt, unsigned grid,
+                                hipStream_t s) {
+  if (opt->tile_w == 16 && opt->tile_h == 16) return dispatch_b<BWD, 16, 16, ENH>(a, opt->blend_batch, grid, s);
+  if (opt->tile_w == 16 && opt->tile_h == 8) return dispatch_b<BWD, 16, 8, ENH>(a, opt->blend_batch, grid, s);
+  if (opt->tile_w == 8 && opt->tile_h == 8) return dispatch_b<BWD, 8, 8, ENH>(a, opt->blend_batch, grid, s);
+  return SGS_EUNSUPPORTED;
+}
+
+static BlendArgs make_args(const sgs_geom* g, int64_t m, const uint32_t* vals, int64_t cap,
+                           const uint32_t* ranges, const sgs_camera* cams_dev, int32_t n_views,
+                           int64_t total_tiles, const sgs_options* opt, int64_t P) {
+  BlendArgs a = {};
+  const float4* rec = reinterpret_cast<const float4*>(g->rec);
+  a.rec0 = rec;
+  a.rec1 = rec + m;
+  a.rec2 = rec + 2 * m;
+  a.rec3 = rec + 3 * m;
+  a.vals = vals;
+  a.n_vals = (uint32_t)cap;
+  a.ranges = reinterpret_cast<const uint2*>(ranges);
+  a.cams = cams_dev;
+  a.n_views = n_views;
+  a.total_tiles = (int32_t)total_tiles;
+  a.m = (uint32_t)m;
+  a.alpha_min = opt->alpha_min;
+  a.alpha_max = opt->alpha_max;
+  a.t_min = opt->t_min;
+  a.P = P;
+  return a;
+}
+
+static unsigned blend_grid(int64_t total_tiles) { return (unsigned)((total_tiles + 7) / 8 * 8); }
+
+sgs_status launch_blend_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals, int64_t cap,
+                            const uint32_t* ranges, const sgs_camera* cams_dev, int32_t n_views,
+                            int64_t total_tiles, int enhanced, const sgs_options* opt,
+                            float* out_rgb, float* out_T, uint32_t* out_last,
+                            uint32_t* out_count, int64_t P, hipStream_t s) {
+  BlendArgs a = make_args(g, m, vals, cap, ranges, cams_dev, n_views, total_tiles, opt, P);
+  a.out_rgb = out_rgb;
+  a.out_T = out_T;
+  a.out_last = out_last;
+  a.out_count = out_count;
+  const unsigned grid = blend_grid(total_tiles);
+  return enhanced ? dispatch_tile<false, true>(a, opt, grid, s)
+                  : dispatch_tile<false, false>(a, opt, grid, s);
+}
+
+sgs_status launch_blend_bwd(const sgs_geom* g, int64_t m, const uint32_t* vals, int64_t cap,
+                            const uint32_t* ranges, const sgs_camera* cams_dev, int32_t n_views,
+                            int64_t total_tiles, int enhanced, const sgs_options* opt,
+                            const float* out_T, const uint32_t* out_last, const float* dL,
+                            int64_t P, float* g2d, hipStream_t s) {
+  BlendArgs a = make_args(g, m, vals, cap, ranges, cams_dev, n_views, total_tiles, opt, P);
+  a.cT = out_T;
+  a.clast = out_last;
+  a.dL = dL;
+  float4* gr = reinterpret_cast<float4*>(g2d);
+  a.g0 = gr;
+  a.g1 = gr + m;
+  a.g2 = gr + 2 * m;
+  a.g3 = gr + 3 * m;
+  const unsigned grid = blend_grid(total_tiles);
+  return enhanced ? dispatch_tile<true, true>(a, opt, grid, s)
+                  : dispatch_tile<true, false>(a, opt, grid, s);
+}
+
+}  // namespace sgs

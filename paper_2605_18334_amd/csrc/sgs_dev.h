@@ -1,0 +1,202 @@
+// Device-side helpers shared by the HIP kernels of the skew-Gaussian
+// rasterizer (gfx950, wave64).  Internal to the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sgs.h"
+
+#define SGS_INV_SQRT2 0.70710678118654752f
+#define SGS_SQRT_2_OVER_PI 0.79788456080286536f   // sqrt(2/pi)
+#define SGS_INV_SQRT_2PI 0.39894228040143268f      // 1/sqrt(2 pi)
+
+namespace sgs {
+
+constexpr int kWave = 64;
+
+// Checks the launch that was just enqueued.
+#define SGS_LAUNCH_CHECK()                                   \
+  do {                                                       \
+    hipError_t e__ = hipGetLastError();                      \
+    if (e__ != hipSuccess) return SGS_EHIP;                  \
+  } while (0)
+
+__device__ __forceinline__ float4 ld4(const float* p, int64_t i) {
+  return reinterpret_cast<const float4*>(p)[i];
+}
+
+// ---------------------------------------------------------------- the pair
+// alpha~ of one (pixel, record) pair, Alg. 1: G' = exp(-(a dx^2 + c dy^2)/2
+// - b dx dy), z = (beta_x dx + beta_y dy)/sqrt 2, alpha~ = d G' (1 + erf z).
+// Written with explicit fma so that the forward and the backward kernels
+// evaluate bit-identical values (their decisions must agree).
+struct Pair {
+  float power;  // exponent of G'
+  float G;      // G'
+  float z;      // skew argument
+  float E;      // 1 + erf(z)
+  float at;     // unclamped alpha (without the enhanced-opacity factor)
+};
+
+__device__ __forceinline__ float pair_power(float a, float b, float c, float dx, float dy) {
+  float q = fmaf(a * dx, dx, fmaf(c * dy, dy, (2.0f * b) * (dx * dy)));
+  return -0.5f * q;
+}
+
+__device__ __forceinline__ void pair_eval(float power, float d, float bx, float by, float dx,
+                                          float dy, bool skew, Pair& p) {
+  p.power = power;
+  p.G = __expf(power);
+  if (skew) {
+    p.z = fmaf(bx, dx, by * dy) * SGS_INV_SQRT2;
+    p.E = 1.0f + erff(p.z);
+  } else {
+    p.z = 0.0f;
+    p.E = 1.0f;
+  }
+  p.at = (d * p.G) * p.E;
+}
+
+// Enhanced opacity factor o(delta) = ((o1+o2) + (o1-o2) erf(w.delta/sqrt2))/2
+// (Sec. "3D Skew Gaussian Rasterization and Splatting").
+__device__ __forceinline__ float enh_opacity(float o1, float o2, float wx, float wy, float dx,
+                                             float dy, float& u, float& erfu) {
+  u = fmaf(wx, dx, wy * dy) * SGS_INV_SQRT2;
+  erfu = erff(u);
+  return 0.5f * fmaf(o1 - o2, erfu, o1 + o2);
+}
+
+// ---------------------------------------------------------------- wave ops
+// Sum over the 64 lanes of a wave with DPP; the total lands in lane 63.
+// All 64 lanes must be active.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ float dpp_src(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, false));
+}
+
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  v += dpp_src<0xB1>(v);          // quad_perm [1,0,3,2]
+  v += dpp_src<0x4E>(v);          // quad_perm [2,3,0,1]
+  v += dpp_src<0x141>(v);         // row_half_mirror
+  v += dpp_src<0x140>(v);         // row_mirror: every lane holds its row sum
+  v += dpp_src<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+  v += dpp_src<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+  return v;                       // lane 63: sum of all 64 lanes
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// ---------------------------------------------------------------- SH
+// Real spherical harmonics up to degree 3 (3DGS ordering m = -l..l, sin terms
+// for m < 0, Condon-Shortley phase), unit direction (x, y, z).
+constexpr float SH_C0 = 0.28209479177387814f;
+constexpr float SH_C1 = 0.4886025119029199f;
+constexpr float SH_C2[5] = {1.0925484305920792f, -1.0925484305920792f, 0.31539156525252005f,
+                            -1.0925484305920792f, 0.5462742152960396f};
+constexpr float SH_C3[7] = {-0.5900435899266435f, 2.890611442640554f, -0.4570457994644658f,
+                            0.3731763325901154f, -0.4570457994644658f, 1.445305721320277f,
+                            -0.5900435899266435f};
+
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
+  Y[0] = SH_C0;
+  if (DEG > 0) {
+    Y[1] = -SH_C1 * y;
+    Y[2] = SH_C1 * z;
+    Y[3] = -SH_C1 * x;
+  }
+  if (DEG > 1) {
+    float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = SH_C2[0] * x * y;
+    Y[5] = SH_C2[1] * y * z;
+    Y[6] = SH_C2[2] * (2.0f * zz - xx - yy);
+    Y[7] = SH_C2[3] * x * z;
+    Y[8] = SH_C2[4] * (xx - yy);
+    if (DEG > 2) {
+      Y[9] = SH_C3[0] * y * (3.0f * xx - yy);
+      Y[10] = SH_C3[1] * x * y * z;
+      Y[11] = SH_C3[2] * y * (4.0f * zz - xx - yy);
+      Y[12] = SH_C3[3] * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+      Y[13] = SH_C3[4] * x * (4.0f * zz - xx - yy);
+      Y[14] = SH_C3[5] * z * (xx - yy);
+      Y[15] = SH_C3[6] * x * (xx - 3.0f * yy);
+    }
+  }
+}
+
+// Gradient of sum_k w[k] Y_k(x,y,z) w.r.t. (x, y, z) of the polynomial forms
+// above (the caller projects it onto the tangent plane of the unit sphere).
+template <int DEG>
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const float* w,
+                                              float& gx, float& gy, float& gz) {
+  gx = gy = gz = 0.0f;
+  if (DEG > 0) {
+    gy += -SH_C1 * w[1];
+    gz += SH_C1 * w[2];
+    gx += -SH_C1 * w[3];
+  }
+  if (DEG > 1) {
+    float xx = x * x, yy = y * y, zz = z * z;
+    gx += SH_C2[0] * y * w[4];
+    gy += SH_C2[0] * x * w[4];
+    gy += SH_C2[1] * z * w[5];
+    gz += SH_C2[1] * y * w[5];
+    gx += SH_C2[2] * (-2.0f * x) * w[6];
+    gy += SH_C2[2] * (-2.0f * y) * w[6];
+    gz += SH_C2[2] * (4.0f * z) * w[6];
+    gx += SH_C2[3] * z * w[7];
+    gz += SH_C2[3] * x * w[7];
+    gx += SH_C2[4] * (2.0f * x) * w[8];
+    gy += SH_C2[4] * (-2.0f * y) * w[8];
+    if (DEG > 2) {
+      // Y9 = C y (3xx - yy)
+      gx += SH_C3[0] * 6.0f * x * y * w[9];
+      gy += SH_C3[0] * (3.0f * xx - 3.0f * yy) * w[9];
+      // Y10 = C x y z
+      gx += SH_C3[1] * y * z * w[10];
+      gy += SH_C3[1] * x * z * w[10];
+      gz += SH_C3[1] * x * y * w[10];
+      // Y11 = C y (4zz - xx - yy)
+      gx += SH_C3[2] * (-2.0f * x * y) * w[11];
+      gy += SH_C3[2] * (4.0f * zz - xx - 3.0f * yy) * w[11];
+      gz += SH_C3[2] * (8.0f * y * z) * w[11];
+      // Y12 = C z (2zz - 3xx - 3yy)
+      gx += SH_C3[3] * (-6.0f * x * z) * w[12];
+      gy += SH_C3[3] * (-6.0f * y * z) * w[12];
+      gz += SH_C3[3] * (6.0f * zz - 3.0f * xx - 3.0f * yy) * w[12];
+      // Y13 = C x (4zz - xx - yy)
+      gx += SH_C3[4] * (4.0f * zz - 3.0f * xx - yy) * w[13];
+      gy += SH_C3[4] * (-2.0f * x * y) * w[13];
+      gz += SH_C3[4] * (8.0f * x * z) * w[13];
+      // Y14 = C z (xx - yy)
+      gx += SH_C3[5] * (2.0f * x * z) * w[14];
+      gy += SH_C3[5] * (-2.0f * y * z) * w[14];
+      gz += SH_C3[5] * (xx - yy) * w[14];
+      // Y15 = C x (xx - 3yy)
+      gx += SH_C3[6] * (3.0f * xx - 3.0f * yy) * w[15];
+      gy += SH_C3[6] * (-6.0f * x * y) * w[15];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- camera
+__device__ __forceinline__ int find_view(const sgs_camera* cams, int n_views, int tile) {
+  int v = 0;
+  for (int k = 1; k < n_views; ++k)
+    if (tile >= cams[k].tile_base) v = k;
+  return v;
+}
+
+// Spreads consecutive workgroups over tile bands so that the tiles one XCD
+// (chiplet, own L2) works on are neighbours: workgroups are dispatched to the
+// 8 XCDs round-robin, so workgroup b runs on XCD b % 8.
+__device__ __forceinline__ int xcd_tile(int b, int total_tiles, int n_blocks) {
+  const int per = n_blocks >> 3;      // n_blocks is a multiple of 8
+  return (b & 7) * per + (b >> 3);
+}
+
+}  // namespace sgs

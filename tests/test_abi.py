@@ -1,0 +1,126 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol include/sgs.h declares, its struct sizes match the binding, and
+the host helpers (CoordEngine, layout, sizes, argument checks) behave."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import sgs_synth as S
+from oracle import sgs_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2605_18334_amd import _abi
+    return _abi, _abi.load()
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "sgs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    _abi, lib = _lib()
+    names = _declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _abi.SIGNATURES, f"binding lacks {n}"
+
+
+def test_struct_sizes_match_binding():
+    _abi, lib = _lib()
+    for i, s in enumerate(_abi.STRUCTS):
+        assert lib.sgs_struct_size(i) == C.sizeof(s), s.__name__
+    assert lib.sgs_struct_size(99) == 0
+
+
+def test_default_options_and_status_strings():
+    _abi, lib = _lib()
+    o = _abi.default_options()
+    assert (o.tile_w, o.tile_h, o.blend_batch, o.sort_mode, o.compensate) == (16, 16, 256, 1, 1)
+    assert o.alpha_min == pytest.approx(1 / 255) and o.alpha_max == pytest.approx(0.99)
+    assert o.t_min == pytest.approx(1e-4) and o.filter_s == pytest.approx(0.3)
+    assert lib.sgs_status_string(0) == b"ok"
+    assert lib.sgs_status_string(1) == b"invalid argument"
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_camera_from_gl_matches_oracle_coord_engine(seed):
+    """The library's CoordEngine/K (float32 out) equals the oracle's FP64
+    M_cv = M_gl T_align, w2c = M_cv^-1, K."""
+    from paper_2605_18334_amd.raster import CameraBatch
+    rng = np.random.default_rng(seed)
+    pose = S.random_request_pose(rng)
+    cam = CameraBatch.camera_from_pose(pose)
+    ref = O.camera_from_pose(pose)
+    w2c = np.array(list(cam.w2c)).reshape(3, 4)
+    np.testing.assert_allclose(w2c, ref.w2c[:3], rtol=0, atol=2e-6 * max(1.0, np.abs(ref.w2c).max()))
+    np.testing.assert_allclose([cam.fx, cam.fy, cam.cx, cam.cy],
+                               [ref.K[0, 0], ref.K[1, 1], ref.K[0, 2], ref.K[1, 2]], rtol=1e-6)
+    np.testing.assert_allclose(list(cam.campos), ref.position, atol=1e-5)
+    assert (cam.width, cam.height) == (pose.width, pose.height)
+
+
+def test_camera_from_gl_rejects_bad_input():
+    _abi, lib = _lib()
+    cam = _abi.Camera()
+    m = (C.c_double * 16)(*np.eye(4).reshape(-1))
+    assert lib.sgs_camera_from_gl(m, 0, 10, 1.0, 0.0, 0.2, None, C.byref(cam)) == 1
+    assert lib.sgs_camera_from_gl(m, 10, 10, 0.0, 0.0, 0.2, None, C.byref(cam)) == 1
+    bad = (C.c_double * 16)(*([float("nan")] + [0.0] * 15))
+    assert lib.sgs_camera_from_gl(bad, 10, 10, 1.0, 0.0, 0.2, None, C.byref(cam)) == 1
+    sing = (C.c_double * 16)(*np.zeros(16))
+    assert lib.sgs_camera_from_gl(sing, 10, 10, 1.0, 0.0, 0.2, None, C.byref(cam)) == 1
+
+
+def test_camera_layout_tiles_and_pixels():
+    _abi, lib = _lib()
+    from paper_2605_18334_amd.raster import CameraBatch
+    poses = S.spline_poses(5, 4)
+    cams = [CameraBatch.camera_from_pose(p) for p in poses]
+    arr = (_abi.Camera * 4)(*cams)
+    for tw, th in [(16, 16), (16, 8), (8, 8)]:
+        o = _abi.default_options(tile_w=tw, tile_h=th)
+        tt, tp = C.c_int64(), C.c_int64()
+        assert lib.sgs_camera_layout(arr, 4, C.byref(o), C.byref(tt), C.byref(tp)) == 0
+        exp_t = sum(-(-p.width // tw) * -(-p.height // th) for p in poses)
+        assert tt.value == exp_t and tp.value == sum(p.width * p.height for p in poses)
+        base = 0
+        for v in range(4):
+            assert arr[v].tile_base == base
+            base += arr[v].tiles_x * arr[v].tiles_y
+    o = _abi.default_options(tile_w=12)
+    assert lib.sgs_camera_layout(arr, 4, C.byref(o), None, None) == 1
+
+
+def test_size_helpers():
+    _abi, lib = _lib()
+    assert lib.sgs_geom_rec_floats(10, 0) == 120 and lib.sgs_geom_rec_floats(10, 1) == 160
+    assert lib.sgs_geom_block_entries(300, 2) == 2 * 2 + 1
+    o = _abi.default_options()
+    a = lib.sgs_bin_sort_scratch_bytes(1000, 5000, 64, C.byref(o))
+    b = lib.sgs_bin_sort_scratch_bytes(1000, 50000, 64, C.byref(o))
+    assert 0 < a < b
+
+
+def test_entry_points_reject_null_arguments_without_gpu():
+    """Argument checks happen before any HIP call."""
+    _abi, lib = _lib()
+    o = _abi.default_options()
+    g = _abi.Geom()
+    p = _abi.Params()
+    p.n = -1
+    assert lib.sgs_preprocess(C.byref(p), None, None, 1, C.byref(o), C.byref(g), None) == 1
+    assert lib.sgs_bin_sort(None, 0, None, None, 1, C.byref(o), 0, None, None, None, None, None, 0, None) == 1
+    assert lib.sgs_render_fwd(None, 0, None, 0, None, None, None, 1, 0, C.byref(o), None, None, None, None,
+                              0, None) == 1
+    assert lib.sgs_render_bwd(None, None, 0, None, 0, None, None, None, 1, C.byref(o), None, None, None, 0,
+                              None, None, None) == 1

