@@ -147,6 +147,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--only", choices=["fwd", "fwdbwd"], default=None,
+                    help="run one workload only (for profiler runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size "
+                         "kernel that scales hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -159,6 +164,15 @@ def main():
     import sgs_synth as S
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.only == "fwdbwd":
+        print(json.dumps(fwd_bwd(max(3, args.steps // 2), 2)), flush=True)
+        return
     sc, pose = S.clustered_config()
     opt = P.default_options()
     gs = P.GaussianSet.from_scene(sc)
@@ -201,12 +215,12 @@ def main():
         "stages_ms": stages, "n_inst": n_inst, "composited_pairs": pairs,
         "roofline": roof,
     }
-    if not args.no_bwd:
+    if not args.no_bwd and args.only is None:
         del R
         torch.cuda.empty_cache()
         out["fwd_bwd"] = fwd_bwd(max(3, args.steps // 2), 2)
         log(f"fwd+bwd {out['fwd_bwd']}")
-    if not args.no_cpu:
+    if not args.no_cpu and args.only is None:
         out["cpu_baseline"] = cpu_baseline(sc, pose, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -1,21 +1,27 @@
 // Tile binning: one instance per (record, covered tile), a stable LSD radix
 // sort by (global tile, depth), and per-tile ranges of the sorted list.
 //
-// Radix sort (hand-written, stable, 8-bit digits, 256-thread blocks of
-// 4096 keys): per pass an upsweep writes each block's digit histogram, three
-// small kernels turn the [blocks][256] histograms into exclusive scatter
-// offsets, and a downsweep ranks keys inside each wave with 8 ballots per
-// key (wave64 multisplit; lanes of one wave hold consecutive keys, so the
-// rank is stable), stages the block's keys in digit order in LDS and writes
-// them out so consecutive lanes write consecutive addresses.
+// Radix sort (hand-written, stable, 8-bit digits, 256-thread blocks of 4096
+// keys), one kernel per pass in the onesweep style (Adinets & Merrill 2022):
+// a single histogram kernel reads the keys once and counts the digits of
+// every pass; each pass kernel takes a block id from an atomic counter (so
+// every lower id is already running), ranks its keys inside each wave64 with
+// 8 ballots per key (lanes hold consecutive keys, so ranks are stable),
+// publishes its per-digit counts, and finds its global offsets by looking
+// back over the published counts of the blocks before it (decoupled
+// look-back).  The look-back spin is bounded: it never hangs, it flags an
+// error word instead.  Keys are staged in LDS in digit order so that
+// consecutive lanes write consecutive addresses.
 //
 // Two orders of work give the same sorted list (by tile, then depth, then
 // record index):
-//   mode 0: 64-bit keys (tile << 32 | depth bits) sorted over 32 + tile bits;
-//   mode 1: the M records are first sorted by depth (32-bit keys), instances
-//           are written in that order with 32-bit tile keys, which are then
-//           sorted over the tile bits only (stable, so depth order and index
-//           order within a tile survive).  Far fewer bytes move.
+//   mode 0: 64-bit keys (tile << 32 | depth bits), written per record in
+//           record order, sorted over 32 + tile bits;
+//   mode 1: the M records are first sorted by depth (32-bit keys); the
+//           instances are expanded in that order with 32-bit tile keys (load
+//           balanced: one block per 2048 instances, not one thread per
+//           record), then sorted over the tile bits only.  Stability keeps
+//           depth order and index order inside a tile.  Far fewer bytes move.
 #include <algorithm>
 
 #include "sgs_dev.h"
@@ -27,6 +33,10 @@ sgs_status launch_scan_blocks(const uint32_t* in, uint32_t* out, int64_t nb, hip
 constexpr int RS_T = 256;          // threads per block
 constexpr int RS_IPT = 16;         // keys per thread
 constexpr int RS_TILE = RS_T * RS_IPT;
+constexpr int RS_MAX_PASSES = 8;
+constexpr uint64_t ST_AGG = 1ull << 32;    // status: block's own digit count
+constexpr uint64_t ST_INC = 2ull << 32;    // status: inclusive prefix over blocks
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
 __device__ __forceinline__ uint32_t count_of(const uint32_t* n_dev, uint32_t n_host, uint32_t cap) {
   const uint32_t n = n_dev ? *n_dev : n_host;
@@ -49,92 +59,76 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
   return (uint32_t)(key >> shift) & mask;
 }
 
-template <typename K>
-__global__ void __launch_bounds__(RS_T) k_rs_upsweep(const K* __restrict__ keys,
-                                                     const uint32_t* n_dev, uint32_t n_host,
-                                                     uint32_t cap, int shift, uint32_t mask,
-                                                     int nbits, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[4][256];
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int k = t; k < 1024; k += RS_T) (&h[0][0])[k] = 0;
-  __syncthreads();
-  const uint32_t n = count_of(n_dev, n_host, cap);
-  const uint64_t base = (uint64_t)blockIdx.x * RS_TILE + (uint64_t)w * (RS_IPT * 64) + lane;
-  const uint64_t lt = lanemask_lt();
-  for (int i = 0; i < RS_IPT; ++i) {
-    const uint64_t idx = base + (uint64_t)i * 64;
-    const bool valid = idx < n;
-    const uint32_t d = valid ? digit_of<K>(keys[idx], shift, mask) : 0u;
-    const uint64_t peers = match_digit(d, valid, nbits);
-    if (valid && (peers & lt) == 0) h[w][d] += (uint32_t)__popcll(peers);
-  }
-  __syncthreads();
-  hist[(uint64_t)blockIdx.x * 256 + t] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
-}
-
-// Column sums of `group` histogram rows per group -> part[g][256].
-__global__ void __launch_bounds__(256) k_rs_scan_a(const uint32_t* __restrict__ hist, uint32_t rows,
-                                                   uint32_t group, uint32_t* __restrict__ part) {
-  const uint32_t g = blockIdx.x, d = threadIdx.x;
-  const uint32_t r0 = g * group, r1 = min(rows, r0 + group);
-  uint32_t s = 0;
-  for (uint32_t r = r0; r < r1; ++r) s += hist[(uint64_t)r * 256 + d];
-  part[(uint64_t)g * 256 + d] = s;
-}
-
-// part[g][d] -> digit start + exclusive prefix over groups.
-__global__ void __launch_bounds__(256) k_rs_scan_b(uint32_t* __restrict__ part, uint32_t groups) {
-  __shared__ uint32_t ws[4];
-  const uint32_t d = threadIdx.x, lane = d & 63, w = d >> 6;
-  uint32_t run = 0;
-  for (uint32_t g = 0; g < groups; ++g) {
-    const uint32_t x = part[(uint64_t)g * 256 + d];
-    part[(uint64_t)g * 256 + d] = run;
-    run += x;
-  }
-  uint32_t inc = run;
+// Exclusive scan over the 256 threads of a block of x (one value per thread).
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* ws4) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint32_t inc = x;
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t y = __shfl_up(inc, off);
-    if ((int)lane >= off) inc += y;
+    if (lane >= off) inc += y;
   }
-  if (lane == 63) ws[w] = inc;
+  if (lane == 63) ws4[w] = inc;
   __syncthreads();
-  uint32_t start = inc - run;
-  for (uint32_t k = 0; k < w; ++k) start += ws[k];
-  for (uint32_t g = 0; g < groups; ++g) part[(uint64_t)g * 256 + d] += start;
+  uint32_t e = inc - x;
+  for (int k = 0; k < w; ++k) e += ws4[k];
+  __syncthreads();
+  return e;
 }
 
-// In place: hist[r][d] -> exclusive global scatter offset of digit d, block r.
-__global__ void __launch_bounds__(256) k_rs_scan_c(uint32_t* __restrict__ hist, uint32_t rows,
-                                                   uint32_t group, const uint32_t* __restrict__ part) {
-  const uint32_t g = blockIdx.x, d = threadIdx.x;
-  const uint32_t r0 = g * group, r1 = min(rows, r0 + group);
-  uint32_t run = part[(uint64_t)g * 256 + d];
-  for (uint32_t r = r0; r < r1; ++r) {
-    const uint32_t x = hist[(uint64_t)r * 256 + d];
-    hist[(uint64_t)r * 256 + d] = run;
-    run += x;
+// Digit histograms of every pass in one read of the keys.
+template <typename K>
+__global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, const uint32_t* n_dev,
+                                                  uint32_t n_host, uint32_t cap, int bits,
+                                                  uint32_t* __restrict__ ghist) {
+  __shared__ uint32_t h[RS_MAX_PASSES][256];
+  const int t = threadIdx.x;
+  const int passes = (bits + 7) / 8;
+  for (int k = t; k < RS_MAX_PASSES * 256; k += RS_T) (&h[0][0])[k] = 0;
+  __syncthreads();
+  const uint32_t n = count_of(n_dev, n_host, cap);
+  const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+  const uint64_t lt = lanemask_lt();
+  for (int i = 0; i < RS_IPT; ++i) {
+    const uint64_t idx = base + (uint64_t)i * RS_T + t;
+    const bool valid = idx < n;
+    const K key = valid ? keys[idx] : (K)0;
+    for (int p = 0; p < passes; ++p) {
+      const int nb = min(8, bits - 8 * p);
+      const uint32_t d = digit_of<K>(key, 8 * p, (1u << nb) - 1u);
+      const uint64_t peers = match_digit(d, valid, nb);
+      if (valid && (peers & lt) == 0) atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
+    }
   }
+  __syncthreads();
+  for (int p = 0; p < passes; ++p)
+    if (h[p][t]) atomicAdd(&ghist[p * 256 + t], h[p][t]);
 }
 
 template <typename K>
-__global__ void __launch_bounds__(RS_T) k_rs_downsweep(const K* __restrict__ kin,
-                                                       const uint32_t* __restrict__ vin,
-                                                       K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                       const uint32_t* n_dev, uint32_t n_host,
-                                                       uint32_t cap, int shift, uint32_t mask,
-                                                       int nbits, const uint32_t* __restrict__ offs) {
+__global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
+                                                  const uint32_t* __restrict__ vin,
+                                                  K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                  const uint32_t* n_dev, uint32_t n_host,
+                                                  uint32_t cap, int shift, int nbits,
+                                                  const uint32_t* __restrict__ ghist,
+                                                  uint64_t* status, uint32_t* counter,
+                                                  uint32_t* err) {
   __shared__ uint32_t wc[4][256];
   __shared__ uint32_t lstart[256];
-  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t goff[256];
+  __shared__ uint32_t ws[4];
+  __shared__ uint32_t s_bid;
   __shared__ K skey[RS_TILE];
   __shared__ uint32_t sval[RS_TILE];
-  const uint32_t n = count_of(n_dev, n_host, cap);
-  const uint64_t bbase = (uint64_t)blockIdx.x * RS_TILE;
-  if (bbase >= n) return;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  if (t == 0) s_bid = atomicAdd(counter, 1u);
   for (int k = t; k < 1024; k += RS_T) (&wc[0][0])[k] = 0;
   __syncthreads();
+  const uint32_t b = s_bid;
+  const uint32_t n = count_of(n_dev, n_host, cap);
+  const uint64_t bbase = (uint64_t)b * RS_TILE;
+  if (bbase >= n) return;   // ids past the data: no later block waits on them
+  const uint32_t mask = (1u << nbits) - 1u;
   const uint64_t base = bbase + (uint64_t)w * (RS_IPT * 64) + lane;
   const uint64_t lt = lanemask_lt();
   K key[RS_IPT];
@@ -154,23 +148,42 @@ __global__ void __launch_bounds__(RS_T) k_rs_downsweep(const K* __restrict__ kin
     if (valid && r == 0) wc[w][d] = c + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  {
-    const uint32_t c0 = wc[0][t], c1 = wc[1][t], c2 = wc[2][t], c3 = wc[3][t];
-    const uint32_t tot = c0 + c1 + c2 + c3;
-    uint32_t inc = tot;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(inc, off);
-      if (lane >= off) inc += y;
+  const uint32_t c0 = wc[0][t], c1 = wc[1][t], c2 = wc[2][t], c3 = wc[3][t];
+  const uint32_t tot = c0 + c1 + c2 + c3;
+  const uint32_t ls = block_excl_scan256(tot, ws);
+  const uint32_t ds = block_excl_scan256(ghist[t], ws);   // start of digit t in the output
+  lstart[t] = ls;
+  wc[0][t] = ls;
+  wc[1][t] = ls + c0;
+  wc[2][t] = ls + c0 + c1;
+  wc[3][t] = ls + c0 + c1 + c2;
+  // publish this block's count of digit t, then look back for the prefix
+  uint64_t* st = status + (uint64_t)b * 256 + t;
+  if (b == 0) {
+    __hip_atomic_store(st, ST_INC | (uint64_t)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    goff[t] = ds;
+  } else {
+    __hip_atomic_store(st, ST_AGG | (uint64_t)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0, spins = 0;
+    uint32_t bp = b - 1;
+    for (;;) {
+      const uint64_t s = __hip_atomic_load(status + (uint64_t)bp * 256 + t, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t f = s & ~0xffffffffull;
+      if (f == 0) {
+        if (++spins > SPIN_LIMIT) {
+          atomicOr(err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += (uint32_t)s;
+      if (f == ST_INC || bp == 0) break;
+      --bp;
     }
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    uint32_t ls = inc - tot;
-    for (int k = 0; k < w; ++k) ls += wsum[k];
-    lstart[t] = ls;
-    wc[0][t] = ls;
-    wc[1][t] = ls + c0;
-    wc[2][t] = ls + c0 + c1;
-    wc[3][t] = ls + c0 + c1 + c2;
+    __hip_atomic_store(st, ST_INC | (uint64_t)(excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    goff[t] = ds + excl;
   }
   __syncthreads();
 #pragma unroll
@@ -185,11 +198,10 @@ __global__ void __launch_bounds__(RS_T) k_rs_downsweep(const K* __restrict__ kin
   }
   __syncthreads();
   const uint32_t cnt = (uint32_t)min((uint64_t)RS_TILE, (uint64_t)n - bbase);
-  const uint32_t* ob = offs + (uint64_t)blockIdx.x * 256;
   for (uint32_t j = t; j < cnt; j += RS_T) {
     const K k = skey[j];
     const uint32_t d = digit_of<K>(k, shift, mask);
-    const uint32_t g = ob[d] + (j - lstart[d]);
+    const uint32_t g = goff[d] + (j - lstart[d]);
     if (g < n) {
       kout[g] = k;
       vout[g] = sval[j];
@@ -198,20 +210,6 @@ __global__ void __launch_bounds__(RS_T) k_rs_downsweep(const K* __restrict__ kin
 }
 
 // ------------------------------------------------------------- duplicate
-__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* ws4) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  uint32_t inc = x;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(inc, off);
-    if (lane >= off) inc += y;
-  }
-  if (lane == 63) ws4[w] = inc;
-  __syncthreads();
-  uint32_t e = inc - x;
-  for (int k = 0; k < w; ++k) e += ws4[k];
-  return e;
-}
-
 struct DupArgs {
   const uint32_t* rect;
   const uint32_t* tiles;
@@ -227,6 +225,7 @@ struct DupArgs {
   uint32_t* vals;
   uint32_t* n_inst;
   const uint32_t* order; // mode 1: records in depth order
+  const uint32_t* offs;  // mode 1: exclusive instance offset of order[j]
   int64_t m;
 };
 
@@ -269,7 +268,8 @@ __global__ void __launch_bounds__(256) k_sorted_block_sums(const uint32_t* __res
                                                            const uint32_t* __restrict__ tiles,
                                                            int64_t m, uint32_t* __restrict__ sums) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  uint32_t c = j < m ? tiles[order[j]] : 0u;
+  const uint32_t o = j < m ? order[j] : 0u;
+  uint32_t c = (j < m && o < (uint64_t)m) ? tiles[o] : 0u;
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
   __shared__ uint32_t ws[4];
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
@@ -277,27 +277,85 @@ __global__ void __launch_bounds__(256) k_sorted_block_sums(const uint32_t* __res
   if (threadIdx.x == 0) sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
-// Mode 1, step 3: instances in depth order with 32-bit tile keys.
-__global__ void __launch_bounds__(256) k_duplicate32(DupArgs a) {
+// Mode 1, step 3: exclusive instance offset of every record in depth order.
+__global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restrict__ order,
+                                                        const uint32_t* __restrict__ tiles, int64_t m,
+                                                        const uint32_t* __restrict__ block_off,
+                                                        int64_t nb, uint32_t* __restrict__ offs,
+                                                        uint32_t* __restrict__ n_inst) {
   __shared__ uint32_t ws[4];
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  uint32_t mrec = j < a.m ? a.order[j] : 0u;
-  if (mrec >= (uint64_t)a.m) mrec = 0u;
-  const uint32_t cnt = j < a.m ? a.tiles[mrec] : 0u;
-  const uint32_t off = a.block_off[blockIdx.x] + block_excl_scan256(cnt, ws);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.n_inst = a.block_off[a.nb_total];
-  if (cnt == 0) return;
-  const int v = (int)(mrec / (uint64_t)a.n);
-  const uint2 r = reinterpret_cast<const uint2*>(a.rect)[mrec];
-  const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
-  const sgs_camera& cam = a.cams[v];
-  uint32_t k = off;
-  for (uint32_t y = y0; y < y1; ++y)
-    for (uint32_t x = x0; x < x1; ++x, ++k)
-      if (k < a.cap) {
-        a.keys32[k] = (uint32_t)(cam.tile_base + y * cam.tiles_x + x);
-        a.vals[k] = mrec;
-      }
+  const uint32_t o = j < m ? order[j] : 0u;
+  const uint32_t c = (j < m && o < (uint64_t)m) ? tiles[o] : 0u;
+  const uint32_t e = block_excl_scan256(c, ws);
+  if (j < m) offs[j] = block_off[blockIdx.x] + e;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_inst = block_off[nb];
+}
+
+// Mode 1, step 4: load-balanced expansion.  Block b writes instances
+// [b*EX_TILE, (b+1)*EX_TILE).  Records in depth order with at least one tile
+// come first (culled ones sort last), so the records that own this range are
+// at most EX_TILE + 1 consecutive entries starting at the last record whose
+// offset is <= the first instance; their offsets and ids are staged in LDS
+// and each thread walks its EX_PT consecutive instances.
+constexpr int EX_PT = 8;
+constexpr int EX_TILE = 256 * EX_PT;
+
+__global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
+  __shared__ uint32_t s_off[EX_TILE + 1];
+  __shared__ uint32_t s_rec[EX_TILE + 1];
+  __shared__ uint32_t s_j0, s_w;
+  const uint32_t total = *a.n_inst;
+  const uint32_t n = total < a.cap ? total : a.cap;
+  const uint64_t o0 = (uint64_t)blockIdx.x * EX_TILE;
+  if (o0 >= n) return;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    // last j with offs[j] <= o0 (offs is non-decreasing, offs[0] = 0)
+    uint64_t lo = 0, hi = (uint64_t)a.m;   // offs[lo] <= o0, answer in [lo, hi)
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (a.offs[mid] <= o0) lo = mid; else hi = mid;
+    }
+    s_j0 = (uint32_t)lo;
+    s_w = (uint32_t)min((uint64_t)(EX_TILE + 1), (uint64_t)a.m - lo);
+  }
+  __syncthreads();
+  const uint32_t j0 = s_j0, W = s_w;
+  for (uint32_t k = t; k < W; k += 256) {
+    s_off[k] = a.offs[j0 + k];
+    s_rec[k] = a.order[j0 + k];
+  }
+  __syncthreads();
+  uint64_t o = o0 + (uint64_t)t * EX_PT;
+  if (o >= n) return;
+  // first record of this thread: last k with s_off[k] <= o
+  uint32_t lo = 0, hi = W;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (s_off[mid] <= o) lo = mid; else hi = mid;
+  }
+  uint32_t k = lo;
+  uint32_t rec = 0xffffffffu, x0 = 0, y0 = 0, wdt = 1, tb = 0, tx = 0;
+  for (int e = 0; e < EX_PT; ++e, ++o) {
+    if (o >= n) break;
+    while (k + 1 < W && s_off[k + 1] <= o) ++k;
+    if (s_rec[k] != rec) {
+      rec = s_rec[k];
+      const uint64_t rm = rec < (uint64_t)a.m ? rec : 0;
+      const uint2 r = reinterpret_cast<const uint2*>(a.rect)[rm];
+      x0 = r.x & 0xffffu;
+      y0 = r.x >> 16;
+      wdt = max(1u, (r.y & 0xffffu) - x0);
+      const sgs_camera& cam = a.cams[rm / (uint64_t)a.n];
+      tb = (uint32_t)cam.tile_base;
+      tx = (uint32_t)cam.tiles_x;
+    }
+    const uint32_t q = (uint32_t)(o - s_off[k]);
+    const uint32_t y = y0 + q / wdt, x = x0 + q % wdt;
+    a.keys32[o] = tb + y * tx + x;
+    a.vals[o] = rec;
+  }
 }
 
 // 64-bit keys from sorted tile keys and the record depths (mode 1, optional).
@@ -334,47 +392,54 @@ __global__ void __launch_bounds__(256) k_tile_ranges(const K* __restrict__ keys,
 // ------------------------------------------------------------------ host side
 static inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+static int rs_passes(int bits) { return (bits + 7) / 8; }
+static uint64_t rs_blocks(uint64_t cap) { return std::max<uint64_t>(1, cdiv(cap, RS_TILE)); }
 
-struct RsScratch {
-  uint32_t* hist;
-  uint32_t* part;
-};
-
-static uint32_t rs_groups(uint64_t rows, uint32_t* group) {
-  uint32_t g = (uint32_t)std::max<uint64_t>(64, cdiv(rows, 512));
-  *group = g;
-  return (uint32_t)std::max<uint64_t>(1, cdiv(rows, g));
+// Scratch of one sort of up to `cap` keys, laid out contiguously so that one
+// fill zeroes it: digit histograms [8][256] u32, look-back status words
+// [8][blocks][256] u64, then block counters [8] and an error word.
+static size_t rs_hist_words() { return (size_t)RS_MAX_PASSES * 256; }
+static size_t rs_status_words(uint64_t cap) { return (size_t)RS_MAX_PASSES * rs_blocks(cap) * 256 * 2; }
+static size_t rs_scratch_bytes(uint64_t cap) {
+  return (rs_hist_words() + rs_status_words(cap) + 64) * 4;
 }
 
-static size_t rs_hist_entries(uint64_t cap) { return std::max<uint64_t>(1, cdiv(cap, RS_TILE)) * 256; }
-// rs_groups never returns more than 512 groups (group >= rows/512), so the
-// partials buffer has a fixed size.
-static size_t rs_part_entries(uint64_t) { return (size_t)512 * 256; }
+struct RsScratch {
+  uint32_t* ghist;
+  uint64_t* status;
+  uint32_t* counters;   // [RS_MAX_PASSES] block counters, error word at [RS_MAX_PASSES]
+};
 
-static int rs_passes(int bits) { return (bits + 7) / 8; }
+static RsScratch rs_carve(char* p, uint64_t cap) {
+  RsScratch s;
+  s.ghist = reinterpret_cast<uint32_t*>(p);
+  s.status = reinterpret_cast<uint64_t*>(p + rs_hist_words() * 4);
+  s.counters = reinterpret_cast<uint32_t*>(p + (rs_hist_words() + rs_status_words(cap)) * 4);
+  return s;
+}
 
-// Sorts (k[src], v[src]) by bits [0, bits) in rs_passes(bits) passes,
+// Sorts (k[src], v[src]) by bits [0, bits), one kernel per 8-bit pass,
 // alternating buffers; the result is in buffer (src + passes) % 2.
 template <typename K>
 static sgs_status radix_sort(K* kb[2], uint32_t* vb[2], int src, const uint32_t* n_dev,
                              uint32_t n_host, uint64_t cap, int bits, RsScratch sc, hipStream_t s) {
-  const uint64_t rows = std::max<uint64_t>(1, cdiv(cap, RS_TILE));
-  uint32_t group;
-  const uint32_t groups = rs_groups(rows, &group);
+  const uint64_t blocks = rs_blocks(cap);
+  const int passes = rs_passes(bits);
+  // zero the histograms and the status words of the passes used
+  const uint64_t zw = rs_hist_words() + (uint64_t)passes * blocks * 256 * 2;
+  k_fill_u32<<<(unsigned)cdiv(zw, 256), 256, 0, s>>>(sc.ghist, zw, 0u);
+  SGS_LAUNCH_CHECK();
+  k_fill_u32<<<1, 256, 0, s>>>(sc.counters, 64, 0u);
+  SGS_LAUNCH_CHECK();
+  k_os_hist<K><<<(unsigned)blocks, RS_T, 0, s>>>(kb[src], n_dev, n_host, (uint32_t)cap, bits, sc.ghist);
+  SGS_LAUNCH_CHECK();
   int cur = src;
-  for (int shift = 0; shift < bits; shift += 8) {
-    const int nb = std::min(8, bits - shift);
-    const uint32_t mask = (1u << nb) - 1u;
-    k_rs_upsweep<K><<<(unsigned)rows, RS_T, 0, s>>>(kb[cur], n_dev, n_host, (uint32_t)cap, shift, mask, nb, sc.hist);
-    SGS_LAUNCH_CHECK();
-    k_rs_scan_a<<<groups, 256, 0, s>>>(sc.hist, (uint32_t)rows, group, sc.part);
-    SGS_LAUNCH_CHECK();
-    k_rs_scan_b<<<1, 256, 0, s>>>(sc.part, groups);
-    SGS_LAUNCH_CHECK();
-    k_rs_scan_c<<<groups, 256, 0, s>>>(sc.hist, (uint32_t)rows, group, sc.part);
-    SGS_LAUNCH_CHECK();
-    k_rs_downsweep<K><<<(unsigned)rows, RS_T, 0, s>>>(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n_dev,
-                                                      n_host, (uint32_t)cap, shift, mask, nb, sc.hist);
+  for (int p = 0; p < passes; ++p) {
+    const int nb = std::min(8, bits - 8 * p);
+    k_os_pass<K><<<(unsigned)blocks, RS_T, 0, s>>>(
+        kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n_dev, n_host, (uint32_t)cap, 8 * p, nb,
+        sc.ghist + p * 256, sc.status + (size_t)p * blocks * 256, sc.counters + p,
+        sc.counters + RS_MAX_PASSES);
     SGS_LAUNCH_CHECK();
     cur ^= 1;
   }
@@ -388,14 +453,15 @@ static int tile_bits(int64_t total_tiles) {
 }
 
 size_t bin_sort_scratch_bytes(int64_t m, int64_t cap, int64_t total_tiles, int mode) {
-  size_t bytes = 0;
+  (void)total_tiles;
   const uint64_t rs_cap = std::max<uint64_t>((uint64_t)cap, mode == 1 ? (uint64_t)m : 0);
-  bytes += align_up(rs_hist_entries(rs_cap) * 4) + align_up(rs_part_entries(rs_cap) * 4);
+  size_t bytes = align_up(rs_scratch_bytes(rs_cap));
   if (mode == 0) {
     bytes += align_up((size_t)cap * 8) + align_up((size_t)cap * 4);
   } else {
     bytes += 4 * align_up((size_t)m * 4);                    // depth keys/vals x2
     bytes += align_up((cdiv(m, 256) + 1) * 4);               // sorted block offsets
+    bytes += align_up((size_t)m * 4);                        // per-record offsets
     bytes += 2 * align_up((size_t)cap * 4) + align_up((size_t)cap * 4);  // tile keys x2, vals alt
   }
   return bytes + 256;
@@ -409,14 +475,11 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   auto take = [&](size_t bytes) { char* r = p; p += align_up(bytes); return r; };
   const int mode = opt->sort_mode;
   const uint64_t rs_cap = std::max<uint64_t>((uint64_t)cap, mode == 1 ? (uint64_t)m : 0);
-  RsScratch sc;
-  sc.hist = reinterpret_cast<uint32_t*>(take(rs_hist_entries(rs_cap) * 4));
-  sc.part = reinterpret_cast<uint32_t*>(take(rs_part_entries(rs_cap) * 4));
+  RsScratch sc = rs_carve(take(rs_scratch_bytes(rs_cap)), rs_cap);
   const int tb = tile_bits(total_tiles);
-  // ranges start empty
   k_fill_u32<<<(unsigned)cdiv(2 * total_tiles, 256), 256, 0, s>>>(ranges, 2 * (uint64_t)total_tiles, 0u);
   SGS_LAUNCH_CHECK();
-  DupArgs a;
+  DupArgs a = {};
   a.rect = g->rect;
   a.tiles = g->tiles;
   a.depth = g->depth;
@@ -460,6 +523,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   uint32_t* dv[2] = {reinterpret_cast<uint32_t*>(take((size_t)m * 4)), reinterpret_cast<uint32_t*>(take((size_t)m * 4))};
   const uint64_t nbs = cdiv(m, 256);
   uint32_t* sbo = reinterpret_cast<uint32_t*>(take((nbs + 1) * 4));
+  uint32_t* offs = reinterpret_cast<uint32_t*>(take((size_t)m * 4));
   uint32_t* tk[2] = {reinterpret_cast<uint32_t*>(take((size_t)cap * 4)), reinterpret_cast<uint32_t*>(take((size_t)cap * 4))};
   uint32_t* valt = reinterpret_cast<uint32_t*>(take((size_t)cap * 4));
   if (m == 0) {
@@ -476,17 +540,18 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   SGS_LAUNCH_CHECK();
   st = launch_scan_blocks(sbo, sbo, (int64_t)nbs, s);
   if (st != SGS_OK) return st;
+  k_sorted_offsets<<<(unsigned)nbs, 256, 0, s>>>(order, g->tiles, m, sbo, (int64_t)nbs, offs, n_inst);
+  SGS_LAUNCH_CHECK();
   const int passes = rs_passes(tb);
   const int src = passes & 1;
   uint32_t* vb[2] = {vals, valt};
   a.order = order;
-  a.block_off = sbo;
-  a.nb_total = (int32_t)nbs;
+  a.offs = offs;
   a.keys32 = tk[src];
   a.vals = vb[src];
-  k_duplicate32<<<(unsigned)nbs, 256, 0, s>>>(a);
-  SGS_LAUNCH_CHECK();
   if (cap > 0) {
+    k_expand32<<<(unsigned)cdiv(cap, EX_TILE), 256, 0, s>>>(a);
+    SGS_LAUNCH_CHECK();
     st = radix_sort<uint32_t>(tk, vb, src, n_inst, 0, (uint64_t)cap, tb, sc, s);
     if (st != SGS_OK) return st;
     k_tile_ranges<uint32_t><<<(unsigned)cdiv(cap, 256), 256, 0, s>>>(tk[0], 0, n_inst, (uint32_t)cap,
