@@ -87,16 +87,11 @@ __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, co
   __syncthreads();
   const uint32_t n = count_of(n_dev, n_host, cap);
   const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
-  const uint64_t lt = lanemask_lt();
   for (int i = 0; i < RS_IPT; ++i) {
     const uint64_t idx = base + (uint64_t)i * RS_T + t;
-    const bool valid = idx < n;
-    const K key = valid ? keys[idx] : (K)0;
-    for (int p = 0; p < passes; ++p) {
-      const int nb = min(8, bits - 8 * p);
-      const uint32_t d = digit_of<K>(key, 8 * p, (1u << nb) - 1u);
-      const uint64_t peers = match_digit(d, valid, nb);
-      if (valid && (peers & lt) == 0) atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
+    if (idx < n) {
+      const K key = keys[idx];
+      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][digit_of<K>(key, 8 * p, 0xffu)], 1u);
     }
   }
   __syncthreads();
@@ -380,13 +375,17 @@ __global__ void __launch_bounds__(256) k_tile_ranges(const K* __restrict__ keys,
                                                      const uint32_t* n_dev, uint32_t cap,
                                                      uint32_t total_tiles,
                                                      uint32_t* __restrict__ ranges) {
+  // each boundary between two different tiles ends one range and starts the next
   const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   const uint32_t n = count_of(n_dev, 0, cap);
   if (i >= n) return;
   const uint32_t t = (uint32_t)(keys[i] >> shift);
-  if (t >= total_tiles) return;
-  if (i == 0 || (uint32_t)(keys[i - 1] >> shift) != t) ranges[2 * (uint64_t)t] = (uint32_t)i;
-  if (i + 1 == n || (uint32_t)(keys[i + 1] >> shift) != t) ranges[2 * (uint64_t)t + 1] = (uint32_t)(i + 1);
+  if (i == 0 && t < total_tiles) ranges[2 * (uint64_t)t] = 0u;
+  const uint32_t tn = i + 1 < n ? (uint32_t)(keys[i + 1] >> shift) : 0xffffffffu;
+  if (tn != t) {
+    if (t < total_tiles) ranges[2 * (uint64_t)t + 1] = (uint32_t)(i + 1);
+    if (tn < total_tiles) ranges[2 * (uint64_t)tn] = (uint32_t)(i + 1);
+  }
 }
 
 // ------------------------------------------------------------------ host side

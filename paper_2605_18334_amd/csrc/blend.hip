@@ -1,11 +1,15 @@
 // Per-tile compositing of projected skew Gaussians, forward and backward.
 //
 // One workgroup per screen tile (TW x TH pixels, one pixel per thread, each
-// wave64 owns an 8x8 block so that a wave's pixels are compact and its
-// per-pair skips tend to be uniform).  The tile's sorted list is walked in
-// batches of B records staged in LDS; every lane of a wave reads the same
-// record at the same time, so per-record branches (symmetric record: no
-// erf) never diverge.
+// wave64 owns an 8x8 block of the tile).  The tile's sorted list is walked in
+// batches of B records staged in LDS.  When a batch is staged, each record
+// gets a mask of the 8x8 wave blocks its evaluation ellipse (the region where
+// the pair is not skipped by the exponent test) can touch, and each wave gets
+// its own compacted, order-preserving list of record indices; a wave only
+// visits its own list.  This is exact: a record missing from a wave's list
+// would have failed the skip test on every lane of that wave.  All lanes of a
+// wave read the same record at the same time, so per-record branches (a
+// symmetric record skips erf) never diverge.
 //
 // Forward (Alg. 1): alpha = min(alpha_max, d G' (1 + erf z)) per pair, pairs
 // below alpha_min skipped, a pixel stops before T would drop below t_min,
@@ -49,7 +53,8 @@ struct BlendArgs {
 
 struct TileSetup {
   int tile, view;
-  int px, py;
+  int px, py;      // this thread's pixel
+  int ox, oy;      // tile origin in pixels
   bool inside;
   const sgs_camera* cam;
 };
@@ -63,20 +68,100 @@ __device__ __forceinline__ bool setup_tile(const BlendArgs& a, TileSetup& s) {
   const int lt = s.tile - s.cam->tile_base;
   const int tx = lt % s.cam->tiles_x, ty = lt / s.cam->tiles_x;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  s.px = tx * TW + (w % (TW / 8)) * 8 + (l & 7);
-  s.py = ty * TH + (w / (TW / 8)) * 8 + (l >> 3);
+  s.ox = tx * TW;
+  s.oy = ty * TH;
+  s.px = s.ox + (w % (TW / 8)) * 8 + (l & 7);
+  s.py = s.oy + (w / (TW / 8)) * 8 + (l >> 3);
   s.inside = s.px < s.cam->width && s.py < s.cam->height;
   return true;
 }
 
+// Staged batch of B records and the per-wave compacted lists.
+template <int TW, int TH, int B, bool ENH>
+struct Stage {
+  static constexpr int NT = TW * TH;
+  static constexpr int NW = NT / 64;
+  static constexpr int NG = B / 64;   // 64-record groups of the batch
+  float4 r0[B], r1[B], r2[B];
+  float4 r3[ENH ? B : 1];
+  uint32_t rid[B];
+  uint8_t mask[B];
+  uint16_t cnt[NW][NG];
+  uint16_t list[NW][B];
+  uint16_t n[NW];
+};
+
+// Loads records [idx0, idx0 + cnt) of the tile list into the stage and builds
+// the per-wave lists.  Every thread of the block must call it.
+template <int TW, int TH, int B, bool ENH>
+__device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup& ts, uint32_t idx0,
+                                            int cnt, Stage<TW, TH, B, ENH>& S) {
+  using St = Stage<TW, TH, B, ENH>;
+  const int t = threadIdx.x, lane = t & 63;
+  const uint64_t lt = lanemask_lt();
+  for (int k = t; k < B; k += St::NT) {
+    uint32_t msk = 0;
+    if (k < cnt) {
+      uint32_t m = a.vals[idx0 + k];
+      if (m >= a.m) m = 0;
+      const float4 q0 = a.rec0[m], q1 = a.rec1[m], q2 = a.rec2[m];
+      S.rid[k] = m;
+      S.r0[k] = q0;
+      S.r1[k] = q1;
+      S.r2[k] = q2;
+      if (ENH) S.r3[k] = a.rec3[m];
+      // AABB of the ellipse delta^T Q delta <= -2 log_thr (pairs outside are skipped)
+      const float det = q0.z * q1.x - q0.w * q0.w;
+      const float R2 = -2.0f * q2.w;
+      const float ex = sqrtf(R2 * q1.x / det) * 1.001f + 0.01f;
+      const float ey = sqrtf(R2 * q0.z / det) * 1.001f + 0.01f;
+      if (!(det > 0.0f) || !(ex < 1e30f) || !(ey < 1e30f)) {
+        msk = (1u << St::NW) - 1u;
+      } else {
+#pragma unroll
+        for (int w = 0; w < St::NW; ++w) {
+          const float lx = (float)(ts.ox + (w % (TW / 8)) * 8) + 0.5f;
+          const float ly = (float)(ts.oy + (w / (TW / 8)) * 8) + 0.5f;
+          if (q0.x + ex >= lx && q0.x - ex <= lx + 7.0f && q0.y + ey >= ly && q0.y - ey <= ly + 7.0f)
+            msk |= 1u << w;
+        }
+      }
+    }
+    S.mask[k] = (uint8_t)msk;
+#pragma unroll
+    for (int w = 0; w < St::NW; ++w) {
+      const uint64_t bal = __ballot((msk >> w) & 1u);
+      if (lane == 0) S.cnt[w][k >> 6] = (uint16_t)__popcll(bal);
+    }
+  }
+  __syncthreads();
+  for (int k = t; k < B; k += St::NT) {
+    const uint32_t msk = S.mask[k];
+#pragma unroll
+    for (int w = 0; w < St::NW; ++w) {
+      const bool bit = (msk >> w) & 1u;
+      const uint64_t bal = __ballot(bit);
+      if (bit) {
+        uint32_t off = (uint32_t)__popcll(bal & lt);
+        for (int g = 0; g < (k >> 6); ++g) off += S.cnt[w][g];
+        S.list[w][off] = (uint16_t)k;
+      }
+    }
+  }
+  if (t < St::NW) {
+    uint32_t s = 0;
+    for (int g = 0; g < St::NG; ++g) s += S.cnt[t][g];
+    S.n[t] = (uint16_t)s;
+  }
+  __syncthreads();
+}
+
 template <int TW, int TH, int B, bool ENH>
 __global__ void __launch_bounds__(TW * TH) k_blend_fwd(BlendArgs a) {
-  constexpr int NT = TW * TH;
-  __shared__ float4 s0[B], s1[B], s2[B];
-  __shared__ float4 s3[ENH ? B : 1];
+  __shared__ Stage<TW, TH, B, ENH> S;
   TileSetup ts;
   if (!setup_tile<TW, TH>(a, ts)) return;
-  const int t = threadIdx.x;
+  const int w = threadIdx.x >> 6;
   const float fx = (float)ts.px + 0.5f, fy = (float)ts.py + 0.5f;
   uint2 rg = a.ranges[ts.tile];
   rg.y = min(rg.y, a.n_vals);
@@ -86,34 +171,25 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd(BlendArgs a) {
   bool done = !ts.inside;
   for (uint32_t base = rg.x; base < rg.y; base += B) {
     if (__syncthreads_and(done)) break;
-    for (int k = t; k < B; k += NT) {
-      const uint32_t idx = base + k;
-      if (idx < rg.y) {
-        uint32_t m = a.vals[idx];
-        if (m >= a.m) m = 0;
-        s0[k] = a.rec0[m];
-        s1[k] = a.rec1[m];
-        s2[k] = a.rec2[m];
-        if (ENH) s3[k] = a.rec3[m];
-      }
-    }
-    __syncthreads();
     const int cnt = (int)min((uint32_t)B, rg.y - base);
-    for (int j = 0; j < cnt; ++j) {
+    stage_batch<TW, TH, B, ENH>(a, ts, base, cnt, S);
+    const int nw = S.n[w];
+    for (int i = 0; i < nw; ++i) {
       if (done) break;
-      const float4 r0 = s0[j];
-      const float4 r1 = s1[j];
+      const int j = S.list[w][i];
+      const float4 r0 = S.r0[j];
+      const float4 r1 = S.r1[j];
       const float dx = fx - r0.x, dy = fy - r0.y;
       const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
-      const float4 r2 = s2[j];
+      const float4 r2 = S.r2[j];
       if (power < r2.w) continue;
       Pair p;
       pair_eval(power, r1.w, r1.y, r1.z, dx, dy, (r1.y != 0.0f) || (r1.z != 0.0f), p);
       float at = p.at;
       if (ENH) {
-        const float4 r3 = s3[j];
-        float u, eu;
-        at *= enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, u, eu);
+        const float4 r3 = S.r3[j];
+        float eu, ee;
+        at *= enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
       }
       const float alpha = fminf(a.alpha_max, at);
       if (alpha < a.alpha_min) continue;
@@ -146,14 +222,12 @@ template <int TW, int TH, int B, bool ENH>
 __global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
   constexpr int NT = TW * TH;
   constexpr int NG = ENH ? 15 : 11;   // values per record: see the flush below
-  __shared__ float4 s0[B], s1[B], s2[B];
-  __shared__ float4 s3[ENH ? B : 1];
-  __shared__ uint32_t sm[B];
+  __shared__ Stage<TW, TH, B, ENH> S;
   __shared__ float sg[NG][B];
   __shared__ uint32_t smax;
   TileSetup ts;
   if (!setup_tile<TW, TH>(a, ts)) return;
-  const int t = threadIdx.x, lane = t & 63;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const float fx = (float)ts.px + 0.5f, fy = (float)ts.py + 0.5f;
   uint2 rg = a.ranges[ts.tile];
   rg.y = min(rg.y, a.n_vals);
@@ -163,7 +237,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
   if (ts.inside) {
     const int64_t pix = ts.cam->pix_base + (int64_t)ts.py * ts.cam->width + ts.px;
     T = a.cT[pix];
-    last = a.clast[pix];
+    last = min(a.clast[pix], rg.y - rg.x);
     g0 = a.dL[pix];
     g1 = a.dL[a.P + pix];
     g2 = a.dL[2 * a.P + pix];
@@ -180,37 +254,30 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
     const int start = end > B ? end - B : 0;
     const int cnt = end - start;
     __syncthreads();
-    for (int k = t; k < cnt; k += NT) {
-      const uint32_t idx = rg.x + start + k;
-      uint32_t m = idx < rg.y ? a.vals[idx] : 0u;
-      if (m >= a.m) m = 0;
-      sm[k] = m;
-      s0[k] = a.rec0[m];
-      s1[k] = a.rec1[m];
-      s2[k] = a.rec2[m];
-      if (ENH) s3[k] = a.rec3[m];
-    }
+    stage_batch<TW, TH, B, ENH>(a, ts, rg.x + start, cnt, S);
     for (int k = t; k < NG * B; k += NT) (&sg[0][0])[k] = 0.0f;
     __syncthreads();
-    for (int j = cnt - 1; j >= 0; --j) {
+    const int nw = S.n[w];
+    for (int i = nw - 1; i >= 0; --i) {
+      const int j = S.list[w][i];
       float gv[NG];
 #pragma unroll
       for (int q = 0; q < NG; ++q) gv[q] = 0.0f;
       bool hit = false;
       if ((uint32_t)(start + j) < last) {
-        const float4 r0 = s0[j];
-        const float4 r1 = s1[j];
+        const float4 r0 = S.r0[j];
+        const float4 r1 = S.r1[j];
         const float dx = fx - r0.x, dy = fy - r0.y;
         const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
-        const float4 r2 = s2[j];
+        const float4 r2 = S.r2[j];
         if (power >= r2.w) {
           Pair p;
           pair_eval(power, r1.w, r1.y, r1.z, dx, dy, (r1.y != 0.0f) || (r1.z != 0.0f), p);
-          float at = p.at, o = 1.0f, u = 0.0f, eu = 0.0f;
+          float at = p.at, o = 1.0f, eu = 0.0f, ee = 1.0f;
           float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
           if (ENH) {
-            r3 = s3[j];
-            o = enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, u, eu);
+            r3 = S.r3[j];
+            o = enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
             at *= o;
           }
           const float alpha = fminf(a.alpha_max, at);
@@ -225,8 +292,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
             dLda -= Tfinal / (1.0f - alpha) * bgdot;
             if (at <= a.alpha_max) {
               const float dd = r1.w * o;              // d, times o(delta) with enhanced opacity
-              const float ez = __expf(-p.z * p.z);    // e^{-z^2}, 1 when z = 0
-              const float s2pi = SGS_SQRT_2_OVER_PI * ez;
+              const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
               const float common = dLda * dd * p.G;
               const float qa = fmaf(r0.z, dx, r0.w * dy), qc = fmaf(r0.w, dx, r1.x * dy);
               gv[0] = common * (qa * p.E - s2pi * r1.y);
@@ -239,7 +305,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
               gv[7] = dLda * p.G * p.E * o;
               if (ENH) {
                 const float base = p.at;             // rho G' (1 + erf z)
-                const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * __expf(-u * u);
+                const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
                 gv[0] -= dLda * base * dodw * r3.z;
                 gv[1] -= dLda * base * dodw * r3.w;
                 gv[11] = dLda * base * 0.5f * (1.0f + eu);
@@ -272,7 +338,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
         any |= v[q] != 0.0f;
       }
       if (!any) continue;
-      const uint32_t m = sm[k];
+      const uint32_t m = S.rid[k];
       float* p0 = reinterpret_cast<float*>(a.g0 + m);
       float* p1 = reinterpret_cast<float*>(a.g1 + m);
       float* p2 = reinterpret_cast<float*>(a.g2 + m);

@@ -35,8 +35,24 @@ struct Pair {
   float G;      // G'
   float z;      // skew argument
   float E;      // 1 + erf(z)
+  float ez;     // exp(-z^2) (1 when z = 0)
   float at;     // unclamped alpha (without the enhanced-opacity factor)
 };
+
+// 1 + erf(z) = erfc(-z) with erfc(x) ~ t P(t) exp(-x^2), t = 1/(1 + p x),
+// x >= 0 (Abramowitz & Stegun 1964, formula 7.1.26, |error| <= 1.5e-7), and
+// erfc(-x) = 2 - erfc(x).  Also returns exp(-z^2), which the backward needs.
+__device__ __forceinline__ float one_plus_erf(float z, float& ez) {
+  const float x = fabsf(z);
+  const float t = __frcp_rn(fmaf(0.3275911f, x, 1.0f));
+  float poly = fmaf(1.061405429f, t, -1.453152027f);
+  poly = fmaf(poly, t, 1.421413741f);
+  poly = fmaf(poly, t, -0.284496736f);
+  poly = fmaf(poly, t, 0.254829592f);
+  ez = __expf(-x * x);
+  const float q = (poly * t) * ez;      // erfc(|z|)
+  return z < 0.0f ? q : 2.0f - q;
+}
 
 __device__ __forceinline__ float pair_power(float a, float b, float c, float dx, float dy) {
   float q = fmaf(a * dx, dx, fmaf(c * dy, dy, (2.0f * b) * (dx * dy)));
@@ -49,20 +65,22 @@ __device__ __forceinline__ void pair_eval(float power, float d, float bx, float 
   p.G = __expf(power);
   if (skew) {
     p.z = fmaf(bx, dx, by * dy) * SGS_INV_SQRT2;
-    p.E = 1.0f + erff(p.z);
+    p.E = one_plus_erf(p.z, p.ez);
   } else {
     p.z = 0.0f;
     p.E = 1.0f;
+    p.ez = 1.0f;
   }
   p.at = (d * p.G) * p.E;
 }
 
 // Enhanced opacity factor o(delta) = ((o1+o2) + (o1-o2) erf(w.delta/sqrt2))/2
 // (Sec. "3D Skew Gaussian Rasterization and Splatting").
+// Returns o(delta); erfu = erf(u), eu = exp(-u^2), u = w.delta/sqrt 2.
 __device__ __forceinline__ float enh_opacity(float o1, float o2, float wx, float wy, float dx,
-                                             float dy, float& u, float& erfu) {
-  u = fmaf(wx, dx, wy * dy) * SGS_INV_SQRT2;
-  erfu = erff(u);
+                                             float dy, float& erfu, float& eu) {
+  const float u = fmaf(wx, dx, wy * dy) * SGS_INV_SQRT2;
+  erfu = one_plus_erf(u, eu) - 1.0f;
   return 0.5f * fmaf(o1 - o2, erfu, o1 + o2);
 }
 

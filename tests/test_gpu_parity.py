@@ -219,6 +219,27 @@ def test_enhanced_opacity_image_matches_oracle():
     _check_image(fr, O.render(sc, pose))
 
 
+def test_single_skewed_gaussian_matches_closed_form_tightly():
+    """One strongly skewed Gaussian in front of the camera: the skew argument
+    z spans about +-4 over the footprint, so the device 1 + erf(z) is checked
+    against the FP64 oracle over its whole range (bound 1.5e-7 for the
+    Abramowitz-Stegun formula, plus float32 rounding)."""
+    pose = S.Pose(np.diag([1.0, -1.0, -1.0, 1.0]), 64, 64, 60.0, 0.2)
+    q = np.array([[1.0], [0.0], [0.0], [0.0]], np.float32)
+    sc = S.Scene(np.array([[0.05], [-0.02], [5.0]], np.float32),
+                 np.array([[math.log(0.12)], [math.log(0.09)], [math.log(0.1)]], np.float32), q,
+                 np.array([[25.0], [-14.0], [3.0]], np.float32), np.array([-0.5], np.float32),
+                 np.array([[[0.4]], [[0.1]], [[-0.3]]], np.float32).reshape(1, 3, 1), 0)
+    fr = _render(sc, pose)
+    ref = O.render(sc, pose)
+    img = _np(fr.image(0)).reshape(3, -1).T
+    ok = ~ref.ambiguous
+    assert ok.mean() > 0.99
+    assert np.abs(img - ref.color)[ok].max() <= 2e-6
+    pr = O.project_numpy(sc, pose)
+    assert np.abs(pr["beta2d"][0]).max() * 12 > 4 * math.sqrt(2)   # |z| reaches ~4 in the footprint
+
+
 def test_ragged_image_and_background():
     sc = S.blobs_scene(17, 800, 2)
     pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 97, 45, 60.0, 0.2, (0.2, 0.5, 0.9))
