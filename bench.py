@@ -139,6 +139,98 @@ def fwd_bwd(steps: int, warmup: int):
                                    "L1 loss vs a separately seeded 1M target"}}
 
 
+def batched(steps: int, warmup: int):
+    """16 views of mixed resolution of a 3M-Gaussian scene: one HIP-graph
+    launch of the autotuned batch vs 16 sequential single-view renders."""
+    import torch
+    import paper_2605_18334_amd as P
+    from paper_2605_18334_amd.batch import BatchRenderer, autotune
+    import sgs_synth as S
+    sc, poses = S.batch_config()
+    gs = P.GaussianSet.from_scene(sc)
+    del sc
+    cfg, timings = autotune(gs, poses, reps=2, log=log)
+    br = BatchRenderer(gs, poses, cfg)
+    br.capture()
+    for _ in range(warmup):
+        br.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        br.replay()
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) * 1e3 / steps
+    assert not br.overflowed()
+    o = P.default_options()
+    singles = [P.Renderer(gs, P.CameraBatch.from_poses([p], o), o) for p in poses]
+    for _ in range(warmup):
+        for r in singles:
+            r.forward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for r in singles:
+            r.forward()
+    torch.cuda.synchronize()
+    ms_s = (time.perf_counter() - t0) * 1e3 / steps
+    same = all(torch.equal(br.image(v), singles[v].image(0)) for v in range(len(poses)))
+    px = br.total_pixels
+    out = {"metric": "Mpix/s render fwd, 16-view batch", "value": px / (ms_b / 1e3) / 1e6, "unit": "Mpix/s",
+           "ms_batched": ms_b, "ms_sequential": ms_s, "speedup_vs_sequential": ms_s / ms_b,
+           "sequential_mpix_s": px / (ms_s / 1e3) / 1e6, "bit_identical_to_single_views": same,
+           "n_inst": br.n_inst(), "tuned": {k: v for k, v in cfg.__dict__.items()},
+           "config": {"workload": "3M skew Gaussians (4-blob generator, SH0), 16 spline poses at "
+                                  "640x480/1280x720/1600x1064/1920x1080 (4 each)"}}
+    del br, singles
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving(duration_s: float, rates):
+    """Poisson request stream against resident 5M skew + 2M symmetric SH3
+    scenes, continuous batching vs FIFO one-at-a-time."""
+    import torch
+    import paper_2605_18334_amd as P
+    from paper_2605_18334_amd.serve import GpuBackend, RenderServer, Request
+    import sgs_synth as S
+    scA, scB = S.serve_scenes()
+    be = GpuBackend({"A": scA, "B": scB})
+    del scA, scB
+    res = {}
+    for name, rate, mb, mi in [(f"batched@{r}", r, 8, 2) for r in rates] + [(f"fifo@{rates[0]}", rates[0], 1, 1)]:
+        rng = np.random.default_rng(8)
+        srv = RenderServer(be, budget_bytes=64 << 30, max_batch=mb, max_inflight=mi)
+        # warm the backend (first launch allocates)
+        srv.start()
+        srv.submit(Request("A", S.random_request_pose(rng))).result(timeout=120)
+        srv.submit(Request("B", S.random_request_pose(rng))).result(timeout=120)
+        srv.results.clear()
+        t0 = time.perf_counter()
+        t = 0.0
+        n = 0
+        pix = 0
+        while t < duration_s:
+            t += rng.exponential(1.0 / rate)
+            now = time.perf_counter() - t0
+            if t > now:
+                time.sleep(t - now)
+            pose = S.random_request_pose(rng)
+            pix += pose.width * pose.height
+            srv.submit(Request("AB"[int(rng.integers(0, 2))], pose, t_arrival=time.perf_counter()))
+            n += 1
+        srv.stop(drain=True, timeout=120)
+        st = srv.stats()
+        st["offered_req_s"] = rate
+        st["mpix_s"] = pix / max(st.get("span_s", 1e-9), 1e-9) / 1e6
+        res[name] = st
+        log(f"serving {name}: {st}")
+    return {"metric": "p50/p99 frame latency (served)", "unit": "ms",
+            "config": {"workload": "resident 5M skew + 2M zero-skew Gaussians (32-cluster generator, SH3); "
+                                   "Poisson arrivals; poses 50% orbit / 50% free flight; "
+                                   "640x480/1280x720/1920x1080; images copied to host"},
+            "runs": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,7 +239,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--only", choices=["fwd", "fwdbwd"], default=None,
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--only", choices=["fwd", "fwdbwd", "batch", "serve"], default=None,
                     help="run one workload only (for profiler runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
@@ -172,6 +267,12 @@ def main():
         del src, dst
     if args.only == "fwdbwd":
         print(json.dumps(fwd_bwd(max(3, args.steps // 2), 2)), flush=True)
+        return
+    if args.only == "batch":
+        print(json.dumps(batched(max(3, args.steps // 4), 1)), flush=True)
+        return
+    if args.only == "serve":
+        print(json.dumps(serving(args.serve_seconds, [60, 240])), flush=True)
         return
     sc, pose = S.clustered_config()
     opt = P.default_options()
@@ -220,6 +321,12 @@ def main():
         torch.cuda.empty_cache()
         out["fwd_bwd"] = fwd_bwd(max(3, args.steps // 2), 2)
         log(f"fwd+bwd {out['fwd_bwd']}")
+    if not args.no_batch and args.only is None:
+        torch.cuda.empty_cache()
+        out["batched"] = batched(max(3, args.steps // 4), 1)
+    if not args.no_serve and args.only is None:
+        torch.cuda.empty_cache()
+        out["served"] = serving(args.serve_seconds, [60, 240])
     if not args.no_cpu and args.only is None:
         out["cpu_baseline"] = cpu_baseline(sc, pose, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -136,6 +136,20 @@ typedef struct {
                               (view-major); the last entry is the total      */
 } sgs_geom;
 
+/* Optional tile scheduling for the blend kernels (device pointers).
+ *  tile_order    [total_tiles] u32: written by sgs_bin_sort when non-NULL, the
+ *                tile ids ordered by decreasing list length (longest first, so
+ *                the slowest tiles start first); read by the blends, which
+ *                then take tiles in this order.
+ *  work_counter  [1] u32: when non-NULL the blends run persistent workgroups
+ *                (as many as fit on the device) that take the next tile from
+ *                this counter until all tiles are done; the call resets it on
+ *                the stream before the kernel.  NULL: one workgroup per tile. */
+typedef struct {
+  uint32_t* tile_order;
+  uint32_t* work_counter;
+} sgs_schedule;
+
 /* Accumulated (+=) gradient of the loss w.r.t. the projected records, same
  * [R][M][4] layout as sgs_geom.rec (plane 2 .w unused).  Device pointer. */
 typedef struct {
@@ -147,7 +161,7 @@ void sgs_default_options(sgs_options* opt);
 
 /* sizeof of the ABI structs, for bindings to check their mirrors:
  * 0 sgs_params, 1 sgs_params_grad, 2 sgs_camera, 3 sgs_options, 4 sgs_geom,
- * 5 sgs_geom_grad; 0 for any other value. */
+ * 5 sgs_geom_grad, 6 sgs_schedule; 0 for any other value. */
 size_t sgs_struct_size(int32_t which);
 const char* sgs_status_string(sgs_status s);
 
@@ -195,14 +209,15 @@ sgs_status sgs_preprocess(const sgs_params* p, const sgs_camera* cams_host,
  *  n_inst_dev    [1] u32 device: receives the instance count.  Instances past
  *                inst_capacity are dropped; the caller compares the count with
  *                the capacity after the fact (graph-friendly, no host sync).
+ *  sched         optional (NULL): if sched->tile_order is set, it is written.
  *  scratch       device, >= sgs_bin_sort_scratch_bytes(...).
  * EINVAL / ECAPACITY for bad sizes. */
 sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_host,
                         const sgs_camera* cams_dev, int32_t n_views,
                         const sgs_options* opt, int64_t inst_capacity,
                         uint64_t* keys, uint32_t* vals, uint32_t* tile_ranges,
-                        uint32_t* n_inst_dev, void* scratch, size_t scratch_bytes,
-                        void* stream);
+                        uint32_t* n_inst_dev, const sgs_schedule* sched, void* scratch,
+                        size_t scratch_bytes, void* stream);
 
 /* Alg. 1 per pixel: alpha = min(alpha_max, d G'(x) (1 + erf(beta.delta/sqrt2)))
  * (times the enhanced-opacity factor), pairs below alpha_min skipped, stop
@@ -213,7 +228,8 @@ sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_hos
  * including the last contributor, 0 if none), out_count [P] (optional, NULL to
  * skip: number of pairs composited into the pixel). */
 sgs_status sgs_render_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals,
-                          int64_t inst_capacity, const uint32_t* tile_ranges, const sgs_camera* cams_host,
+                          int64_t inst_capacity, const uint32_t* tile_ranges,
+                          const sgs_schedule* sched, const sgs_camera* cams_host,
                           const sgs_camera* cams_dev, int32_t n_views, int32_t enhanced,
                           const sgs_options* opt, float* out_rgb, float* out_T,
                           uint32_t* out_last, uint32_t* out_count, int64_t total_pixels,
@@ -227,7 +243,7 @@ sgs_status sgs_render_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals,
  * g2d must be zeroed by the caller before the call. */
 sgs_status sgs_render_bwd(const sgs_params* p, const sgs_geom* g, int64_t m,
                           const uint32_t* vals, int64_t inst_capacity,
-                          const uint32_t* tile_ranges,
+                          const uint32_t* tile_ranges, const sgs_schedule* sched,
                           const sgs_camera* cams_host, const sgs_camera* cams_dev,
                           int32_t n_views, const sgs_options* opt, const float* out_T,
                           const uint32_t* out_last, const float* dL_drgb,

@@ -48,7 +48,11 @@ class GeomGrad(C.Structure):
     _fields_ = [("rec", P)]
 
 
-STRUCTS = [Params, ParamsGrad, Camera, Options, Geom, GeomGrad]
+class Schedule(C.Structure):
+    _fields_ = [("tile_order", P), ("work_counter", P)]
+
+
+STRUCTS = [Params, ParamsGrad, Camera, Options, Geom, GeomGrad, Schedule]
 
 STATUS = {0: "SGS_OK", 1: "SGS_EINVAL", 2: "SGS_ECAPACITY", 3: "SGS_EHIP", 4: "SGS_EUNSUPPORTED"}
 
@@ -67,12 +71,14 @@ SIGNATURES = {
     "sgs_preprocess": (C.c_int, [C.POINTER(Params), C.POINTER(Camera), P, C.c_int32,
                                  C.POINTER(Options), C.POINTER(Geom), P]),
     "sgs_bin_sort": (C.c_int, [C.POINTER(Geom), C.c_int64, C.POINTER(Camera), P, C.c_int32,
-                               C.POINTER(Options), C.c_int64, P, P, P, P, P, C.c_size_t, P]),
-    "sgs_render_fwd": (C.c_int, [C.POINTER(Geom), C.c_int64, P, C.c_int64, P, C.POINTER(Camera), P, C.c_int32,
-                                 C.c_int32, C.POINTER(Options), P, P, P, P, C.c_int64, P]),
+                               C.POINTER(Options), C.c_int64, P, P, P, P, C.POINTER(Schedule), P,
+                               C.c_size_t, P]),
+    "sgs_render_fwd": (C.c_int, [C.POINTER(Geom), C.c_int64, P, C.c_int64, P, C.POINTER(Schedule),
+                                 C.POINTER(Camera), P, C.c_int32, C.c_int32, C.POINTER(Options), P, P, P,
+                                 P, C.c_int64, P]),
     "sgs_render_bwd": (C.c_int, [C.POINTER(Params), C.POINTER(Geom), C.c_int64, P, C.c_int64, P,
-                                 C.POINTER(Camera), P, C.c_int32, C.POINTER(Options), P, P, P,
-                                 C.c_int64, C.POINTER(GeomGrad), C.POINTER(ParamsGrad), P]),
+                                 C.POINTER(Schedule), C.POINTER(Camera), P, C.c_int32, C.POINTER(Options),
+                                 P, P, P, C.c_int64, C.POINTER(GeomGrad), C.POINTER(ParamsGrad), P]),
 }
 
 _lib = None

@@ -388,6 +388,18 @@ __global__ void __launch_bounds__(256) k_tile_ranges(const K* __restrict__ keys,
   }
 }
 
+// Keys that order tiles by decreasing list length (16 bits, saturating).
+__global__ void __launch_bounds__(256) k_tile_len_keys(const uint32_t* __restrict__ ranges,
+                                                       uint32_t total_tiles,
+                                                       uint32_t* __restrict__ k,
+                                                       uint32_t* __restrict__ v) {
+  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= total_tiles) return;
+  const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+  k[t] = 0xffffu - min(len, 0xffffu);
+  v[t] = t;
+}
+
 // ------------------------------------------------------------------ host side
 static inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -451,10 +463,15 @@ static int tile_bits(int64_t total_tiles) {
   return std::max(b, 1);
 }
 
+static uint64_t rs_capacity(int64_t m, int64_t cap, int64_t total_tiles, int mode) {
+  return std::max<uint64_t>(std::max<uint64_t>((uint64_t)cap, mode == 1 ? (uint64_t)m : 0),
+                            (uint64_t)total_tiles);
+}
+
 size_t bin_sort_scratch_bytes(int64_t m, int64_t cap, int64_t total_tiles, int mode) {
-  (void)total_tiles;
-  const uint64_t rs_cap = std::max<uint64_t>((uint64_t)cap, mode == 1 ? (uint64_t)m : 0);
+  const uint64_t rs_cap = rs_capacity(m, cap, total_tiles, mode);
   size_t bytes = align_up(rs_scratch_bytes(rs_cap));
+  bytes += 3 * align_up((size_t)total_tiles * 4);            // tile-order keys x2, vals alt
   if (mode == 0) {
     bytes += align_up((size_t)cap * 8) + align_up((size_t)cap * 4);
   } else {
@@ -469,12 +486,22 @@ size_t bin_sort_scratch_bytes(int64_t m, int64_t cap, int64_t total_tiles, int m
 sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_camera* cams_dev,
                            int32_t n_views, int64_t total_tiles, const sgs_options* opt,
                            int64_t cap, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
-                           uint32_t* n_inst, void* scratch, hipStream_t s) {
+                           uint32_t* n_inst, uint32_t* tile_order, void* scratch, hipStream_t s) {
   char* p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(scratch) + 255) & ~(uintptr_t)255);
   auto take = [&](size_t bytes) { char* r = p; p += align_up(bytes); return r; };
   const int mode = opt->sort_mode;
-  const uint64_t rs_cap = std::max<uint64_t>((uint64_t)cap, mode == 1 ? (uint64_t)m : 0);
+  const uint64_t rs_cap = rs_capacity(m, cap, total_tiles, mode);
   RsScratch sc = rs_carve(take(rs_scratch_bytes(rs_cap)), rs_cap);
+  uint32_t* ok[2] = {reinterpret_cast<uint32_t*>(take((size_t)total_tiles * 4)),
+                     reinterpret_cast<uint32_t*>(take((size_t)total_tiles * 4))};
+  uint32_t* ov[2] = {tile_order, reinterpret_cast<uint32_t*>(take((size_t)total_tiles * 4))};
+  // tiles by decreasing list length (after the ranges are known)
+  auto order_tiles = [&]() -> sgs_status {
+    if (!tile_order) return SGS_OK;
+    k_tile_len_keys<<<(unsigned)cdiv(total_tiles, 256), 256, 0, s>>>(ranges, (uint32_t)total_tiles, ok[0], ov[0]);
+    SGS_LAUNCH_CHECK();
+    return radix_sort<uint32_t>(ok, ov, 0, nullptr, (uint32_t)total_tiles, (uint64_t)total_tiles, 16, sc, s);
+  };
   const int tb = tile_bits(total_tiles);
   k_fill_u32<<<(unsigned)cdiv(2 * total_tiles, 256), 256, 0, s>>>(ranges, 2 * (uint64_t)total_tiles, 0u);
   SGS_LAUNCH_CHECK();
@@ -515,7 +542,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
                                                                       (uint32_t)total_tiles, ranges);
       SGS_LAUNCH_CHECK();
     }
-    return SGS_OK;
+    return order_tiles();
   }
   // mode 1
   uint32_t* dk[2] = {reinterpret_cast<uint32_t*>(take((size_t)m * 4)), reinterpret_cast<uint32_t*>(take((size_t)m * 4))};
@@ -528,7 +555,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   if (m == 0) {
     k_fill_u32<<<1, 256, 0, s>>>(n_inst, 1, 0u);
     SGS_LAUNCH_CHECK();
-    return SGS_OK;
+    return order_tiles();
   }
   k_depth_keys<<<(unsigned)nbs, 256, 0, s>>>(g->depth, g->tiles, m, dk[0], dv[0]);
   SGS_LAUNCH_CHECK();
@@ -562,7 +589,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
       SGS_LAUNCH_CHECK();
     }
   }
-  return SGS_OK;
+  return order_tiles();
 }
 
 }  // namespace sgs

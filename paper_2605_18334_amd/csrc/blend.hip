@@ -19,6 +19,8 @@
 // kept as a running sum.  Per-pair partial derivatives are summed over the
 // wave with DPP, over the waves in LDS, and written with one set of global
 // atomics per (record, tile).
+#include <algorithm>
+
 #include "sgs_dev.h"
 
 namespace sgs {
@@ -41,6 +43,8 @@ struct BlendArgs {
   float* out_T;
   uint32_t* out_last;
   uint32_t* out_count;     // optional: contributing pairs per pixel
+  const uint32_t* tile_order;  // optional: tiles in this order (longest lists first)
+  uint32_t* work_counter;      // optional: persistent workgroups take tiles from it
   // backward
   const float* cT;
   const uint32_t* clast;
@@ -60,9 +64,9 @@ struct TileSetup {
 };
 
 template <int TW, int TH>
-__device__ __forceinline__ bool setup_tile(const BlendArgs& a, TileSetup& s) {
-  s.tile = xcd_tile(blockIdx.x, a.total_tiles, gridDim.x);
-  if (s.tile >= a.total_tiles) return false;
+__device__ __forceinline__ bool setup_tile(const BlendArgs& a, int tile, TileSetup& s) {
+  s.tile = tile;
+  if (tile < 0 || tile >= a.total_tiles) return false;
   s.view = find_view(a.cams, a.n_views, s.tile);
   s.cam = a.cams + s.view;
   const int lt = s.tile - s.cam->tile_base;
@@ -156,11 +160,28 @@ __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup&
   __syncthreads();
 }
 
+// Tile of a one-workgroup-per-tile launch: the given order, else XCD bands.
+__device__ __forceinline__ int launch_tile(const BlendArgs& a) {
+  if (a.tile_order)
+    return blockIdx.x < (uint32_t)a.total_tiles ? (int)a.tile_order[blockIdx.x] : a.total_tiles;
+  return xcd_tile(blockIdx.x, a.total_tiles, gridDim.x);
+}
+
+// Persistent workgroups: the next tile index from the counter (every
+// workgroup ends once the counter passes the number of tiles).
+__device__ __forceinline__ int next_tile(const BlendArgs& a, uint32_t* s_next) {
+  if (threadIdx.x == 0) *s_next = atomicAdd(a.work_counter, 1u);
+  __syncthreads();
+  const uint32_t idx = *s_next;
+  __syncthreads();
+  if (idx >= (uint32_t)a.total_tiles) return -1;
+  return a.tile_order ? (int)a.tile_order[idx] : (int)idx;
+}
+
 template <int TW, int TH, int B, bool ENH>
-__global__ void __launch_bounds__(TW * TH) k_blend_fwd(BlendArgs a) {
-  __shared__ Stage<TW, TH, B, ENH> S;
+__device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW, TH, B, ENH>& S) {
   TileSetup ts;
-  if (!setup_tile<TW, TH>(a, ts)) return;
+  if (!setup_tile<TW, TH>(a, tile, ts)) return;
   const int w = threadIdx.x >> 6;
   const float fx = (float)ts.px + 0.5f, fy = (float)ts.py + 0.5f;
   uint2 rg = a.ranges[ts.tile];
@@ -219,14 +240,34 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd(BlendArgs a) {
 }
 
 template <int TW, int TH, int B, bool ENH>
-__global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
-  constexpr int NT = TW * TH;
-  constexpr int NG = ENH ? 15 : 11;   // values per record: see the flush below
+__global__ void __launch_bounds__(TW * TH) k_blend_fwd(BlendArgs a) {
   __shared__ Stage<TW, TH, B, ENH> S;
-  __shared__ float sg[NG][B];
-  __shared__ uint32_t smax;
+  __shared__ uint32_t s_next;
+  if (!a.work_counter) {
+    fwd_tile<TW, TH, B, ENH>(a, launch_tile(a), S);
+    return;
+  }
+  for (int tile = next_tile(a, &s_next); tile >= 0; tile = next_tile(a, &s_next))
+    fwd_tile<TW, TH, B, ENH>(a, tile, S);
+}
+
+template <int TW, int TH, int B, bool ENH>
+struct BwdShared {
+  static constexpr int NG = ENH ? 15 : 11;   // values per record: see the flush below
+  Stage<TW, TH, B, ENH> S;
+  float sg[NG][B];
+  uint32_t smax;
+};
+
+template <int TW, int TH, int B, bool ENH>
+__device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared<TW, TH, B, ENH>& X) {
+  constexpr int NT = TW * TH;
+  constexpr int NG = BwdShared<TW, TH, B, ENH>::NG;
+  auto& S = X.S;
+  auto& sg = X.sg;
+  uint32_t& smax = X.smax;
   TileSetup ts;
-  if (!setup_tile<TW, TH>(a, ts)) return;
+  if (!setup_tile<TW, TH>(a, tile, ts)) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const float fx = (float)ts.px + 0.5f, fy = (float)ts.py + 0.5f;
   uint2 rg = a.ranges[ts.tile];
@@ -364,14 +405,52 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
   }
 }
 
+template <int TW, int TH, int B, bool ENH>
+__global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
+  __shared__ BwdShared<TW, TH, B, ENH> X;
+  __shared__ uint32_t s_next;
+  if (!a.work_counter) {
+    bwd_tile<TW, TH, B, ENH>(a, launch_tile(a), X);
+    return;
+  }
+  for (int tile = next_tile(a, &s_next); tile >= 0; tile = next_tile(a, &s_next)) {
+    bwd_tile<TW, TH, B, ENH>(a, tile, X);
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
+
 // ------------------------------------------------------------------ launchers
+// Workgroups that fit on the device at once (persistent launches).
+template <typename F>
+static unsigned resident_grid(F kernel, int threads) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess) return 0;
+  return (unsigned)(cus * (per > 0 ? per : 1));
+}
+
 template <int TW, int TH, int B, bool ENH>
 static void launch_fwd_t(const BlendArgs& a, unsigned grid, hipStream_t s) {
-  k_blend_fwd<TW, TH, B, ENH><<<grid, TW * TH, 0, s>>>(a);
+  auto k = k_blend_fwd<TW, TH, B, ENH>;
+  if (a.work_counter) {
+    const unsigned g = resident_grid(k, TW * TH);
+    grid = g ? std::min(g, grid) : grid;
+    k_zero_u32<<<1, 1, 0, s>>>(a.work_counter);
+  }
+  k<<<grid, TW * TH, 0, s>>>(a);
 }
 template <int TW, int TH, int B, bool ENH>
 static void launch_bwd_t(const BlendArgs& a, unsigned grid, hipStream_t s) {
-  k_blend_bwd<TW, TH, B, ENH><<<grid, TW * TH, 0, s>>>(a);
+  auto k = k_blend_bwd<TW, TH, B, ENH>;
+  if (a.work_counter) {
+    const unsigned g = resident_grid(k, TW * TH);
+    grid = g ? std::min(g, grid) : grid;
+    k_zero_u32<<<1, 1, 0, s>>>(a.work_counter);
+  }
+  k<<<grid, TW * TH, 0, s>>>(a);
 }
 
 template <bool BWD, int TW, int TH, bool ENH>
@@ -396,9 +475,14 @@ static sgs_status dispatch_tile(const BlendArgs& a, const sgs_options* opt, unsi
 }
 
 static BlendArgs make_args(const sgs_geom* g, int64_t m, const uint32_t* vals, int64_t cap,
-                           const uint32_t* ranges, const sgs_camera* cams_dev, int32_t n_views,
-                           int64_t total_tiles, const sgs_options* opt, int64_t P) {
+                           const uint32_t* ranges, const sgs_schedule* sched,
+                           const sgs_camera* cams_dev, int32_t n_views, int64_t total_tiles,
+                           const sgs_options* opt, int64_t P) {
   BlendArgs a = {};
+  if (sched) {
+    a.tile_order = sched->tile_order;
+    a.work_counter = sched->work_counter;
+  }
   const float4* rec = reinterpret_cast<const float4*>(g->rec);
   a.rec0 = rec;
   a.rec1 = rec + m;
@@ -421,11 +505,12 @@ static BlendArgs make_args(const sgs_geom* g, int64_t m, const uint32_t* vals, i
 static unsigned blend_grid(int64_t total_tiles) { return (unsigned)((total_tiles + 7) / 8 * 8); }
 
 sgs_status launch_blend_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals, int64_t cap,
-                            const uint32_t* ranges, const sgs_camera* cams_dev, int32_t n_views,
+                            const uint32_t* ranges, const sgs_schedule* sched,
+                            const sgs_camera* cams_dev, int32_t n_views,
                             int64_t total_tiles, int enhanced, const sgs_options* opt,
                             float* out_rgb, float* out_T, uint32_t* out_last,
                             uint32_t* out_count, int64_t P, hipStream_t s) {
-  BlendArgs a = make_args(g, m, vals, cap, ranges, cams_dev, n_views, total_tiles, opt, P);
+  BlendArgs a = make_args(g, m, vals, cap, ranges, sched, cams_dev, n_views, total_tiles, opt, P);
   a.out_rgb = out_rgb;
   a.out_T = out_T;
   a.out_last = out_last;
@@ -436,11 +521,12 @@ sgs_status launch_blend_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals, 
 }
 
 sgs_status launch_blend_bwd(const sgs_geom* g, int64_t m, const uint32_t* vals, int64_t cap,
-                            const uint32_t* ranges, const sgs_camera* cams_dev, int32_t n_views,
+                            const uint32_t* ranges, const sgs_schedule* sched,
+                            const sgs_camera* cams_dev, int32_t n_views,
                             int64_t total_tiles, int enhanced, const sgs_options* opt,
                             const float* out_T, const uint32_t* out_last, const float* dL,
                             int64_t P, float* g2d, hipStream_t s) {
-  BlendArgs a = make_args(g, m, vals, cap, ranges, cams_dev, n_views, total_tiles, opt, P);
+  BlendArgs a = make_args(g, m, vals, cap, ranges, sched, cams_dev, n_views, total_tiles, opt, P);
   a.cT = out_T;
   a.clast = out_last;
   a.dL = dL;

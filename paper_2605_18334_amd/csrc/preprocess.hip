@@ -239,55 +239,55 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
 }
 
 // Exclusive scan of nb block sums into out[0..nb], out[nb] = total.  One
-// block of 1024 threads, 8 consecutive entries per thread per round.
+// block of 1024 threads, 8 consecutive entries per thread per round.  Sums
+// are kept in 64 bits; an offset past 2^32 - 1 is written as 0xffffffff (the
+// caller sees a saturated total and rejects the frame).
 __global__ void __launch_bounds__(1024) k_scan_blocks(const uint32_t* __restrict__ in,
                                                       uint32_t* __restrict__ out, int64_t nb) {
-  __shared__ uint32_t wsum[16];
-  __shared__ uint32_t carry_s;
+  __shared__ uint64_t wsum[16];
+  __shared__ uint64_t carry_s;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   if (t == 0) carry_s = 0;
   __syncthreads();
+  auto sat = [](uint64_t x) { return x > 0xffffffffull ? 0xffffffffu : (uint32_t)x; };
   for (int64_t base = 0; base < nb; base += 8192) {
-    uint32_t v[8];
-    uint32_t loc = 0;
+    uint64_t v[8];
+    uint64_t loc = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int64_t idx = base + (int64_t)t * 8 + k;
-      v[k] = idx < nb ? in[idx] : 0u;
-      const uint32_t x = v[k];
+      const uint64_t x = idx < nb ? (uint64_t)in[idx] : 0ull;
       v[k] = loc;
       loc += x;
     }
-    // inclusive wave scan of loc
-    uint32_t inc = loc;
+    uint64_t inc = loc;
     for (int off = 1; off < 64; off <<= 1) {
-      uint32_t y = __shfl_up(inc, off);
+      const uint64_t y = __shfl_up(inc, off);
       if (lane >= off) inc += y;
     }
     if (lane == 63) wsum[w] = inc;
     __syncthreads();
     if (w == 0) {
-      uint32_t ws = lane < 16 ? wsum[lane] : 0u;
-      uint32_t wi = ws;
+      const uint64_t ws = lane < 16 ? wsum[lane] : 0ull;
+      uint64_t wi = ws;
       for (int off = 1; off < 16; off <<= 1) {
-        uint32_t y = __shfl_up(wi, off);
+        const uint64_t y = __shfl_up(wi, off);
         if (lane >= off) wi += y;
       }
       if (lane < 16) wsum[lane] = wi - ws;   // exclusive wave offsets
     }
     __syncthreads();
-    const uint32_t carry = carry_s;
-    const uint32_t pre = carry + wsum[w] + inc - loc;
+    const uint64_t pre = carry_s + wsum[w] + inc - loc;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int64_t idx = base + (int64_t)t * 8 + k;
-      if (idx < nb) out[idx] = pre + v[k];
+      if (idx < nb) out[idx] = sat(pre + v[k]);
     }
     __syncthreads();
     if (t == 1023) carry_s = pre + loc;
     __syncthreads();
   }
-  if (t == 0) out[nb] = carry_s;
+  if (t == 0) out[nb] = sat(carry_s);
 }
 
 // ------------------------------------------------------------------ backward

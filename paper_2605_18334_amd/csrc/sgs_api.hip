@@ -16,14 +16,16 @@ sgs_status launch_preprocess_bwd(const sgs_params*, const sgs_camera*, int32_t,
 size_t bin_sort_scratch_bytes(int64_t m, int64_t cap, int64_t total_tiles, int mode);
 sgs_status launch_bin_sort(const sgs_geom*, int64_t m, int64_t n, const sgs_camera*, int32_t,
                            int64_t total_tiles, const sgs_options*, int64_t cap, uint64_t*,
-                           uint32_t*, uint32_t*, uint32_t*, void*, hipStream_t);
+                           uint32_t*, uint32_t*, uint32_t*, uint32_t* tile_order, void*,
+                           hipStream_t);
 sgs_status launch_blend_fwd(const sgs_geom*, int64_t, const uint32_t*, int64_t, const uint32_t*,
-                            const sgs_camera*, int32_t, int64_t, int, const sgs_options*, float*,
-                            float*, uint32_t*, uint32_t*, int64_t, hipStream_t);
-sgs_status launch_blend_bwd(const sgs_geom*, int64_t, const uint32_t*, int64_t, const uint32_t*,
-                            const sgs_camera*, int32_t, int64_t, int, const sgs_options*,
-                            const float*, const uint32_t*, const float*, int64_t, float*,
+                            const sgs_schedule*, const sgs_camera*, int32_t, int64_t, int,
+                            const sgs_options*, float*, float*, uint32_t*, uint32_t*, int64_t,
                             hipStream_t);
+sgs_status launch_blend_bwd(const sgs_geom*, int64_t, const uint32_t*, int64_t, const uint32_t*,
+                            const sgs_schedule*, const sgs_camera*, int32_t, int64_t, int,
+                            const sgs_options*, const float*, const uint32_t*, const float*,
+                            int64_t, float*, hipStream_t);
 }  // namespace sgs
 
 namespace {
@@ -97,6 +99,7 @@ size_t sgs_struct_size(int32_t which) {
     case 3: return sizeof(sgs_options);
     case 4: return sizeof(sgs_geom);
     case 5: return sizeof(sgs_geom_grad);
+    case 6: return sizeof(sgs_schedule);
   }
   return 0;
 }
@@ -209,8 +212,8 @@ sgs_status sgs_preprocess(const sgs_params* p, const sgs_camera* cams_host,
 sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_host,
                         const sgs_camera* cams_dev, int32_t n_views, const sgs_options* opt,
                         int64_t inst_capacity, uint64_t* keys, uint32_t* vals,
-                        uint32_t* tile_ranges, uint32_t* n_inst_dev, void* scratch,
-                        size_t scratch_bytes, void* stream) {
+                        uint32_t* tile_ranges, uint32_t* n_inst_dev, const sgs_schedule* sched,
+                        void* scratch, size_t scratch_bytes, void* stream) {
   if (!g || m < 0 || !cams_ok(cams_host, n_views) || !cams_dev || !options_ok(opt) ||
       inst_capacity < 0 || inst_capacity >= ((int64_t)1 << 32) || !tile_ranges || !n_inst_dev)
     return SGS_EINVAL;
@@ -222,11 +225,13 @@ sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_hos
   if (!scratch || scratch_bytes < sgs::bin_sort_scratch_bytes(m, inst_capacity, tt, opt->sort_mode))
     return SGS_ECAPACITY;
   return sgs::launch_bin_sort(g, m, m / n_views, cams_dev, n_views, tt, opt, inst_capacity, keys,
-                              vals, tile_ranges, n_inst_dev, scratch, (hipStream_t)stream);
+                              vals, tile_ranges, n_inst_dev, sched ? sched->tile_order : nullptr,
+                              scratch, (hipStream_t)stream);
 }
 
 sgs_status sgs_render_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals,
-                          int64_t inst_capacity, const uint32_t* tile_ranges, const sgs_camera* cams_host,
+                          int64_t inst_capacity, const uint32_t* tile_ranges,
+                          const sgs_schedule* sched, const sgs_camera* cams_host,
                           const sgs_camera* cams_dev, int32_t n_views, int32_t enhanced,
                           const sgs_options* opt, float* out_rgb, float* out_T,
                           uint32_t* out_last, uint32_t* out_count, int64_t total_pixels,
@@ -237,14 +242,14 @@ sgs_status sgs_render_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals,
   if (total_pixels != pixels_total(cams_host, n_views)) return SGS_EINVAL;
   if (inst_capacity < 0 || inst_capacity >= ((int64_t)1 << 32) || (!vals && inst_capacity > 0))
     return SGS_EINVAL;
-  return sgs::launch_blend_fwd(g, m, vals, inst_capacity, tile_ranges, cams_dev, n_views,
+  return sgs::launch_blend_fwd(g, m, vals, inst_capacity, tile_ranges, sched, cams_dev, n_views,
                                tiles_total(cams_host, n_views), enhanced ? 1 : 0, opt, out_rgb,
                                out_T, out_last, out_count, total_pixels, (hipStream_t)stream);
 }
 
 sgs_status sgs_render_bwd(const sgs_params* p, const sgs_geom* g, int64_t m,
                           const uint32_t* vals, int64_t inst_capacity,
-                          const uint32_t* tile_ranges,
+                          const uint32_t* tile_ranges, const sgs_schedule* sched,
                           const sgs_camera* cams_host, const sgs_camera* cams_dev,
                           int32_t n_views, const sgs_options* opt, const float* out_T,
                           const uint32_t* out_last, const float* dL_drgb, int64_t total_pixels,
@@ -259,7 +264,8 @@ sgs_status sgs_render_bwd(const sgs_params* p, const sgs_geom* g, int64_t m,
   if (inst_capacity < 0 || inst_capacity >= ((int64_t)1 << 32) || (!vals && inst_capacity > 0))
     return SGS_EINVAL;
   const int enhanced = p->opa2_logit != nullptr;
-  sgs_status st = sgs::launch_blend_bwd(g, m, vals, inst_capacity, tile_ranges, cams_dev, n_views,
+  sgs_status st = sgs::launch_blend_bwd(g, m, vals, inst_capacity, tile_ranges, sched, cams_dev,
+                                        n_views,
                                         tiles_total(cams_host, n_views), enhanced, opt, out_T,
                                         out_last, dL_drgb, total_pixels, g2d->rec,
                                         (hipStream_t)stream);

@@ -183,7 +183,7 @@ def bin_sort(geom, bufs, m: int, cams: CameraBatch, opt: _abi.Options, capacity:
     out["scratch"] = torch.empty(sb, dtype=torch.uint8, device=dev)
     check("sgs_bin_sort", lib.sgs_bin_sort(
         C.byref(geom), m, cams.host, _ptr(cams.dev), cams.n_views, C.byref(opt), capacity,
-        _ptr(out["keys"]), _ptr(out["vals"]), _ptr(out["ranges"]), _ptr(out["n_inst"]),
+        _ptr(out["keys"]), _ptr(out["vals"]), _ptr(out["ranges"]), _ptr(out["n_inst"]), None,
         _ptr(out["scratch"]), sb, _stream(stream)))
     return out
 
@@ -200,6 +200,8 @@ def render(gs: GaussianSet, cams: CameraBatch, opt: _abi.Options | None = None,
     geom, bufs = preprocess(gs, cams, opt, stream)
     if capacity is None:
         capacity = int(bufs["block_off"][-1].item()) & 0xFFFFFFFF
+        if capacity == 0xFFFFFFFF:
+            raise _abi.SgsError("sgs_preprocess: instance count exceeds 2^32-1", 2)
     bs = bin_sort(geom, bufs, m, cams, opt, capacity, keep_keys, stream)
     bufs.update(bs)
     dev = bufs["depth"].device
@@ -209,7 +211,7 @@ def render(gs: GaussianSet, cams: CameraBatch, opt: _abi.Options | None = None,
     out_last = torch.empty(P, dtype=torch.int32, device=dev)
     bufs["count"] = torch.empty(P, dtype=torch.int32, device=dev) if count else None
     check("sgs_render_fwd", lib.sgs_render_fwd(
-        C.byref(geom), m, _ptr(bufs["vals"]), capacity, _ptr(bufs["ranges"]), cams.host, _ptr(cams.dev),
+        C.byref(geom), m, _ptr(bufs["vals"]), capacity, _ptr(bufs["ranges"]), None, cams.host, _ptr(cams.dev),
         cams.n_views, int(gs.enhanced), C.byref(opt), _ptr(out_rgb), _ptr(out_T), _ptr(out_last),
         _ptr(bufs["count"]), P, _stream(stream)))
     return Frame(gs, cams, opt, geom, bufs, capacity, out_rgb, out_T, out_last)
@@ -231,7 +233,7 @@ def render_backward(fr: Frame, dL_drgb: torch.Tensor, stream=None) -> dict:
     p = gs.struct()
     check("sgs_render_bwd", lib.sgs_render_bwd(
         C.byref(p), C.byref(fr.geom), fr.m, _ptr(fr.bufs["vals"]), fr.n_inst, _ptr(fr.bufs["ranges"]),
-        fr.cams.host, _ptr(fr.cams.dev), fr.cams.n_views, C.byref(fr.opt), _ptr(fr.out_T),
+        None, fr.cams.host, _ptr(fr.cams.dev), fr.cams.n_views, C.byref(fr.opt), _ptr(fr.out_T),
         _ptr(fr.out_last), _ptr(dL), fr.cams.total_pixels, C.byref(gg), C.byref(pg),
         _stream(stream)))
     grads["g2d"] = g2d
@@ -285,7 +287,7 @@ class Renderer:
 
     def __init__(self, gs: GaussianSet, cams: CameraBatch, opt: _abi.Options | None = None,
                  capacity: int | None = None, headroom: float = 1.25, keep_keys: bool = False,
-                 count: bool = False):
+                 count: bool = False, tile_order: bool = False, persistent: bool = False):
         self.lib = load()
         self.gs, self.cams = gs, cams
         self.opt = opt if opt is not None else _abi.default_options()
@@ -295,7 +297,10 @@ class Renderer:
         dev = gs.mean.device
         if capacity is None:
             self.preprocess()
-            capacity = int(int(self.bufs["block_off"][-1].item()) * headroom) + 1024
+            total = int(self.bufs["block_off"][-1].item()) & 0xFFFFFFFF
+            if total == 0xFFFFFFFF:
+                raise _abi.SgsError("sgs_preprocess: instance count exceeds 2^32-1", 2)
+            capacity = min(int(total * headroom) + 1024, 0xFFFFFFFE)
         self.capacity = int(capacity)
         b = self.bufs
         b["vals"] = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
@@ -311,7 +316,11 @@ class Renderer:
         self.out_T = torch.empty(P, dtype=torch.float32, device=dev)
         self.out_last = torch.empty(P, dtype=torch.int32, device=dev)
         b["count"] = torch.empty(P, dtype=torch.int32, device=dev) if count else None
+        b["tile_order"] = torch.empty(cams.total_tiles, dtype=torch.int32, device=dev) if tile_order else None
+        b["work_counter"] = torch.zeros(1, dtype=torch.int32, device=dev) if persistent else None
+        self.sched = _abi.Schedule(_ptr(b["tile_order"]), _ptr(b["work_counter"]))
         self._bwd = None
+        self.graph = None
 
     # ---- forward stages
     def preprocess(self, stream=None):
@@ -324,13 +333,15 @@ class Renderer:
         check("sgs_bin_sort", self.lib.sgs_bin_sort(
             C.byref(self.geom), self.m, self.cams.host, _ptr(self.cams.dev), self.cams.n_views,
             C.byref(self.opt), self.capacity, _ptr(b["keys"]), _ptr(b["vals"]), _ptr(b["ranges"]),
-            _ptr(b["n_inst"]), _ptr(b["scratch"]), self.scratch_bytes, _stream(stream)))
+            _ptr(b["n_inst"]), C.byref(self.sched), _ptr(b["scratch"]), self.scratch_bytes,
+            _stream(stream)))
 
     def blend(self, stream=None):
         b = self.bufs
         check("sgs_render_fwd", self.lib.sgs_render_fwd(
             C.byref(self.geom), self.m, _ptr(b["vals"]), self.capacity, _ptr(b["ranges"]),
-            self.cams.host, _ptr(self.cams.dev), self.cams.n_views, int(self.gs.enhanced),
+            C.byref(self.sched), self.cams.host, _ptr(self.cams.dev), self.cams.n_views,
+            int(self.gs.enhanced),
             C.byref(self.opt), _ptr(self.out_rgb), _ptr(self.out_T), _ptr(self.out_last),
             _ptr(b["count"]), self.cams.total_pixels, _stream(stream)))
 
@@ -338,6 +349,27 @@ class Renderer:
         self.preprocess(stream)
         self.bin_sort(stream)
         self.blend(stream)
+        return self.out_rgb
+
+    def capture(self):
+        """Captures forward() (preprocess, bin/sort, blend: every kernel of the
+        frame) into one HIP graph; replay() then launches the whole frame with
+        one call.  Camera poses may change between replays through
+        CameraBatch.upload() (same layout); the capacity is fixed."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.forward()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.forward()
+        self.graph = g
+        return g
+
+    def replay(self) -> torch.Tensor:
+        self.graph.replay()
         return self.out_rgb
 
     def n_inst(self) -> int:
@@ -369,7 +401,7 @@ class Renderer:
         b = self.bufs
         check("sgs_render_bwd", self.lib.sgs_render_bwd(
             C.byref(self.params), C.byref(self.geom), self.m, _ptr(b["vals"]), self.capacity,
-            _ptr(b["ranges"]), self.cams.host, _ptr(self.cams.dev), self.cams.n_views, C.byref(self.opt),
+            _ptr(b["ranges"]), C.byref(self.sched), self.cams.host, _ptr(self.cams.dev), self.cams.n_views, C.byref(self.opt),
             _ptr(self.out_T), _ptr(self.out_last), _ptr(dL_drgb), self.cams.total_pixels,
             C.byref(gg), C.byref(pg), _stream(stream)))
         return grads

@@ -119,8 +119,9 @@ def test_entry_points_reject_null_arguments_without_gpu():
     p = _abi.Params()
     p.n = -1
     assert lib.sgs_preprocess(C.byref(p), None, None, 1, C.byref(o), C.byref(g), None) == 1
-    assert lib.sgs_bin_sort(None, 0, None, None, 1, C.byref(o), 0, None, None, None, None, None, 0, None) == 1
-    assert lib.sgs_render_fwd(None, 0, None, 0, None, None, None, 1, 0, C.byref(o), None, None, None, None,
-                              0, None) == 1
-    assert lib.sgs_render_bwd(None, None, 0, None, 0, None, None, None, 1, C.byref(o), None, None, None, 0,
-                              None, None, None) == 1
+    assert lib.sgs_bin_sort(None, 0, None, None, 1, C.byref(o), 0, None, None, None, None, None, None, 0,
+                            None) == 1
+    assert lib.sgs_render_fwd(None, 0, None, 0, None, None, None, None, 1, 0, C.byref(o), None, None, None,
+                              None, 0, None) == 1
+    assert lib.sgs_render_bwd(None, None, 0, None, 0, None, None, None, None, 1, C.byref(o), None, None, None,
+                              0, None, None, None) == 1
