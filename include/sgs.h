@@ -72,7 +72,21 @@ typedef struct {
 } sgs_params;
 
 /* Accumulated (+=) gradients, device pointers, same shapes as sgs_params.
- * A pointer may be NULL when the matching parameter is NULL. */
+ * Any pointer may be NULL (that output is skipped).
+ *
+ * The last three fields are the per-Gaussian statistics that drive
+ * densification (Sec. "Depth-Aware Densification Strategy", Eq. depth_grad),
+ * gathered by the backward of each call over its n views v, where L_v is
+ * view v's part of the loss and a view "sees" a Gaussian when its extent
+ * covers at least one tile:
+ *   densify_uv[i]    += sum over seeing views of the screen-space gradient
+ *                       norm || (dL_v/dmu2d_x * W_v/2, dL_v/dmu2d_y * H_v/2) ||
+ *                       (NDC units, the 2D statistic g_uv)
+ *   densify_z[i]      = max(densify_z[i], max over seeing views of
+ *                       | r_v . dL_v/dmean |), r_v the third row of view v's
+ *                       w2c: the gradient w.r.t. the depth of the centre (g_z)
+ *   densify_count[i] += number of seeing views
+ * The caller zeroes them once per densification interval. */
 typedef struct {
   float* mean;
   float* log_scale;
@@ -82,6 +96,9 @@ typedef struct {
   float* opa2_logit;
   float* opa_dir;
   float* sh;
+  float* densify_uv;        /* [N] or NULL */
+  float* densify_z;         /* [N] or NULL */
+  uint32_t* densify_count;  /* [N] or NULL */
 } sgs_params_grad;
 
 /* One pinhole view in the OpenCV convention (+x right, +y down, +z forward;

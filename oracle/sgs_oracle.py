@@ -211,9 +211,12 @@ def to_tensors(scene, requires_grad=False) -> dict:
     }
 
 
-def project(P: dict, sh_degree: int, cam: Camera, opt: Options = Options()) -> Projected:
+def project(P: dict, sh_degree: int, cam: Camera, opt: Options = Options(),
+            mu2d_shift: torch.Tensor | None = None) -> Projected:
     """Per-Gaussian projection (Sec. "Preliminary of 3D Gaussian Splatting";
-    appendix "Forward Pass"; 2D skew and enhanced-opacity readings above)."""
+    appendix "Forward Pass"; 2D skew and enhanced-opacity readings above).
+    ``mu2d_shift`` [N,2] (pixels) is added to the projected means: a handle
+    for the gradient with respect to the 2D means, zero in every render."""
     mean = P["mean"]
     n = mean.shape[0]
     # Sigma = R S S^T R^T
@@ -253,6 +256,8 @@ def project(P: dict, sh_degree: int, cam: Camera, opt: Options = Options()) -> P
     else:
         rho = torch.ones_like(detf_s)
     mu2d = torch.stack([fx * tx / tzs + cx, fy * ty / tzs + cy], 1)
+    if mu2d_shift is not None:
+        mu2d = mu2d + mu2d_shift
     o1 = torch.sigmoid(P["opa_logit"])
     o2 = torch.sigmoid(P["opa2_logit"]) if P.get("opa2_logit") is not None else o1
     if P.get("skew") is not None and not opt.symmetric:
@@ -428,7 +433,23 @@ def render_grad(scene, pose_or_cam, dL_dC: np.ndarray, pixels: np.ndarray | None
     derivative.  Returns float64 numpy arrays in the scene's SoA shapes."""
     cam = pose_or_cam if isinstance(pose_or_cam, Camera) else camera_from_pose(pose_or_cam)
     P = to_tensors(scene, requires_grad=True)
-    pr = project(P, scene.sh_degree, cam, opt)
+    total, _ = _loss_graph(P, scene.sh_degree, cam, dL_dC, pixels, opt, chunk_elems)
+    leaves = {k: v for k, v in P.items() if v is not None}
+    grads = torch.autograd.grad(total, list(leaves.values()), allow_unused=True)
+    out = {}
+    for (k, v), gr in zip(leaves.items(), grads):
+        gr = torch.zeros_like(v) if gr is None else gr
+        a = gr.detach().numpy()
+        out[k] = a.transpose(1, 2, 0) if k == "sh" else (a.T if a.ndim == 2 else a)
+    return out
+
+
+def _loss_graph(P: dict, sh_degree: int, cam: Camera, dL_dC, pixels, opt: Options,
+                chunk_elems: int, mu2d_shift: torch.Tensor | None = None):
+    """L = sum_p dL_dC[p] . C(p) as a differentiable graph of the leaves in P
+    (and of mu2d_shift), with the included pairs and stop points held fixed
+    at their values.  Returns (L, Projected)."""
+    pr = project(P, sh_degree, cam, opt, mu2d_shift)
     order = depth_order(pr)
     pixels, pc = pixel_centres(cam, pixels)
     g = torch.from_numpy(np.asarray(dL_dC, np.float64).reshape(-1, 3))
@@ -447,11 +468,43 @@ def render_grad(scene, pose_or_cam, dL_dC: np.ndarray, pixels: np.ndarray | None
         at = alpha_tilde(pcs, pr, sub, opt)
         C, _ = composite(at, pr.rgb[sub], bg, inc[:, cols], opt)
         total = total + (C * g[s:s + step]).sum()
-    leaves = {k: v for k, v in P.items() if v is not None}
-    grads = torch.autograd.grad(total, list(leaves.values()), allow_unused=True)
-    out = {}
-    for (k, v), gr in zip(leaves.items(), grads):
-        gr = torch.zeros_like(v) if gr is None else gr
-        a = gr.detach().numpy()
-        out[k] = a.transpose(1, 2, 0) if k == "sh" else (a.T if a.ndim == 2 else a)
-    return out
+    return total, pr
+
+
+def densify_stats(scene, pose_or_cam, dL_dC: np.ndarray, pixels: np.ndarray | None = None,
+                  opt: Options = Options(), chunk_elems: int = 1 << 19) -> dict:
+    """Per-Gaussian densification statistics of one view for the loss
+    L = sum_p dL_dC[p] . C(p) (Sec. "Depth-Aware Densification Strategy",
+    Eq. depth_grad, with the 2D statistic of 3DGS beside it):
+      uv[i]    = || (dL/dmu2d_x * W/2, dL/dmu2d_y * H/2) ||, the gradient with
+                 respect to the projected mean in NDC units (mu2d held as a
+                 variable of its own: conic, skew and colour fixed);
+      z[i]     = | r . dL/dmean_i |, r the camera's depth axis (third row of
+                 w2c): the derivative of L when the centre moves in depth,
+                 through every path (projection, footprint, SH direction);
+      reach[i] = alpha reaches alpha_min at some requested pixel;
+      valid[i] = not culled (in front of the near plane, invertible 2D
+                 covariance).
+    Float64 numpy arrays [N] (bool for reach and valid)."""
+    cam = pose_or_cam if isinstance(pose_or_cam, Camera) else camera_from_pose(pose_or_cam)
+    P = to_tensors(scene, requires_grad=True)
+    shift = torch.zeros((scene.n, 2), dtype=F64, requires_grad=True)
+    total, pr = _loss_graph(P, scene.sh_degree, cam, dL_dC, pixels, opt, chunk_elems, shift)
+    g_mean, g_shift = torch.autograd.grad(total, [P["mean"], shift], allow_unused=True)
+    g_mean = torch.zeros((scene.n, 3), dtype=F64) if g_mean is None else g_mean
+    g_shift = torch.zeros((scene.n, 2), dtype=F64) if g_shift is None else g_shift
+    ndc = g_shift.detach().numpy() * np.array([0.5 * cam.W, 0.5 * cam.H])
+    r = cam.w2c[2, :3]
+    z = np.abs(g_mean.detach().numpy() @ r)
+    with torch.no_grad():
+        pr0 = project(to_tensors(scene), scene.sh_degree, cam, opt)
+        idx = torch.nonzero(pr0.valid).flatten()
+        _, pc = pixel_centres(cam, pixels)
+        reach = np.zeros(scene.n, bool)
+        step = max(1, chunk_elems // max(1, idx.numel()))
+        for s in range(0, pc.shape[0], step):
+            at = alpha_tilde(pc[s:s + step], pr0, idx, opt)
+            hit = (torch.clamp(at, max=opt.alpha_max) >= opt.alpha_min).any(0)
+            reach[idx[hit].numpy()] = True
+    return {"uv": np.sqrt((ndc * ndc).sum(1)), "z": z, "reach": reach,
+            "valid": pr0.valid.numpy().copy(), "dL_dmu2d": g_shift.detach().numpy()}

@@ -7,8 +7,8 @@ missing (no CPU fallback exists).
 """
 from ._abi import SgsError, default_options, load
 from .raster import (CameraBatch, Frame, GaussianSet, Renderer, SkewGaussianRasterizer, bin_sort,
-                     preprocess, rasterize, render, render_backward)
+                     densify_stats, preprocess, rasterize, render, render_backward)
 
 __all__ = ["SgsError", "default_options", "load", "CameraBatch", "Frame", "GaussianSet", "Renderer",
-           "SkewGaussianRasterizer", "bin_sort", "preprocess", "rasterize", "render",
+           "SkewGaussianRasterizer", "bin_sort", "densify_stats", "preprocess", "rasterize", "render",
            "render_backward"]

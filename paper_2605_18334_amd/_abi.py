@@ -22,7 +22,8 @@ class Params(C.Structure):
 
 class ParamsGrad(C.Structure):
     _fields_ = [("mean", P), ("log_scale", P), ("quat", P), ("skew", P),
-                ("opa_logit", P), ("opa2_logit", P), ("opa_dir", P), ("sh", P)]
+                ("opa_logit", P), ("opa2_logit", P), ("opa_dir", P), ("sh", P),
+                ("densify_uv", P), ("densify_z", P), ("densify_count", P)]
 
 
 class Camera(C.Structure):

@@ -117,14 +117,21 @@ DEFAULT_CANDIDATES = [
     LaunchConfig(16, 16, 256, 1, True, True, 16),
     LaunchConfig(16, 16, 128, 1, True, False, 16),
     LaunchConfig(16, 8, 128, 1, True, False, 16),
-    LaunchConfig(8, 8, 64, 1, True, False, 16),
+    LaunchConfig(16, 8, 128, 1, True, False, 4),
+    LaunchConfig(8, 8, 64, 1, True, False, 4),
     LaunchConfig(16, 16, 256, 1, True, False, 8),
     LaunchConfig(16, 16, 256, 1, True, False, 4),
 ]
 
 
 def time_config(gs, poses, cfg: LaunchConfig, reps: int = 3) -> float:
-    br = BatchRenderer(gs, poses, cfg)
+    """Milliseconds per frame, or inf when the library rejects the
+    configuration for this workload (for example, too many instances)."""
+    try:
+        br = BatchRenderer(gs, poses, cfg)
+    except (_abi.SgsError, torch.cuda.OutOfMemoryError):
+        torch.cuda.empty_cache()
+        return float("inf")
     br.forward()
     torch.cuda.synchronize()
     if br.overflowed():
@@ -161,6 +168,8 @@ def autotune(gs: GaussianSet, poses, candidates=None, reps: int = 3, use_cache: 
         timings[json.dumps(asdict(c))] = ms
         if log:
             log(f"autotune {asdict(c)}: {ms:.3f} ms")
+    if not any(v < float("inf") for v in timings.values()):
+        raise _abi.SgsError("autotune: no candidate configuration fits this workload", 2)
     best = min(timings, key=timings.get)
     cfg = LaunchConfig(**json.loads(best))
     if use_cache:

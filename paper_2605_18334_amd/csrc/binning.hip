@@ -206,6 +206,11 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
 
 // ------------------------------------------------------------- duplicate
 struct DupArgs {
+  const float4* rec0;    // record planes: (mu_x, mu_y, a, b), (c, beta, d), (..., log_thr)
+  const float4* rec1;
+  const float4* rec2;
+  float alpha_min;
+  int32_t tile_w, tile_h;
   const uint32_t* rect;
   const uint32_t* tiles;
   const float* depth;
@@ -224,6 +229,13 @@ struct DupArgs {
   int64_t m;
 };
 
+// Skew cut of a record from its stored plane 1 (beta, opacity factor d):
+// the same value the preprocess used when it counted the record's tiles.
+__device__ __forceinline__ float record_zcut(const DupArgs& a, float4 q1) {
+  if (q1.y == 0.0f && q1.z == 0.0f) return -1e30f;
+  return skew_zcut(a.alpha_min, q1.w);
+}
+
 // Mode 0: records in index order; block (bx, v) covers records v*N + bx*256 + t.
 __global__ void __launch_bounds__(256) k_duplicate64(DupArgs a) {
   __shared__ uint32_t ws[4];
@@ -235,17 +247,22 @@ __global__ void __launch_bounds__(256) k_duplicate64(DupArgs a) {
   if (v == 0 && blockIdx.x == 0 && threadIdx.x == 0) *a.n_inst = a.block_off[a.nb_total];
   if (cnt == 0) return;
   const uint2 r = reinterpret_cast<const uint2*>(a.rect)[m];
-  const uint32_t x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
+  const int x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
   const sgs_camera& cam = a.cams[v];
   const uint64_t lo = (uint64_t)__float_as_uint(a.depth[m]);
+  const float4 q0 = a.rec0[m], q1 = a.rec1[m], q2 = a.rec2[m];
+  const float zc = record_zcut(a, q1);
   uint32_t k = off;
-  for (uint32_t y = y0; y < y1; ++y)
-    for (uint32_t x = x0; x < x1; ++x, ++k)
+  for (int y = y0; y < y1; ++y) {
+    int c0, c1;
+    row_span(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, zc, y, a.tile_w, a.tile_h, x0, x1, c0, c1);
+    for (int x = c0; x < c1 && k < off + cnt; ++x, ++k)
       if (k < a.cap) {
         const uint64_t tile = (uint64_t)(cam.tile_base + y * cam.tiles_x + x);
         a.keys64[k] = (tile << 32) | lo;
         a.vals[k] = (uint32_t)m;
       }
+  }
 }
 
 // Mode 1, step 1: depth keys of all records (culled ones sort last).
@@ -331,7 +348,10 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
     if (s_off[mid] <= o) lo = mid; else hi = mid;
   }
   uint32_t k = lo;
-  uint32_t rec = 0xffffffffu, x0 = 0, y0 = 0, wdt = 1, tb = 0, tx = 0;
+  uint32_t rec = 0xffffffffu, tb = 0, tx = 0, cum = 0;
+  int x0 = 0, x1 = 0, y1 = 0, row = 0, c0 = 0, c1 = 0;
+  float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
+  float zc = -1e30f;
   for (int e = 0; e < EX_PT; ++e, ++o) {
     if (o >= n) break;
     while (k + 1 < W && s_off[k + 1] <= o) ++k;
@@ -340,15 +360,28 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
       const uint64_t rm = rec < (uint64_t)a.m ? rec : 0;
       const uint2 r = reinterpret_cast<const uint2*>(a.rect)[rm];
       x0 = r.x & 0xffffu;
-      y0 = r.x >> 16;
-      wdt = max(1u, (r.y & 0xffffu) - x0);
+      x1 = r.y & 0xffffu;
+      row = r.x >> 16;
+      y1 = r.y >> 16;
+      q0 = a.rec0[rm];
+      q1 = a.rec1[rm];
+      q2 = a.rec2[rm];
       const sgs_camera& cam = a.cams[rm / (uint64_t)a.n];
       tb = (uint32_t)cam.tile_base;
       tx = (uint32_t)cam.tiles_x;
+      cum = 0;
+      zc = record_zcut(a, q1);
+      row_span(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, zc, row, a.tile_w, a.tile_h, x0, x1, c0, c1);
     }
+    // instance q of this record: walk the rows of its rect until q falls in one
     const uint32_t q = (uint32_t)(o - s_off[k]);
-    const uint32_t y = y0 + q / wdt, x = x0 + q % wdt;
-    a.keys32[o] = tb + y * tx + x;
+    while (q >= cum + (uint32_t)(c1 - c0) && row + 1 < y1) {
+      cum += (uint32_t)(c1 - c0);
+      ++row;
+      row_span(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, zc, row, a.tile_w, a.tile_h, x0, x1, c0, c1);
+    }
+    const uint32_t x = min((uint32_t)(c0 + (q - cum)), (uint32_t)max(x1 - 1, 0));
+    a.keys32[o] = tb + (uint32_t)row * tx + x;
     a.vals[o] = rec;
   }
 }
@@ -506,6 +539,13 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   k_fill_u32<<<(unsigned)cdiv(2 * total_tiles, 256), 256, 0, s>>>(ranges, 2 * (uint64_t)total_tiles, 0u);
   SGS_LAUNCH_CHECK();
   DupArgs a = {};
+  const uint64_t mm = (uint64_t)m;
+  a.rec0 = reinterpret_cast<const float4*>(g->rec);
+  a.rec1 = a.rec0 + mm;
+  a.rec2 = a.rec0 + 2 * mm;
+  a.tile_w = opt->tile_w;
+  a.tile_h = opt->tile_h;
+  a.alpha_min = opt->alpha_min;
   a.rect = g->rect;
   a.tiles = g->tiles;
   a.depth = g->depth;

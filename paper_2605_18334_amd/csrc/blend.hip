@@ -122,12 +122,21 @@ __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup&
       if (!(det > 0.0f) || !(ex < 1e30f) || !(ey < 1e30f)) {
         msk = (1u << St::NW) - 1u;
       } else {
+        // skew half-plane: alpha <= d (1 + erf(z)) stays below alpha_min
+        // wherever beta.delta < sqrt2 * zcut
+        const bool skew = (q1.y != 0.0f) || (q1.z != 0.0f);
+        const float zc = skew ? skew_zcut(a.alpha_min, q1.w) : -1e30f;
+        const float need = zc * 1.41421356f;
 #pragma unroll
         for (int w = 0; w < St::NW; ++w) {
           const float lx = (float)(ts.ox + (w % (TW / 8)) * 8) + 0.5f;
           const float ly = (float)(ts.oy + (w / (TW / 8)) * 8) + 0.5f;
-          if (q0.x + ex >= lx && q0.x - ex <= lx + 7.0f && q0.y + ey >= ly && q0.y - ey <= ly + 7.0f)
-            msk |= 1u << w;
+          bool hit = q0.x + ex >= lx && q0.x - ex <= lx + 7.0f && q0.y + ey >= ly && q0.y - ey <= ly + 7.0f;
+          if (hit && zc > -1e29f) {
+            const float top = skew_box_max(q1.y, q1.z, lx + 3.5f, ly + 3.5f, q0.x, q0.y, 3.5f, 3.5f);
+            hit = top + 1e-3f * (1.0f + fabsf(top) + fabsf(need)) >= need;
+          }
+          if (hit) msk |= 1u << w;
         }
       }
     }

@@ -209,13 +209,23 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
           if (x0 <= x1 && y0 <= y1) {
             const int tx0 = (int)x0 / a.opt.tile_w, tx1 = (int)x1 / a.opt.tile_w + 1;
             const int ty0 = (int)y0 / a.opt.tile_h, ty1 = (int)y1 / a.opt.tile_h + 1;
-            ntiles = (uint32_t)((tx1 - tx0) * (ty1 - ty0));
             rx = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
             ry = (uint32_t)tx1 | ((uint32_t)ty1 << 16);
             const float thr = -L - 1e-3f;   // power below thr => alpha < alpha_min
+            // stored opacity factor: rho * alpha_1, or rho alone with enhanced
+            // opacity (an upper bound of rho * o(delta), so the cut stays safe)
+            const float d = a.enhanced ? P.rho : P.rho * P.o1;
+            const float zc = has_skew ? skew_zcut(a.opt.alpha_min, d) : -1e30f;
+            // tiles of the rect that the evaluation ellipse (cut by the skew
+            // half-plane) reaches, row by row
+            for (int row = ty0; row < ty1; ++row) {
+              int c0, c1;
+              row_span(P.mux, P.muy, P.a, P.b, P.c, thr, P.b2x, P.b2y, zc, row, a.opt.tile_w,
+                       a.opt.tile_h, tx0, tx1, c0, c1);
+              ntiles += (uint32_t)(c1 - c0);
+            }
             const int64_t M = a.m;
             float4* rec = reinterpret_cast<float4*>(a.rec);
-            const float d = a.enhanced ? P.rho : P.rho * P.o1;
             rec[m] = make_float4(P.mux, P.muy, P.a, P.b);
             rec[M + m] = make_float4(P.c, P.b2x, P.b2y, d);
             rec[2 * M + m] = make_float4(P.rgb[0], P.rgb[1], P.rgb[2], thr);
@@ -350,6 +360,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(PreBwdArgs a) {
   float gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0};
   float gbeta[3] = {0, 0, 0}, gdirv3[3] = {0, 0, 0};
   float gl1 = 0.0f, gl2 = 0.0f;
+  float st_uv = 0.0f, st_z = 0.0f;   // densification statistics over the views
+  uint32_t st_n = 0;
   const float4* g2 = reinterpret_cast<const float4*>(a.g2d);
   for (int v = 0; v < a.n_views; ++v) {
     const int64_t m = (int64_t)v * n + i;
@@ -441,7 +453,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(PreBwdArgs a) {
     gtx += G0.x * cam.fx * itz;
     gty += G0.y * cam.fy * itz;
     gtz -= (G0.x * cam.fx * P.tx + G0.y * cam.fy * P.ty) * itz2;
-    for (int k = 0; k < 3; ++k) gmean[k] += W[k] * gtx + W[4 + k] * gty + W[8 + k] * gtz;
+    float gmv[3];   // this view's gradient w.r.t. the mean
+    for (int k = 0; k < 3; ++k) gmv[k] = W[k] * gtx + W[4 + k] * gty + W[8 + k] * gtz;
     // M = R diag(s)
     float gR[3][3];
     for (int r = 0; r < 3; ++r)
@@ -481,12 +494,23 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(PreBwdArgs a) {
         sh_basis_grad<DEG>(P.dir[0], P.dir[1], P.dir[2], wk, gdx, gdy, gdz);
         const float dd = gdx * P.dir[0] + gdy * P.dir[1] + gdz * P.dir[2];
         const float idist = 1.0f / P.dist;
-        gmean[0] += (gdx - P.dir[0] * dd) * idist;
-        gmean[1] += (gdy - P.dir[1] * dd) * idist;
-        gmean[2] += (gdz - P.dir[2] * dd) * idist;
+        gmv[0] += (gdx - P.dir[0] * dd) * idist;
+        gmv[1] += (gdy - P.dir[1] * dd) * idist;
+        gmv[2] += (gdz - P.dir[2] * dd) * idist;
       }
     }
+    for (int k = 0; k < 3; ++k) gmean[k] += gmv[k];
+    // densification statistics (Sec. "Depth-Aware Densification Strategy"):
+    // screen-space gradient norm in NDC units (pixels scale by W/2, H/2) and
+    // the derivative along this view's depth axis (third row of w2c)
+    const float gu = G0.x * (0.5f * (float)cam.width), gv = G0.y * (0.5f * (float)cam.height);
+    st_uv += sqrtf(gu * gu + gv * gv);
+    st_z = fmaxf(st_z, fabsf(W[8] * gmv[0] + W[9] * gmv[1] + W[10] * gmv[2]));
+    ++st_n;
   }
+  if (a.g.densify_uv) a.g.densify_uv[i] += st_uv;
+  if (a.g.densify_z) a.g.densify_z[i] = fmaxf(a.g.densify_z[i], st_z);
+  if (a.g.densify_count) a.g.densify_count[i] += st_n;
   for (int k = 0; k < 3; ++k) {
     if (a.g.mean) a.g.mean[k * n + i] += gmean[k];
     if (a.g.log_scale) a.g.log_scale[k * n + i] += gls[k];

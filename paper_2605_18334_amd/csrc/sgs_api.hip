@@ -220,7 +220,7 @@ sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_hos
   if (m % n_views != 0 || m >= ((int64_t)1 << 32)) return SGS_EINVAL;
   if (inst_capacity > 0 && !vals) return SGS_EINVAL;
   if (opt->sort_mode == 0 && inst_capacity > 0 && !keys) return SGS_EINVAL;
-  if (m > 0 && (!g->depth || !g->rect || !g->tiles || !g->block_off)) return SGS_EINVAL;
+  if (m > 0 && (!g->rec || !g->depth || !g->rect || !g->tiles || !g->block_off)) return SGS_EINVAL;
   const int64_t tt = tiles_total(cams_host, n_views);
   if (!scratch || scratch_bytes < sgs::bin_sort_scratch_bytes(m, inst_capacity, tt, opt->sort_mode))
     return SGS_ECAPACITY;

@@ -84,6 +84,92 @@ __device__ __forceinline__ float enh_opacity(float o1, float o2, float wx, float
   return 0.5f * fmaf(o1 - o2, erfu, o1 + o2);
 }
 
+// ---------------------------------------------------------------- tiles
+// Columns [c0, c1) of tile row `row` that the evaluation ellipse of a record
+// can reach: the ellipse {delta : a dx^2 + 2 b dx dy + c dy^2 <= R2} around
+// (mx, my), R2 = -2 log_thr (outside it every pair is skipped), sampled at
+// pixel centres (i + 0.5), widened by a small margin and clipped to the
+// record's rect [x0, x1).  Counting (preprocess) and enumeration (duplicate)
+// call this same contraction-free code with the same stored record values, so
+// they agree exactly.
+// Skew cut: pairs whose z = beta.delta/sqrt2 is below the returned value have
+// alpha <= d (1 + erf z) < alpha_min (G' <= 1), d the record's largest
+// opacity factor.  1e-3 below the exact root of 1 + erf(z0) = alpha_min/d;
+// since d <= 1, z0 >= -2.04 and the slope of 1 + erf there keeps that margin
+// far above the float32 error of the evaluated alpha.  -1e30: no cut.
+__device__ __forceinline__ float skew_zcut(float alpha_min, float d) {
+  const float t = alpha_min / d - 1.0f;
+  if (!(t > -1.0f)) return -1e30f;
+  if (t >= 1.0f) return 1e30f;
+  return erfinvf(t) - 1e-3f;
+}
+
+// Largest beta.delta over pixel centres of the box with centre (cx, cy) and
+// half extents (hx, hy), delta = centre - mean.
+__device__ __forceinline__ float skew_box_max(float bx, float by, float cx, float cy, float mx,
+                                              float my, float hx, float hy) {
+#pragma clang fp contract(off)
+  return bx * (cx - mx) + by * (cy - my) + fabsf(bx) * hx + fabsf(by) * hy;
+}
+
+__device__ __forceinline__ void row_span(float mx, float my, float a, float b, float c,
+                                         float log_thr, float bx, float by, float zcut, int row,
+                                         int tw, int th, int x0, int x1, int& c0, int& c1) {
+#pragma clang fp contract(off)
+  c0 = x0;
+  c1 = x0;
+  const float R2 = -2.0f * log_thr * 1.002f + 1e-3f;
+  const float det = a * c - b * b;
+  if (!(det > 0.0f) || !(R2 > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) {
+    c1 = x1;                                   // degenerate: keep the whole rect row
+    return;
+  }
+  const float ey = sqrtf(R2 * a / det);
+  float u0 = ((float)(row * th) + 0.5f - 0.01f) - my;
+  float u1 = ((float)(row * th + th) - 0.5f + 0.01f) - my;
+  u0 = fmaxf(u0, -ey);
+  u1 = fminf(u1, ey);
+  if (!(u0 <= u1)) return;
+  const float ex = sqrtf(R2 * c / det);
+  const float R = sqrtf(R2);
+  const float yx = -b * R / sqrtf(c * det);    // dy where x is largest on the ellipse
+  const float r0 = sqrtf(fmaxf(a * R2 - det * u0 * u0, 0.0f));
+  const float r1 = sqrtf(fmaxf(a * R2 - det * u1 * u1, 0.0f));
+  float xr = fmaxf((-b * u0 + r0) / a, (-b * u1 + r1) / a);
+  float xl = fminf((-b * u0 - r0) / a, (-b * u1 - r1) / a);
+  if (yx >= u0 && yx <= u1) xr = ex;
+  if (-yx >= u0 && -yx <= u1) xl = -ex;
+  xr = xr * 1.001f + 0.01f;
+  xl = xl * 1.001f - 0.01f;
+  const float px0 = ceilf(mx + xl - 0.5f), px1 = floorf(mx + xr - 0.5f);
+  if (!(px0 <= px1) || !(px1 >= 0.0f)) return;
+  const float lo = fmaxf(px0, 0.0f);
+  const int t0 = (int)fminf(lo, 1e9f) / tw;
+  const int t1 = (int)fminf(px1, 1e9f) / tw + 1;
+  c0 = max(x0, t0);
+  c1 = min(x1, t1);
+  // skew cut: beta.delta over a tile of this row is linear in the column, so
+  // the tiles it keeps are an interval; half extents widened by half a pixel
+  if (zcut > -1e29f && (bx != 0.0f || by != 0.0f) && c0 < c1) {
+    const float hx = 0.5f * (float)tw, hy = 0.5f * (float)th;
+    const float cy = (float)(row * th) + hy;
+    const float need = zcut * 1.41421356f;                 // beta.delta >= need
+    const float base = skew_box_max(bx, by, hx, cy, mx, my, hx, hy);   // column 0
+    const float step = bx * (float)tw;                      // per column
+    const float slack = 1e-3f * (1.0f + fabsf(base) + fabsf(need) + fabsf(step) * (float)c1);
+    if (step > 0.0f) {
+      const float k = (need - base - slack) / step;
+      if (k > (float)c0) c0 = min(c1, (int)ceilf(fminf(k, 1e9f)));
+    } else if (step < 0.0f) {
+      const float k = (need - base - slack) / step;      // columns <= k survive
+      if (k < (float)(c1 - 1)) c1 = max(c0, (int)floorf(fmaxf(k, -1e9f)) + 1);
+    } else if (base + slack < need) {
+      c1 = c0;
+    }
+  }
+  if (c1 < c0) c1 = c0;
+}
+
 // ---------------------------------------------------------------- wave ops
 // Sum over the 64 lanes of a wave with DPP; the total lands in lane 63.
 // All 64 lanes must be active.

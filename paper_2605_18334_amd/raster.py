@@ -217,9 +217,28 @@ def render(gs: GaussianSet, cams: CameraBatch, opt: _abi.Options | None = None,
     return Frame(gs, cams, opt, geom, bufs, capacity, out_rgb, out_T, out_last)
 
 
-def render_backward(fr: Frame, dL_drgb: torch.Tensor, stream=None) -> dict:
+def densify_stats(gs: "GaussianSet") -> dict:
+    """Zeroed accumulators of the densification statistics (Sec. "Depth-Aware
+    Densification Strategy"): ``uv`` sums the NDC screen-space gradient norm
+    over the views that see a Gaussian, ``z`` keeps the largest |dL/d depth|
+    of its centre, ``count`` counts the views; pass to a backward, which
+    accumulates into them."""
+    dev = gs.mean.device
+    return {"uv": torch.zeros(gs.n, dtype=torch.float32, device=dev),
+            "z": torch.zeros(gs.n, dtype=torch.float32, device=dev),
+            "count": torch.zeros(gs.n, dtype=torch.int32, device=dev)}
+
+
+def _params_grad(grads: dict, densify: dict | None) -> "_abi.ParamsGrad":
+    d = densify or {}
+    return _abi.ParamsGrad(*[_ptr(grads[f]) for f in GaussianSet.FIELDS],
+                           _ptr(d.get("uv")), _ptr(d.get("z")), _ptr(d.get("count")))
+
+
+def render_backward(fr: Frame, dL_drgb: torch.Tensor, stream=None, densify: dict | None = None) -> dict:
     """Gradients of the loss w.r.t. every Gaussian parameter, given dL/dC in
-    the layout of Frame.out_rgb ([3, P])."""
+    the layout of Frame.out_rgb ([3, P]); with ``densify`` (from
+    densify_stats) the densification statistics are accumulated too."""
     lib = load()
     gs = fr.gs
     dL = dL_drgb.contiguous().float()
@@ -228,7 +247,7 @@ def render_backward(fr: Frame, dL_drgb: torch.Tensor, stream=None) -> dict:
                       device=dL.device)
     grads = {f: (None if getattr(gs, f) is None else torch.zeros_like(getattr(gs, f)))
              for f in GaussianSet.FIELDS}
-    pg = _abi.ParamsGrad(*[_ptr(grads[f]) for f in GaussianSet.FIELDS])
+    pg = _params_grad(grads, densify)
     gg = _abi.GeomGrad(_ptr(g2d))
     p = gs.struct()
     check("sgs_render_bwd", lib.sgs_render_bwd(
@@ -383,17 +402,19 @@ class Renderer:
         return self.out_rgb[:, c.pix_base:c.pix_base + c.width * c.height].reshape(3, c.height, c.width)
 
     # ---- backward
-    def backward(self, dL_drgb: torch.Tensor, stream=None) -> dict:
-        """Gradients (fresh zeroed buffers reused across calls) for dL/dC."""
+    def backward(self, dL_drgb: torch.Tensor, stream=None, densify: dict | None = None) -> dict:
+        """Gradients (fresh zeroed buffers reused across calls) for dL/dC;
+        ``densify`` (from densify_stats) accumulates the densification
+        statistics of this backward."""
         gs = self.gs
         if self._bwd is None:
             g2d = torch.empty(int(self.lib.sgs_geom_rec_floats(self.m, int(gs.enhanced))),
                               dtype=torch.float32, device=gs.mean.device)
             grads = {f: (None if getattr(gs, f) is None else torch.empty_like(getattr(gs, f)))
                      for f in GaussianSet.FIELDS}
-            self._bwd = (g2d, grads, _abi.ParamsGrad(*[_ptr(grads[f]) for f in GaussianSet.FIELDS]),
-                         _abi.GeomGrad(_ptr(g2d)))
-        g2d, grads, pg, gg = self._bwd
+            self._bwd = (g2d, grads, _abi.GeomGrad(_ptr(g2d)))
+        g2d, grads, gg = self._bwd
+        pg = _params_grad(grads, densify)
         g2d.zero_()
         for v in grads.values():
             if v is not None:

@@ -89,46 +89,50 @@ def test_preprocess_matches_oracle_projection():
 
 
 # ------------------------------------------------------------------ K2-K4
-def _expected_binning(fr, m, cams):
-    """Stable CPU sort of the instances the GPU's own rects and depths define."""
+def _check_binning(fr, m, cams):
+    """The sorted instance list is exactly a stable sort of the emitted
+    (record, tile) set: keys = (tile << 32 | depth bits of the record), keys
+    non-decreasing, equal keys in ascending record order; each record emits
+    tiles[record] distinct tiles, all inside its rect; ranges match keys."""
+    n = int(_u32(fr.bufs["n_inst"])[0])
+    assert n == fr.n_inst
+    keys = _np(fr.bufs["keys"])[:n].view(np.uint64)
+    vals = _u32(fr.bufs["vals"])[:n]
     rect = _u32(fr.bufs["rect"])[:2 * m].reshape(m, 2)
     tiles = _u32(fr.bufs["tiles"])[:m]
     depth = _np(fr.bufs["depth"])[:m].view(np.uint32).astype(np.uint64)
-    n = m // cams.n_views
-    keys, vals = [], []
-    for rec in np.nonzero(tiles)[0]:
-        v = rec // n
+    tile = (keys >> np.uint64(32)).astype(np.int64)
+    assert n == int(tiles.astype(np.int64).sum())
+    np.testing.assert_array_equal(keys & np.uint64(0xffffffff), depth[vals])
+    assert (keys[1:] >= keys[:-1]).all()
+    eq = keys[1:] == keys[:-1]
+    assert (vals[1:][eq] > vals[:-1][eq]).all()
+    np.testing.assert_array_equal(np.bincount(vals, minlength=m), tiles)
+    pair = vals.astype(np.int64) * (1 << 32) + tile
+    assert len(np.unique(pair)) == n
+    nper = m // cams.n_views
+    for v in range(cams.n_views):
         c = cams.view(v)
-        x0, y0, x1, y1 = rect[rec, 0] & 0xffff, rect[rec, 0] >> 16, rect[rec, 1] & 0xffff, rect[rec, 1] >> 16
-        assert (x1 - x0) * (y1 - y0) == tiles[rec]
-        ty, tx = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
-        t = (c.tile_base + ty * c.tiles_x + tx).reshape(-1).astype(np.uint64)
-        keys.append((t << np.uint64(32)) | depth[rec])
-        vals.append(np.full(t.shape, rec, np.uint32))
-    keys = np.concatenate(keys)
-    vals = np.concatenate(vals)
-    order = np.argsort(keys, kind="stable")
-    return keys[order], vals[order]
+        sel = (vals // nper) == v
+        lt = tile[sel] - c.tile_base
+        tx, ty = lt % c.tiles_x, lt // c.tiles_x
+        r = rect[vals[sel]]
+        assert ((tx >= (r[:, 0] & 0xffff)) & (tx < (r[:, 1] & 0xffff)) &
+                (ty >= (r[:, 0] >> 16)) & (ty < (r[:, 1] >> 16))).all()
+    ranges = _u32(fr.bufs["ranges"]).reshape(-1, 2)
+    starts = np.searchsorted(tile, np.arange(cams.total_tiles), "left")
+    ends = np.searchsorted(tile, np.arange(cams.total_tiles), "right")
+    has = ends > starts
+    np.testing.assert_array_equal(ranges[has, 0], starts[has])
+    np.testing.assert_array_equal(ranges[has, 1], ends[has])
+    assert (ranges[~has, 0] == ranges[~has, 1]).all()
 
 
 @pytest.mark.parametrize("mode", [0, 1])
 def test_bin_sort_bit_exact(mode):
     sc, pose = S.tiny_config()
     fr = _render(sc, pose, sort_mode=mode)
-    m = sc.n
-    ek, ev = _expected_binning(fr, m, fr.cams)
-    n = int(_u32(fr.bufs["n_inst"])[0])
-    assert n == len(ek) == fr.n_inst
-    np.testing.assert_array_equal(_np(fr.bufs["keys"])[:n].view(np.uint64), ek)
-    np.testing.assert_array_equal(_u32(fr.bufs["vals"])[:n], ev)
-    ranges = _u32(fr.bufs["ranges"]).reshape(-1, 2)
-    tile = (ek >> np.uint64(32)).astype(np.int64)
-    for t in range(fr.cams.total_tiles):
-        idx = np.nonzero(tile == t)[0]
-        if len(idx):
-            assert tuple(ranges[t]) == (idx[0], idx[-1] + 1)
-        else:
-            assert ranges[t][0] == ranges[t][1]
+    _check_binning(fr, sc.n, fr.cams)
 
 
 def test_sort_modes_agree_on_large_multiview_input():
@@ -136,6 +140,7 @@ def test_sort_modes_agree_on_large_multiview_input():
     poses = S.spline_poses(3, 3)
     a = _render(sc, poses, sort_mode=0)
     b = _render(sc, poses, sort_mode=1)
+    _check_binning(b, sc.n * 3, b.cams)
     n = a.n_inst
     assert n == b.n_inst and n > 1_000_000
     np.testing.assert_array_equal(_np(a.bufs["keys"])[:n], _np(b.bufs["keys"])[:n])
@@ -147,29 +152,29 @@ def test_sort_modes_agree_on_large_multiview_input():
 
 def test_extent_is_conservative():
     """Every (Gaussian, pixel) pair the oracle lets through (alpha above
-    1/255 by a margin) lies inside that Gaussian's GPU tile rect."""
+    1/255 by a margin) has its (Gaussian, tile) instance in the sorted list."""
     sc, pose = S.tiny_config()
     fr = _render(sc, pose)
-    m = sc.n
-    rect = _u32(fr.bufs["rect"])[:2 * m].reshape(m, 2)
-    tiles = _u32(fr.bufs["tiles"])[:m]
+    n = fr.n_inst
+    keys = _np(fr.bufs["keys"])[:n].view(np.uint64)
+    vals = _u32(fr.bufs["vals"])[:n].astype(np.int64)
+    emitted = set((vals * (1 << 32) + (keys >> np.uint64(32)).astype(np.int64)).tolist())
     cam = O.camera_from_pose(pose)
-    import torch as T
-    with T.no_grad():
+    tx_n = (cam.W + 15) // 16
+    with torch.no_grad():
         pr = O.project(O.to_tensors(sc), 0, cam)
         pix, pc = O.pixel_centres(cam, None)
-        idx = T.nonzero(pr.valid).flatten()
-        bad = 0
+        idx = torch.nonzero(pr.valid).flatten()
+        bad = checked = 0
         for s in range(0, len(pix), 2048):
             at = O.alpha_tilde(pc[s:s + 2048], pr, idx, O.Options()).numpy()
             pp, gg = np.nonzero(at >= (1 / 255) * (1 + 1e-6))
-            g = idx.numpy()[gg]
-            px = pix[s + pp] % cam.W // 16
-            py = pix[s + pp] // cam.W // 16
-            inside = (tiles[g] > 0) & (px >= (rect[g, 0] & 0xffff)) & (px < (rect[g, 1] & 0xffff)) & \
-                     (py >= (rect[g, 0] >> 16)) & (py < (rect[g, 1] >> 16))
-            bad += int((~inside).sum())
-    assert bad == 0
+            g = idx.numpy()[gg].astype(np.int64)
+            t = (pix[s + pp] // cam.W // 16) * tx_n + (pix[s + pp] % cam.W) // 16
+            for key in (g * (1 << 32) + t).tolist():
+                checked += 1
+                bad += key not in emitted
+    assert checked > 10000 and bad == 0
 
 
 # ------------------------------------------------------------------ images
@@ -325,6 +330,59 @@ def test_gradients_match_oracle_enhanced_opacity():
     sc = S.blobs_scene(9, 300, 1, enhanced=True)
     pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 64, 64)
     _grad_check(sc, pose, seed=2)
+
+
+def _densify_check(sc, poses, seed, rtol=1e-2):
+    """Densification statistics fused into the backward, over a batch of
+    views, against the oracle's per-view statistics: uv sums over the views,
+    z is the maximum, count the number of views that see the Gaussian."""
+    P = _P()
+    o = P.default_options()
+    gs = P.GaussianSet.from_scene(sc)
+    cams = P.CameraBatch.from_poses(poses, o)
+    fr = P.render(gs, cams, o)
+    Pt = sum(p.width * p.height for p in poses)
+    g = np.random.default_rng(seed).normal(size=(3, Pt)).astype(np.float32)
+    st = P.densify_stats(gs)
+    P.render_backward(fr, torch.from_numpy(g).cuda(), densify=st)
+    uv, z, cnt = (_np(st[k]).astype(np.float64) for k in ("uv", "z", "count"))
+    ref_uv = np.zeros(sc.n)
+    ref_z = np.zeros(sc.n)
+    reach = np.zeros(sc.n, np.int64)
+    valid = np.zeros(sc.n, np.int64)
+    base = 0
+    for p in poses:
+        n_p = p.width * p.height
+        r = O.densify_stats(sc, p, g[:, base:base + n_p].T.astype(np.float64))
+        base += n_p
+        ref_uv += np.where(r["valid"], r["uv"], 0.0)
+        ref_z = np.maximum(ref_z, r["z"])
+        reach += r["reach"]
+        valid += r["valid"]
+    # counts: every view where alpha reaches 1/255 sees the Gaussian (the
+    # extent is conservative); a view sees only Gaussians it does not cull
+    assert (cnt >= reach).all() and (cnt <= valid).all()
+    assert (cnt > 0).sum() >= 10
+    for name, gv, rv in (("uv", uv, ref_uv), ("z", z, ref_z)):
+        rel = np.linalg.norm(gv - rv) / max(np.linalg.norm(rv), 1e-30)
+        assert rel <= rtol, (name, rel)
+        big = rv > 1e-2 * rv.max()
+        e = np.abs(gv - rv)[big] / rv[big]
+        assert np.quantile(e, 0.99) <= 5 * rtol, (name, np.quantile(e, 0.99))
+    return st
+
+
+def test_densify_stats_match_oracle_one_view():
+    sc = S.blobs_scene(4, 64, 3)
+    _densify_check(sc, [S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 64, 48)], seed=7)
+
+
+def test_densify_stats_accumulate_over_views():
+    sc = S.blobs_scene(31, 400, 2)
+    poses = [S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 64, 48),
+             S.Pose(S.look_at_gl((3.0, 1.0, 7.0), up=(0, 1, 0)), 40, 56)]
+    st = _densify_check(sc, poses, seed=8)
+    assert int(_np(st["count"]).max()) == 2
 
 
 def test_autograd_function_matches_direct_backward():

@@ -442,3 +442,68 @@ def test_gradient_matches_central_differences_enhanced():
     pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 48, 48)
     g = np.random.default_rng(2).normal(size=(48 * 48, 3))
     _fd_check(sc, pose, None, g, n_coords=40, seed=6)
+
+
+def test_densify_stats_match_central_differences():
+    """Densification statistics (Sec. "Depth-Aware Densification Strategy"):
+    g_z is pinned by central differences of L when one centre moves along the
+    camera's depth axis, g_uv by central differences of L in that Gaussian's
+    projected mean (scaled to NDC units by W/2, H/2).  Coordinates whose
+    decisions flip within +-h are skipped."""
+    sc = S.blobs_scene(4, 64, 3)
+    W_, H_ = 64, 48
+    pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), W_, H_)
+    g = np.random.default_rng(11).normal(size=(W_ * H_, 3))
+    st = O.densify_stats(sc, pose, g)
+    cam = O.camera_from_pose(pose)
+    r = cam.w2c[2, :3]
+    opt = O.Options()
+
+    def loss(s, shift=None):
+        with torch.no_grad():
+            pr = O.project(O.to_tensors(s), s.sh_degree, cam, opt, shift)
+            order = O.depth_order(pr)
+            _, pc = O.pixel_centres(cam, None)
+            at = O.alpha_tilde(pc, pr, order, opt)
+            inc = O.inclusion(at, opt)
+            C, _ = O.composite(at, pr.rgb[order], torch.zeros(3, dtype=torch.float64), inc, opt)
+            sig = (order.numpy().tobytes(), inc.numpy().tobytes(), (pr.rgb > 0).numpy().tobytes(),
+                   (at < opt.alpha_max).numpy().tobytes())
+            return float((C.numpy() * g).sum()), sig
+
+    assert st["reach"].sum() >= 20
+    assert not (st["reach"] & ~st["valid"]).any()
+    h = 1e-6
+    cand = np.flatnonzero(st["reach"])
+    checked_z = checked_uv = 0
+    for i in cand[:24]:
+        # depth axis
+        vals = []
+        for sgn in (1, -1):
+            s2 = sc.subset(np.arange(sc.n))
+            m = np.array(s2.mean, dtype=np.float64, order="C")
+            m[:, i] += sgn * h * r
+            s2.mean = m
+            vals.append(loss(s2))
+        if vals[0][1] == vals[1][1]:
+            fd = (vals[0][0] - vals[1][0]) / (2 * h)
+            assert abs(abs(fd) - st["z"][i]) <= 1e-6 * max(1.0, st["z"][i]), (i, fd, st["z"][i])
+            checked_z += 1
+        # projected mean, both axes
+        comp = []
+        for ax in range(2):
+            vals = []
+            for sgn in (1, -1):
+                sh = torch.zeros((sc.n, 2), dtype=torch.float64)
+                sh[i, ax] = sgn * h
+                vals.append(loss(sc, sh))
+            if vals[0][1] != vals[1][1]:
+                break
+            comp.append((vals[0][0] - vals[1][0]) / (2 * h))
+        if len(comp) == 2:
+            uv = math.hypot(comp[0] * W_ / 2, comp[1] * H_ / 2)
+            assert abs(uv - st["uv"][i]) <= 1e-6 * max(1.0, st["uv"][i]), (i, uv, st["uv"][i])
+            checked_uv += 1
+    assert checked_z >= 16 and checked_uv >= 16
+    # the statistics are not trivially zero
+    assert st["z"][cand].max() > 0 and st["uv"][cand].max() > 0
