@@ -145,7 +145,8 @@ typedef struct {
  */
 typedef struct {
   float* rec;              /* [R][M][4]                                     */
-  float* depth;            /* [M] camera-space z (the sort key)             */
+  float* depth;            /* [M] camera-space z (the sort key); all-ones
+                              bits (a NaN) for records without tiles       */
   uint32_t* rect;          /* [M][2] tile rect: (x0 | y0<<16, x1 | y1<<16), half-open */
   uint32_t* tiles;         /* [M] number of tiles covered (0 = culled)      */
   uint32_t* block_off;     /* [sgs_geom_block_entries(N, V)] exclusive prefix of the
@@ -216,9 +217,11 @@ sgs_status sgs_preprocess(const sgs_params* p, const sgs_camera* cams_host,
                           const sgs_camera* cams_dev, int32_t n_views,
                           const sgs_options* opt, const sgs_geom* g, void* stream);
 
-/* Writes, for each record with tiles > 0 and each tile of its rect in
- * row-major order, one instance, sorts them stably by (global tile, depth)
- * (ties keep record order) and extracts tile_ranges[t] = [start, end).
+/* Writes, for each record with tiles > 0 and each tile its extent reaches
+ * (row-major inside its rect: per tile row, the columns whose pixel centres
+ * the evaluation ellipse reaches, cut by the skew half-plane), one instance,
+ * sorts them stably by (global tile, depth) (ties keep record order) and
+ * extracts tile_ranges[t] = [start, end).
  *  keys          [inst_capacity] u64 (tile<<32 | float bits of depth), sorted;
  *                may be NULL (then not written) in sort_mode 1.
  *  vals          [inst_capacity] u32 record index m, sorted.
@@ -226,6 +229,8 @@ sgs_status sgs_preprocess(const sgs_params* p, const sgs_camera* cams_host,
  *  n_inst_dev    [1] u32 device: receives the instance count.  Instances past
  *                inst_capacity are dropped; the caller compares the count with
  *                the capacity after the fact (graph-friendly, no host sync).
+ *                0xffffffff marks an internal failure (a sort look-back that
+ *                did not complete in bounded time): the outputs are invalid.
  *  sched         optional (NULL): if sched->tile_order is set, it is written.
  *  scratch       device, >= sgs_bin_sort_scratch_bytes(...).
  * EINVAL / ECAPACITY for bad sizes. */

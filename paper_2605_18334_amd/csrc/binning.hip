@@ -9,26 +9,30 @@
 // 8 ballots per key (lanes hold consecutive keys, so ranks are stable),
 // publishes its per-digit counts, and finds its global offsets by looking
 // back over the published counts of the blocks before it (decoupled
-// look-back).  The look-back spin is bounded: it never hangs, it flags an
-// error word instead.  Keys are staged in LDS in digit order so that
-// consecutive lanes write consecutive addresses.
+// look-back, eight predecessors read at once).  The look-back spin is
+// bounded: it never hangs; it flags an error word and marks the instance
+// count invalid (0xffffffff) instead.  Keys are staged in LDS in digit order
+// so that consecutive lanes write consecutive addresses.  All look-back
+// state, histograms and block counters of one bin_sort call are zeroed by a
+// single fill kernel at its start.
 //
 // Two orders of work give the same sorted list (by tile, then depth, then
 // record index):
 //   mode 0: 64-bit keys (tile << 32 | depth bits), written per record in
 //           record order, sorted over 32 + tile bits;
-//   mode 1: the M records are first sorted by depth (32-bit keys); the
-//           instances are expanded in that order with 32-bit tile keys (load
-//           balanced: one block per 2048 instances, not one thread per
-//           record), then sorted over the tile bits only.  Stability keeps
-//           depth order and index order inside a tile.  Far fewer bytes move.
+//   mode 1: the M records are first sorted by depth (32-bit keys: the depth
+//           buffer's own bits, all-ones for records without tiles, so those
+//           sort last); a single-pass scan (decoupled look-back) gives each
+//           record its instance offset in that order; the instances are
+//           expanded in that order with 32-bit tile keys (load balanced: one
+//           block per 2048 instances, not one thread per record), then
+//           sorted over the tile bits only.  Stability keeps depth order and
+//           index order inside a tile.  Far fewer bytes move.
 #include <algorithm>
 
 #include "sgs_dev.h"
 
 namespace sgs {
-
-sgs_status launch_scan_blocks(const uint32_t* in, uint32_t* out, int64_t nb, hipStream_t s);
 
 constexpr int RS_T = 256;          // threads per block
 constexpr int RS_IPT = 16;         // keys per thread
@@ -37,6 +41,8 @@ constexpr int RS_MAX_PASSES = 8;
 constexpr uint64_t ST_AGG = 1ull << 32;    // status: block's own digit count
 constexpr uint64_t ST_INC = 2ull << 32;    // status: inclusive prefix over blocks
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
+constexpr int LB_W = 8;            // look-back: predecessor statuses read at once
+constexpr uint32_t N_INVALID = 0xffffffffu;   // instance count after a failed look-back
 
 __device__ __forceinline__ uint32_t count_of(const uint32_t* n_dev, uint32_t n_host, uint32_t cap) {
   const uint32_t n = n_dev ? *n_dev : n_host;
@@ -99,6 +105,9 @@ __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, co
     if (h[p][t]) atomicAdd(&ghist[p * 256 + t], h[p][t]);
 }
 
+// vin == nullptr: the values are the input positions (0, 1, 2, ...).
+// On a look-back that does not finish in bounded time: err |= 1 and, when
+// n_fold is given, *n_fold = N_INVALID.
 template <typename K>
 __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
                                                   const uint32_t* __restrict__ vin,
@@ -107,7 +116,7 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
                                                   uint32_t cap, int shift, int nbits,
                                                   const uint32_t* __restrict__ ghist,
                                                   uint64_t* status, uint32_t* counter,
-                                                  uint32_t* err) {
+                                                  uint32_t* err, uint32_t* n_fold) {
   __shared__ uint32_t wc[4][256];
   __shared__ uint32_t lstart[256];
   __shared__ uint32_t goff[256];
@@ -134,14 +143,25 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
     const uint64_t idx = base + (uint64_t)i * 64;
     const bool valid = idx < n;
     key[i] = valid ? kin[idx] : (K)0;
-    val[i] = valid ? vin[idx] : 0u;
+    val[i] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
+  }
+  // rank inside the wave: the lowest lane of each digit's peers reserves
+  // their slots with one LDS atomic (the atomics of the RS_IPT rounds are in
+  // flight together), then every lane fetches its leader's base
+  uint32_t lead_base[RS_IPT];
+  int leader[RS_IPT];
+#pragma unroll
+  for (int i = 0; i < RS_IPT; ++i) {
+    const bool valid = base + (uint64_t)i * 64 < n;
     const uint32_t d = digit_of<K>(key[i], shift, mask);
     const uint64_t peers = match_digit(d, valid, nbits);
-    const uint32_t r = (uint32_t)__popcll(peers & lt);
-    const uint32_t c = wc[w][d];
-    rank[i] = c + r;
-    if (valid && r == 0) wc[w][d] = c + (uint32_t)__popcll(peers);
+    rank[i] = (uint32_t)__popcll(peers & lt);
+    leader[i] = peers ? __builtin_ctzll(peers) : lane;
+    lead_base[i] = 0;
+    if (valid && rank[i] == 0) lead_base[i] = atomicAdd(&wc[w][d], (uint32_t)__popcll(peers));
   }
+#pragma unroll
+  for (int i = 0; i < RS_IPT; ++i) rank[i] += __shfl(lead_base[i], leader[i]);
   __syncthreads();
   const uint32_t c0 = wc[0][t], c1 = wc[1][t], c2 = wc[2][t], c3 = wc[3][t];
   const uint32_t tot = c0 + c1 + c2 + c3;
@@ -159,23 +179,44 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
     goff[t] = ds;
   } else {
     __hip_atomic_store(st, ST_AGG | (uint64_t)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // walk back LB_W predecessors at a time (their loads are in flight
+    // together), summing published counts until an inclusive prefix
     uint32_t excl = 0, spins = 0;
-    uint32_t bp = b - 1;
-    for (;;) {
-      const uint64_t s = __hip_atomic_load(status + (uint64_t)bp * 256 + t, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-      const uint64_t f = s & ~0xffffffffull;
-      if (f == 0) {
+    int64_t q0 = (int64_t)b - 1;
+    bool done = false;
+    while (!done) {
+      uint64_t sw[LB_W];
+#pragma unroll
+      for (int k = 0; k < LB_W; ++k) {
+        const int64_t q = q0 - k;
+        sw[k] = q >= 0 ? __hip_atomic_load(status + (uint64_t)q * 256 + t, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT)
+                       : ST_INC;   // block 0 publishes an inclusive prefix: never reached
+      }
+      int adv = 0;
+      bool stop = false;
+#pragma unroll
+      for (int k = 0; k < LB_W; ++k) {
+        if (!stop) {
+          const uint64_t f = sw[k] & ~0xffffffffull;
+          if (f == 0) {
+            stop = true;             // not yet published: reload from here
+          } else {
+            excl += (uint32_t)sw[k];
+            ++adv;
+            if (f == ST_INC) stop = done = true;
+          }
+        }
+      }
+      q0 -= adv;
+      if (!done && adv == 0) {
         if (++spins > SPIN_LIMIT) {
           atomicOr(err, 1u);
+          if (n_fold) atomicExch(n_fold, N_INVALID);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        continue;
       }
-      excl += (uint32_t)s;
-      if (f == ST_INC || bp == 0) break;
-      --bp;
     }
     __hip_atomic_store(st, ST_INC | (uint64_t)(excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     goff[t] = ds + excl;
@@ -226,6 +267,8 @@ struct DupArgs {
   uint32_t* n_inst;
   const uint32_t* order; // mode 1: records in depth order
   const uint32_t* offs;  // mode 1: exclusive instance offset of order[j]
+  uint32_t* ghist;       // mode 1: digit histograms [hpasses][256] of the tile keys
+  int32_t hpasses;
   int64_t m;
 };
 
@@ -251,11 +294,12 @@ __global__ void __launch_bounds__(256) k_duplicate64(DupArgs a) {
   const sgs_camera& cam = a.cams[v];
   const uint64_t lo = (uint64_t)__float_as_uint(a.depth[m]);
   const float4 q0 = a.rec0[m], q1 = a.rec1[m], q2 = a.rec2[m];
-  const float zc = record_zcut(a, q1);
+  Span sp;
+  span_setup(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, record_zcut(a, q1), sp);
   uint32_t k = off;
   for (int y = y0; y < y1; ++y) {
     int c0, c1;
-    row_span(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, zc, y, a.tile_w, a.tile_h, x0, x1, c0, c1);
+    span_row(sp, y, a.tile_w, a.tile_h, x0, x1, c0, c1);
     for (int x = c0; x < c1 && k < off + cnt; ++x, ++k)
       if (k < a.cap) {
         const uint64_t tile = (uint64_t)(cam.tile_base + y * cam.tiles_x + x);
@@ -265,125 +309,223 @@ __global__ void __launch_bounds__(256) k_duplicate64(DupArgs a) {
   }
 }
 
-// Mode 1, step 1: depth keys of all records (culled ones sort last).
-__global__ void __launch_bounds__(256) k_depth_keys(const float* __restrict__ depth,
-                                                    const uint32_t* __restrict__ tiles, int64_t m,
-                                                    uint32_t* __restrict__ k, uint32_t* __restrict__ v) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= m) return;
-  k[i] = tiles[i] ? __float_as_uint(depth[i]) : 0xffffffffu;
-  v[i] = (uint32_t)i;
-}
+// Mode 1, step 2: exclusive instance offset of every record in depth order,
+// one pass: each block of SO_TILE entries scans its tile counts, publishes
+// its total and looks back over the published totals of the blocks before
+// it, 64 at a time (one per lane of wave 0).  The block that takes the last
+// id writes the instance count (N_INVALID after a failed look-back, here or
+// in the depth sort; saturated at 2^32 - 2).
+constexpr int SO_IPT = 8;
+constexpr int SO_TILE = 256 * SO_IPT;
 
-// Mode 1, step 2: per-block sums of tile counts in depth order.
-__global__ void __launch_bounds__(256) k_sorted_block_sums(const uint32_t* __restrict__ order,
-                                                           const uint32_t* __restrict__ tiles,
-                                                           int64_t m, uint32_t* __restrict__ sums) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const uint32_t o = j < m ? order[j] : 0u;
-  uint32_t c = (j < m && o < (uint64_t)m) ? tiles[o] : 0u;
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  __shared__ uint32_t ws[4];
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
-}
-
-// Mode 1, step 3: exclusive instance offset of every record in depth order.
 __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restrict__ order,
-                                                        const uint32_t* __restrict__ tiles, int64_t m,
-                                                        const uint32_t* __restrict__ block_off,
-                                                        int64_t nb, uint32_t* __restrict__ offs,
-                                                        uint32_t* __restrict__ n_inst) {
+                                                        const uint32_t* __restrict__ tiles,
+                                                        int64_t m, uint32_t* __restrict__ offs,
+                                                        uint32_t* __restrict__ n_inst,
+                                                        uint64_t* status, uint32_t* counter,
+                                                        uint32_t* err) {
+  constexpr uint64_t VMASK = (1ull << 62) - 1;   // 62-bit running totals, 2 flag bits
+  constexpr uint64_t F_AGG = 1ull << 62, F_INC = 2ull << 62;
   __shared__ uint32_t ws[4];
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const uint32_t o = j < m ? order[j] : 0u;
-  const uint32_t c = (j < m && o < (uint64_t)m) ? tiles[o] : 0u;
-  const uint32_t e = block_excl_scan256(c, ws);
-  if (j < m) offs[j] = block_off[blockIdx.x] + e;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *n_inst = block_off[nb];
+  __shared__ uint32_t s_bid, s_tot;
+  __shared__ uint64_t s_excl;
+  const int t = threadIdx.x, lane = t & 63;
+  if (t == 0) s_bid = atomicAdd(counter, 1u);
+  __syncthreads();
+  const uint32_t b = s_bid;
+  const int64_t j0 = (int64_t)b * SO_TILE + (int64_t)t * SO_IPT;
+  uint32_t c[SO_IPT];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < SO_IPT; ++k) {
+    const int64_t j = j0 + k;
+    const uint32_t o = j < m ? order[j] : 0xffffffffu;
+    c[k] = o < (uint64_t)m ? tiles[o] : 0u;
+    sum += c[k];
+  }
+  const uint32_t e = block_excl_scan256(sum, ws);
+  if (t == 255) s_tot = e + sum;
+  __syncthreads();
+  const uint64_t tot = s_tot;
+  if (t < 64) {
+    uint64_t excl = 0;
+    uint64_t* st = status + b;
+    if (b == 0) {
+      if (t == 0) __hip_atomic_store(st, F_INC | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (t == 0) __hip_atomic_store(st, F_AGG | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int64_t q0 = (int64_t)b - 1;
+      uint32_t spins = 0;
+      for (;;) {
+        const int64_t q = q0 - lane;
+        const uint64_t sv = q >= 0 ? __hip_atomic_load(status + q, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)
+                                   : F_INC;
+        const uint64_t f = sv & ~VMASK;
+        const uint64_t ready = __ballot(f != 0);
+        const uint64_t inc = __ballot(f == F_INC);
+        const int nr = ready == ~0ull ? 64 : __builtin_ctzll(~ready);   // ready prefix
+        const int fi = inc ? __builtin_ctzll(inc) : 64;                  // first inclusive
+        const int take = fi < nr ? fi + 1 : nr;
+        uint64_t v = lane < take ? (sv & VMASK) : 0ull;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        excl += v;
+        if (fi < nr) break;
+        q0 -= take;
+        if (take == 0) {
+          if (++spins > SPIN_LIMIT) {
+            if (lane == 0) {
+              atomicOr(err, 1u);
+              atomicExch(n_inst, N_INVALID);
+            }
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      if (t == 0)
+        __hip_atomic_store(st, F_INC | ((excl + tot) & VMASK), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (t == 0) s_excl = excl;
+  }
+  __syncthreads();
+  uint64_t run = s_excl + e;
+#pragma unroll
+  for (int k = 0; k < SO_IPT; ++k) {
+    const int64_t j = j0 + k;
+    if (j < m) offs[j] = (uint32_t)run;
+    run += c[k];
+  }
+  if (b == gridDim.x - 1 && t == 0) {
+    const uint64_t total = s_excl + tot;
+    atomicMax(n_inst, *err ? N_INVALID : (total < N_INVALID ? (uint32_t)total : N_INVALID - 1u));
+  }
 }
 
-// Mode 1, step 4: load-balanced expansion.  Block b writes instances
-// [b*EX_TILE, (b+1)*EX_TILE).  Records in depth order with at least one tile
-// come first (culled ones sort last), so the records that own this range are
-// at most EX_TILE + 1 consecutive entries starting at the last record whose
-// offset is <= the first instance; their offsets and ids are staged in LDS
-// and each thread walks its EX_PT consecutive instances.
-constexpr int EX_PT = 8;
-constexpr int EX_TILE = 256 * EX_PT;
+// Mode 1, step 3: load-balanced expansion.  Block b writes instances
+// [o0, o1) = [b*EX_TILE, (b+1)*EX_TILE).  Records in depth order with at least
+// one tile come first (culled ones sort last), so the records that own this
+// range are at most EX_TILE + 1 consecutive entries starting at the last
+// record j0 whose offset is <= o0.  The block enumerates (record, tile row)
+// items of those records in order, 256 at a time: each thread computes one
+// row's span once, a block scan turns the row counts into instance offsets
+// (a running sum from offs[j0]: records' instances are their rows' in order),
+// and each thread writes the instances of its row that fall in [o0, o1).
+// The digit histograms of the tile-key sort are counted here as well: a
+// row's instances have consecutive tile keys, so the low digit is counted
+// per instance and every higher digit once per run of equal high bits.
+constexpr int EX_TILE = 2048;
+constexpr int EX_W = EX_TILE + 1;
+
+// Exclusive scan of one value per thread; *tot receives the block total.
+__device__ __forceinline__ uint32_t block_scan256_total(uint32_t x, uint32_t* ws4, uint32_t* tot) {
+  const uint32_t e = block_excl_scan256(x, ws4);
+  if (threadIdx.x == 255) *tot = e + x;
+  __syncthreads();
+  return e;
+}
 
 __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
-  __shared__ uint32_t s_off[EX_TILE + 1];
-  __shared__ uint32_t s_rec[EX_TILE + 1];
-  __shared__ uint32_t s_j0, s_w;
+  __shared__ uint32_t s_rec[EX_W];
+  __shared__ uint32_t s_rows[EX_W + 1];   // exclusive prefix of the records' rect rows
+  __shared__ uint32_t hist[4][256];
+  __shared__ uint32_t ws[4];
+  __shared__ uint32_t s_tot, s_j0, s_w;
   const uint32_t total = *a.n_inst;
   const uint32_t n = total < a.cap ? total : a.cap;
   const uint64_t o0 = (uint64_t)blockIdx.x * EX_TILE;
   if (o0 >= n) return;
+  const uint64_t o1 = min(o0 + (uint64_t)EX_TILE, (uint64_t)n);
   const int t = threadIdx.x;
+  for (int k = t; k < 4 * 256; k += 256) (&hist[0][0])[k] = 0u;
+  // last j with offs[j] <= o0 (offs is non-decreasing, offs[0] = 0): a
+  // 256-way search, one sample per thread and round (about log_256 M rounds)
+  uint64_t jlo = 0, jhi = (uint64_t)a.m;   // offs[jlo] <= o0, answer in [jlo, jhi)
+  while (jhi - jlo > 1) {
+    const uint64_t step = (jhi - jlo + 255) / 256;
+    const uint64_t idx = jlo + (uint64_t)t * step;
+    const int below = __syncthreads_count(idx < jhi && a.offs[idx] <= o0);   // >= 1 (t = 0)
+    const uint64_t nlo = jlo + (uint64_t)(below - 1) * step;
+    jhi = min(jhi, nlo + step);
+    jlo = nlo;
+  }
   if (t == 0) {
-    // last j with offs[j] <= o0 (offs is non-decreasing, offs[0] = 0)
-    uint64_t lo = 0, hi = (uint64_t)a.m;   // offs[lo] <= o0, answer in [lo, hi)
-    while (hi - lo > 1) {
-      const uint64_t mid = (lo + hi) >> 1;
-      if (a.offs[mid] <= o0) lo = mid; else hi = mid;
-    }
-    s_j0 = (uint32_t)lo;
-    s_w = (uint32_t)min((uint64_t)(EX_TILE + 1), (uint64_t)a.m - lo);
+    s_j0 = (uint32_t)jlo;
+    s_w = (uint32_t)min((uint64_t)EX_W, (uint64_t)a.m - jlo);
   }
   __syncthreads();
   const uint32_t j0 = s_j0, W = s_w;
-  for (uint32_t k = t; k < W; k += 256) {
-    s_off[k] = a.offs[j0 + k];
-    s_rec[k] = a.order[j0 + k];
+  // rows of the window's records (records starting at or past o1: none)
+  uint32_t carry = 0;
+  for (uint32_t c = 0; c < W; c += 256) {
+    const uint32_t k = c + t;
+    uint32_t rows = 0;
+    if (k < W) {
+      const uint32_t rec = a.order[j0 + k];
+      s_rec[k] = rec;
+      if ((k == 0 || a.offs[j0 + k] < o1) && rec < (uint64_t)a.m && a.tiles[rec] > 0) {
+        const uint2 r = reinterpret_cast<const uint2*>(a.rect)[rec];
+        rows = (r.y >> 16) - min(r.x >> 16, r.y >> 16);
+      }
+    }
+    const uint32_t e = block_scan256_total(rows, ws, &s_tot);
+    if (k < W) s_rows[k] = carry + e;
+    carry += s_tot;
+    __syncthreads();
   }
+  if (t == 0) s_rows[W] = carry;
   __syncthreads();
-  uint64_t o = o0 + (uint64_t)t * EX_PT;
-  if (o >= n) return;
-  // first record of this thread: last k with s_off[k] <= o
-  uint32_t lo = 0, hi = W;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (s_off[mid] <= o) lo = mid; else hi = mid;
-  }
-  uint32_t k = lo;
-  uint32_t rec = 0xffffffffu, tb = 0, tx = 0, cum = 0;
-  int x0 = 0, x1 = 0, y1 = 0, row = 0, c0 = 0, c1 = 0;
-  float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
-  float zc = -1e30f;
-  for (int e = 0; e < EX_PT; ++e, ++o) {
-    if (o >= n) break;
-    while (k + 1 < W && s_off[k + 1] <= o) ++k;
-    if (s_rec[k] != rec) {
-      rec = s_rec[k];
+  const uint32_t R = carry;
+  uint64_t run = a.offs[j0];    // instance offset of the next item
+  for (uint32_t base = 0; base < R && run < o1; base += 256) {
+    const uint32_t i = base + t;
+    uint32_t cnt = 0, rec = 0, tk = 0;
+    int c0 = 0;
+    if (i < R) {
+      // record of item i: last k with s_rows[k] <= i
+      uint32_t lo = 0, hi = W;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_rows[mid] <= i) lo = mid; else hi = mid;
+      }
+      rec = s_rec[lo];
       const uint64_t rm = rec < (uint64_t)a.m ? rec : 0;
       const uint2 r = reinterpret_cast<const uint2*>(a.rect)[rm];
-      x0 = r.x & 0xffffu;
-      x1 = r.y & 0xffffu;
-      row = r.x >> 16;
-      y1 = r.y >> 16;
-      q0 = a.rec0[rm];
-      q1 = a.rec1[rm];
-      q2 = a.rec2[rm];
+      const int x0 = r.x & 0xffffu, x1 = r.y & 0xffffu;
+      const int row = (int)(r.x >> 16) + (int)(i - s_rows[lo]);
+      const float4 q0 = a.rec0[rm], q1 = a.rec1[rm], q2 = a.rec2[rm];
+      Span sp;
+      span_setup(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, record_zcut(a, q1), sp);
+      int c1;
+      span_row(sp, row, a.tile_w, a.tile_h, x0, x1, c0, c1);
+      cnt = (uint32_t)(c1 - c0);
       const sgs_camera& cam = a.cams[rm / (uint64_t)a.n];
-      tb = (uint32_t)cam.tile_base;
-      tx = (uint32_t)cam.tiles_x;
-      cum = 0;
-      zc = record_zcut(a, q1);
-      row_span(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, zc, row, a.tile_w, a.tile_h, x0, x1, c0, c1);
+      tk = (uint32_t)cam.tile_base + (uint32_t)row * (uint32_t)cam.tiles_x;
     }
-    // instance q of this record: walk the rows of its rect until q falls in one
-    const uint32_t q = (uint32_t)(o - s_off[k]);
-    while (q >= cum + (uint32_t)(c1 - c0) && row + 1 < y1) {
-      cum += (uint32_t)(c1 - c0);
-      ++row;
-      row_span(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, zc, row, a.tile_w, a.tile_h, x0, x1, c0, c1);
+    const uint32_t e = block_scan256_total(cnt, ws, &s_tot);
+    const uint64_t start = run + e;
+    const uint64_t lo = max(start, o0), hi = min(start + cnt, o1);
+    const uint32_t tlo = tk + (uint32_t)c0 + (uint32_t)(lo - start);
+    for (uint64_t o = lo; o < hi; ++o) {
+      const uint32_t key = tlo + (uint32_t)(o - lo);
+      a.keys32[o] = key;
+      a.vals[o] = rec;
+      atomicAdd(&hist[0][key & 255u], 1u);
     }
-    const uint32_t x = min((uint32_t)(c0 + (q - cum)), (uint32_t)max(x1 - 1, 0));
-    a.keys32[o] = tb + (uint32_t)row * tx + x;
-    a.vals[o] = rec;
+    if (a.hpasses > 1 && hi > lo) {
+      const uint32_t thi = tlo + (uint32_t)(hi - lo);
+      for (uint32_t seg = tlo; seg < thi;) {
+        const uint32_t end = min(thi, (seg | 255u) + 1u);
+        for (int p = 1; p < a.hpasses; ++p) atomicAdd(&hist[p][(seg >> (8 * p)) & 255u], end - seg);
+        seg = end;
+      }
+    }
+    run += s_tot;
+    __syncthreads();
   }
+  for (int p = 0; p < a.hpasses; ++p)
+    if (hist[p][t]) atomicAdd(&a.ghist[p * 256 + t], hist[p][t]);
 }
 
 // 64-bit keys from sorted tile keys and the record depths (mode 1, optional).
@@ -398,9 +540,18 @@ __global__ void __launch_bounds__(256) k_make_keys64(const uint32_t* __restrict_
   out[i] = ((uint64_t)tk[i] << 32) | (v < m ? (uint64_t)__float_as_uint(depth[v]) : 0ull);
 }
 
-__global__ void __launch_bounds__(256) k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
-  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = v;
+// Zeroes up to ZL_MAX regions (words), one grid row per region.
+constexpr int ZL_MAX = 8;
+struct ZeroList {
+  uint32_t* p[ZL_MAX];
+  uint64_t n[ZL_MAX];
+};
+
+__global__ void __launch_bounds__(256) k_zero(ZeroList z) {
+  uint32_t* p = z.p[blockIdx.y];
+  const uint64_t n = z.n[blockIdx.y];
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+    p[i] = 0u;
 }
 
 template <typename K>
@@ -439,53 +590,55 @@ static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 static int rs_passes(int bits) { return (bits + 7) / 8; }
 static uint64_t rs_blocks(uint64_t cap) { return std::max<uint64_t>(1, cdiv(cap, RS_TILE)); }
 
-// Scratch of one sort of up to `cap` keys, laid out contiguously so that one
-// fill zeroes it: digit histograms [8][256] u32, look-back status words
-// [8][blocks][256] u64, then block counters [8] and an error word.
-static size_t rs_hist_words() { return (size_t)RS_MAX_PASSES * 256; }
-static size_t rs_status_words(uint64_t cap) { return (size_t)RS_MAX_PASSES * rs_blocks(cap) * 256 * 2; }
-static size_t rs_scratch_bytes(uint64_t cap) {
-  return (rs_hist_words() + rs_status_words(cap) + 64) * 4;
+// Scratch of one sort of up to `cap` keys in `passes` passes, contiguous so
+// that it is zeroed as one region: block counters [64] (one per pass), digit
+// histograms [passes][256] u32, look-back status [passes][blocks][256] u64.
+static size_t rs_words(uint64_t cap, int passes) {
+  return 64 + (size_t)passes * 256 + (size_t)passes * rs_blocks(cap) * 256 * 2;
 }
 
 struct RsScratch {
+  uint32_t* counters;
   uint32_t* ghist;
   uint64_t* status;
-  uint32_t* counters;   // [RS_MAX_PASSES] block counters, error word at [RS_MAX_PASSES]
+  uint32_t* err;        // shared error word of the bin_sort call
+  uint32_t* n_fold;     // instance count to mark N_INVALID on failure, or null
 };
 
-static RsScratch rs_carve(char* p, uint64_t cap) {
+static RsScratch rs_carve(uint32_t* p, int passes, uint32_t* err, uint32_t* n_fold) {
   RsScratch s;
-  s.ghist = reinterpret_cast<uint32_t*>(p);
-  s.status = reinterpret_cast<uint64_t*>(p + rs_hist_words() * 4);
-  s.counters = reinterpret_cast<uint32_t*>(p + (rs_hist_words() + rs_status_words(cap)) * 4);
+  s.counters = p;
+  s.ghist = p + 64;
+  s.status = reinterpret_cast<uint64_t*>(p + 64 + (size_t)passes * 256);
+  s.err = err;
+  s.n_fold = n_fold;
   return s;
 }
 
-// Sorts (k[src], v[src]) by bits [0, bits), one kernel per 8-bit pass,
-// alternating buffers; the result is in buffer (src + passes) % 2.
+// Sorts by bits [0, bits), one kernel per 8-bit pass.  Pass 0 reads
+// (kin, vin) (vin == nullptr: values are the positions); the result lands in
+// (kb[0], vb[0]).  kin may be kb[passes & 1] (sorting in place) or another
+// buffer.  The scratch must be zero, except that with hist_done its digit
+// histograms already hold the counts of the keys.
 template <typename K>
-static sgs_status radix_sort(K* kb[2], uint32_t* vb[2], int src, const uint32_t* n_dev,
-                             uint32_t n_host, uint64_t cap, int bits, RsScratch sc, hipStream_t s) {
+static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32_t* vb[2],
+                             const uint32_t* n_dev, uint32_t n_host, uint64_t cap, int bits,
+                             RsScratch sc, hipStream_t s, bool hist_done = false) {
   const uint64_t blocks = rs_blocks(cap);
   const int passes = rs_passes(bits);
-  // zero the histograms and the status words of the passes used
-  const uint64_t zw = rs_hist_words() + (uint64_t)passes * blocks * 256 * 2;
-  k_fill_u32<<<(unsigned)cdiv(zw, 256), 256, 0, s>>>(sc.ghist, zw, 0u);
-  SGS_LAUNCH_CHECK();
-  k_fill_u32<<<1, 256, 0, s>>>(sc.counters, 64, 0u);
-  SGS_LAUNCH_CHECK();
-  k_os_hist<K><<<(unsigned)blocks, RS_T, 0, s>>>(kb[src], n_dev, n_host, (uint32_t)cap, bits, sc.ghist);
-  SGS_LAUNCH_CHECK();
-  int cur = src;
+  if (!hist_done) {
+    k_os_hist<K><<<(unsigned)blocks, RS_T, 0, s>>>(kin, n_dev, n_host, (uint32_t)cap, bits, sc.ghist);
+    SGS_LAUNCH_CHECK();
+  }
   for (int p = 0; p < passes; ++p) {
     const int nb = std::min(8, bits - 8 * p);
+    const int dst = (passes - 1 - p) & 1;
+    const K* ki = p == 0 ? kin : kb[dst ^ 1];
+    const uint32_t* vi = p == 0 ? vin : vb[dst ^ 1];
     k_os_pass<K><<<(unsigned)blocks, RS_T, 0, s>>>(
-        kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n_dev, n_host, (uint32_t)cap, 8 * p, nb,
-        sc.ghist + p * 256, sc.status + (size_t)p * blocks * 256, sc.counters + p,
-        sc.counters + RS_MAX_PASSES);
+        ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, 8 * p, nb, sc.ghist + p * 256,
+        sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold);
     SGS_LAUNCH_CHECK();
-    cur ^= 1;
   }
   return SGS_OK;
 }
@@ -496,48 +649,100 @@ static int tile_bits(int64_t total_tiles) {
   return std::max(b, 1);
 }
 
-static uint64_t rs_capacity(int64_t m, int64_t cap, int64_t total_tiles, int mode) {
-  return std::max<uint64_t>(std::max<uint64_t>((uint64_t)cap, mode == 1 ? (uint64_t)m : 0),
-                            (uint64_t)total_tiles);
+// Layout of the scratch of one bin_sort call.  Computed from a base address
+// (0 to size it): every buffer is 256-byte aligned.
+struct BinLayout {
+  uint32_t* misc;                 // [64]: error word at 0
+  uint32_t* rs_main;              // main sort (64-bit keys, or tile keys)
+  int main_passes;
+  uint32_t* rs_depth;             // mode 1: depth presort
+  uint32_t* rs_order;             // tile order sort
+  uint32_t* so_status;            // mode 1: offsets scan: [64] counter, then u64 status
+  size_t so_words;
+  uint32_t* ok[2];                // tile order keys
+  uint32_t* ov_alt;               // tile order values (alternate)
+  uint64_t* kalt;                 // mode 0: alternate 64-bit keys
+  uint32_t* valt;                 // alternate values
+  uint32_t* dk[2];                // mode 1: depth keys
+  uint32_t* dv[2];                // mode 1: record order
+  uint32_t* offs;                 // mode 1: per-record instance offsets
+  uint32_t* tk[2];                // mode 1: tile keys
+  size_t bytes;
+};
+
+static BinLayout bin_layout(uintptr_t base, int64_t m, int64_t cap, int64_t total_tiles, int mode) {
+  BinLayout L = {};
+  uintptr_t p = (base + 255) & ~(uintptr_t)255;
+  const uintptr_t p0 = p;
+  auto take = [&](size_t bytes) { uintptr_t r = p; p += align_up(bytes); return r; };
+  const uint64_t T = (uint64_t)total_tiles, C = (uint64_t)cap, M = (uint64_t)m;
+  const int tb = tile_bits(total_tiles);
+  L.main_passes = rs_passes(mode == 0 ? 32 + tb : tb);
+  L.misc = reinterpret_cast<uint32_t*>(take(64 * 4));
+  L.rs_main = reinterpret_cast<uint32_t*>(take(rs_words(C, L.main_passes) * 4));
+  L.rs_order = reinterpret_cast<uint32_t*>(take(rs_words(T, 2) * 4));
+  L.ok[0] = reinterpret_cast<uint32_t*>(take(T * 4));
+  L.ok[1] = reinterpret_cast<uint32_t*>(take(T * 4));
+  L.ov_alt = reinterpret_cast<uint32_t*>(take(T * 4));
+  if (mode == 0) {
+    L.kalt = reinterpret_cast<uint64_t*>(take(C * 8));
+    L.valt = reinterpret_cast<uint32_t*>(take(C * 4));
+  } else {
+    L.rs_depth = reinterpret_cast<uint32_t*>(take(rs_words(M, 4) * 4));
+    L.so_words = 64 + 2 * (size_t)cdiv(std::max<uint64_t>(M, 1), SO_TILE);
+    L.so_status = reinterpret_cast<uint32_t*>(take(L.so_words * 4));
+    for (int k = 0; k < 2; ++k) {
+      L.dk[k] = reinterpret_cast<uint32_t*>(take(M * 4));
+      L.dv[k] = reinterpret_cast<uint32_t*>(take(M * 4));
+      L.tk[k] = reinterpret_cast<uint32_t*>(take(C * 4));
+    }
+    L.offs = reinterpret_cast<uint32_t*>(take(M * 4));
+    L.valt = reinterpret_cast<uint32_t*>(take(C * 4));
+  }
+  L.bytes = (size_t)(p - p0) + 256;
+  return L;
 }
 
 size_t bin_sort_scratch_bytes(int64_t m, int64_t cap, int64_t total_tiles, int mode) {
-  const uint64_t rs_cap = rs_capacity(m, cap, total_tiles, mode);
-  size_t bytes = align_up(rs_scratch_bytes(rs_cap));
-  bytes += 3 * align_up((size_t)total_tiles * 4);            // tile-order keys x2, vals alt
-  if (mode == 0) {
-    bytes += align_up((size_t)cap * 8) + align_up((size_t)cap * 4);
-  } else {
-    bytes += 4 * align_up((size_t)m * 4);                    // depth keys/vals x2
-    bytes += align_up((cdiv(m, 256) + 1) * 4);               // sorted block offsets
-    bytes += align_up((size_t)m * 4);                        // per-record offsets
-    bytes += 2 * align_up((size_t)cap * 4) + align_up((size_t)cap * 4);  // tile keys x2, vals alt
-  }
-  return bytes + 256;
+  return bin_layout(0, m, cap, total_tiles, mode).bytes;
 }
 
 sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_camera* cams_dev,
                            int32_t n_views, int64_t total_tiles, const sgs_options* opt,
                            int64_t cap, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                            uint32_t* n_inst, uint32_t* tile_order, void* scratch, hipStream_t s) {
-  char* p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(scratch) + 255) & ~(uintptr_t)255);
-  auto take = [&](size_t bytes) { char* r = p; p += align_up(bytes); return r; };
   const int mode = opt->sort_mode;
-  const uint64_t rs_cap = rs_capacity(m, cap, total_tiles, mode);
-  RsScratch sc = rs_carve(take(rs_scratch_bytes(rs_cap)), rs_cap);
-  uint32_t* ok[2] = {reinterpret_cast<uint32_t*>(take((size_t)total_tiles * 4)),
-                     reinterpret_cast<uint32_t*>(take((size_t)total_tiles * 4))};
-  uint32_t* ov[2] = {tile_order, reinterpret_cast<uint32_t*>(take((size_t)total_tiles * 4))};
+  const BinLayout L = bin_layout(reinterpret_cast<uintptr_t>(scratch), m, cap, total_tiles, mode);
+  const uint64_t T = (uint64_t)total_tiles, C = (uint64_t)cap;
+  uint32_t* err = L.misc;
+  // one fill zeroes the ranges, the instance count and every sort's state
+  ZeroList z = {};
+  int nz = 0;
+  auto zero = [&](uint32_t* ptr, uint64_t words) { z.p[nz] = ptr; z.n[nz] = words; ++nz; };
+  zero(ranges, 2 * T);
+  zero(n_inst, 1);
+  zero(L.misc, 64);
+  if (C > 0) zero(L.rs_main, rs_words(C, L.main_passes));
+  if (tile_order) zero(L.rs_order, rs_words(T, 2));
+  if (mode == 1 && m > 0) {
+    zero(L.rs_depth, rs_words((uint64_t)m, 4));
+    zero(L.so_status, L.so_words);
+  }
+  uint64_t zmax = 0;
+  for (int k = 0; k < nz; ++k) zmax = std::max(zmax, z.n[k]);
+  k_zero<<<dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(cdiv(zmax, 256), 1), 2048), nz), 256, 0, s>>>(z);
+  SGS_LAUNCH_CHECK();
+
   // tiles by decreasing list length (after the ranges are known)
   auto order_tiles = [&]() -> sgs_status {
     if (!tile_order) return SGS_OK;
-    k_tile_len_keys<<<(unsigned)cdiv(total_tiles, 256), 256, 0, s>>>(ranges, (uint32_t)total_tiles, ok[0], ov[0]);
+    uint32_t* ok[2] = {L.ok[0], L.ok[1]};
+    uint32_t* ov[2] = {tile_order, L.ov_alt};
+    k_tile_len_keys<<<(unsigned)cdiv(T, 256), 256, 0, s>>>(ranges, (uint32_t)T, ok[0], ov[0]);
     SGS_LAUNCH_CHECK();
-    return radix_sort<uint32_t>(ok, ov, 0, nullptr, (uint32_t)total_tiles, (uint64_t)total_tiles, 16, sc, s);
+    return radix_sort<uint32_t>(ok[0], ov[0], ok, ov, nullptr, (uint32_t)T, T, 16,
+                                rs_carve(L.rs_order, 2, err, n_inst), s);
   };
-  const int tb = tile_bits(total_tiles);
-  k_fill_u32<<<(unsigned)cdiv(2 * total_tiles, 256), 256, 0, s>>>(ranges, 2 * (uint64_t)total_tiles, 0u);
-  SGS_LAUNCH_CHECK();
   DupArgs a = {};
   const uint64_t mm = (uint64_t)m;
   a.rec0 = reinterpret_cast<const float4*>(g->rec);
@@ -556,13 +761,12 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   a.vals = vals;
   a.n_inst = n_inst;
   a.m = m;
+  const RsScratch sc_main = rs_carve(L.rs_main, L.main_passes, err, n_inst);
   if (mode == 0) {
-    const int bits = 32 + tb;
-    const int passes = rs_passes(bits);
-    uint64_t* kalt = reinterpret_cast<uint64_t*>(take((size_t)cap * 8));
-    uint32_t* valt = reinterpret_cast<uint32_t*>(take((size_t)cap * 4));
-    uint64_t* kb[2] = {keys, kalt};
-    uint32_t* vb[2] = {vals, valt};
+    const int passes = L.main_passes;
+    const int tb = tile_bits(total_tiles);
+    uint64_t* kb[2] = {keys, L.kalt};
+    uint32_t* vb[2] = {vals, L.valt};
     const int src = passes & 1;             // so that the result lands in buffer 0
     a.block_off = g->block_off;
     a.nb_total = a.nbx * n_views;
@@ -571,61 +775,50 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
     if (n > 0) {
       k_duplicate64<<<dim3(a.nbx, n_views), 256, 0, s>>>(a);
       SGS_LAUNCH_CHECK();
-    } else {
-      k_fill_u32<<<1, 256, 0, s>>>(n_inst, 1, 0u);
-      SGS_LAUNCH_CHECK();
     }
     if (cap > 0) {
-      sgs_status st = radix_sort<uint64_t>(kb, vb, src, n_inst, 0, (uint64_t)cap, bits, sc, s);
+      sgs_status st = radix_sort<uint64_t>(kb[src], vb[src], kb, vb, n_inst, 0, C, 32 + tb, sc_main, s);
       if (st != SGS_OK) return st;
-      k_tile_ranges<uint64_t><<<(unsigned)cdiv(cap, 256), 256, 0, s>>>(keys, 32, n_inst, (uint32_t)cap,
-                                                                      (uint32_t)total_tiles, ranges);
+      k_tile_ranges<uint64_t><<<(unsigned)cdiv(C, 256), 256, 0, s>>>(keys, 32, n_inst, (uint32_t)C,
+                                                                      (uint32_t)T, ranges);
       SGS_LAUNCH_CHECK();
     }
     return order_tiles();
   }
   // mode 1
-  uint32_t* dk[2] = {reinterpret_cast<uint32_t*>(take((size_t)m * 4)), reinterpret_cast<uint32_t*>(take((size_t)m * 4))};
-  uint32_t* dv[2] = {reinterpret_cast<uint32_t*>(take((size_t)m * 4)), reinterpret_cast<uint32_t*>(take((size_t)m * 4))};
-  const uint64_t nbs = cdiv(m, 256);
-  uint32_t* sbo = reinterpret_cast<uint32_t*>(take((nbs + 1) * 4));
-  uint32_t* offs = reinterpret_cast<uint32_t*>(take((size_t)m * 4));
-  uint32_t* tk[2] = {reinterpret_cast<uint32_t*>(take((size_t)cap * 4)), reinterpret_cast<uint32_t*>(take((size_t)cap * 4))};
-  uint32_t* valt = reinterpret_cast<uint32_t*>(take((size_t)cap * 4));
-  if (m == 0) {
-    k_fill_u32<<<1, 256, 0, s>>>(n_inst, 1, 0u);
-    SGS_LAUNCH_CHECK();
-    return order_tiles();
-  }
-  k_depth_keys<<<(unsigned)nbs, 256, 0, s>>>(g->depth, g->tiles, m, dk[0], dv[0]);
-  SGS_LAUNCH_CHECK();
-  sgs_status st = radix_sort<uint32_t>(dk, dv, 0, nullptr, (uint32_t)m, (uint64_t)m, 32, sc, s);
+  if (m == 0) return order_tiles();
+  const int tb = tile_bits(total_tiles);
+  uint32_t* dk[2] = {L.dk[0], L.dk[1]};
+  uint32_t* dv[2] = {L.dv[0], L.dv[1]};
+  // depth presort straight from the depth buffer (all-ones for tile-less records)
+  sgs_status st = radix_sort<uint32_t>(reinterpret_cast<const uint32_t*>(g->depth), nullptr, dk, dv,
+                                       nullptr, (uint32_t)m, mm, 32, rs_carve(L.rs_depth, 4, err, nullptr), s);
   if (st != SGS_OK) return st;
-  const uint32_t* order = dv[rs_passes(32) & 1];
-  k_sorted_block_sums<<<(unsigned)nbs, 256, 0, s>>>(order, g->tiles, m, sbo);
+  const uint32_t* order = dv[0];
+  k_sorted_offsets<<<(unsigned)cdiv(mm, SO_TILE), 256, 0, s>>>(
+      order, g->tiles, m, L.offs, n_inst, reinterpret_cast<uint64_t*>(L.so_status + 64), L.so_status, err);
   SGS_LAUNCH_CHECK();
-  st = launch_scan_blocks(sbo, sbo, (int64_t)nbs, s);
-  if (st != SGS_OK) return st;
-  k_sorted_offsets<<<(unsigned)nbs, 256, 0, s>>>(order, g->tiles, m, sbo, (int64_t)nbs, offs, n_inst);
-  SGS_LAUNCH_CHECK();
-  const int passes = rs_passes(tb);
+  const int passes = L.main_passes;
   const int src = passes & 1;
-  uint32_t* vb[2] = {vals, valt};
+  uint32_t* tk[2] = {L.tk[0], L.tk[1]};
+  uint32_t* vb[2] = {vals, L.valt};
   a.order = order;
-  a.offs = offs;
+  a.offs = L.offs;
   a.keys32 = tk[src];
   a.vals = vb[src];
+  a.ghist = sc_main.ghist;
+  a.hpasses = passes;
   if (cap > 0) {
-    k_expand32<<<(unsigned)cdiv(cap, EX_TILE), 256, 0, s>>>(a);
+    k_expand32<<<(unsigned)cdiv(C, EX_TILE), 256, 0, s>>>(a);
     SGS_LAUNCH_CHECK();
-    st = radix_sort<uint32_t>(tk, vb, src, n_inst, 0, (uint64_t)cap, tb, sc, s);
+    st = radix_sort<uint32_t>(tk[src], vb[src], tk, vb, n_inst, 0, C, tb, sc_main, s, true);
     if (st != SGS_OK) return st;
-    k_tile_ranges<uint32_t><<<(unsigned)cdiv(cap, 256), 256, 0, s>>>(tk[0], 0, n_inst, (uint32_t)cap,
-                                                                      (uint32_t)total_tiles, ranges);
+    k_tile_ranges<uint32_t><<<(unsigned)cdiv(C, 256), 256, 0, s>>>(tk[0], 0, n_inst, (uint32_t)C,
+                                                                      (uint32_t)T, ranges);
     SGS_LAUNCH_CHECK();
     if (keys) {
-      k_make_keys64<<<(unsigned)cdiv(cap, 256), 256, 0, s>>>(tk[0], vals, g->depth, (uint64_t)m, n_inst,
-                                                              (uint32_t)cap, keys);
+      k_make_keys64<<<(unsigned)cdiv(C, 256), 256, 0, s>>>(tk[0], vals, g->depth, mm, n_inst,
+                                                            (uint32_t)C, keys);
       SGS_LAUNCH_CHECK();
     }
   }

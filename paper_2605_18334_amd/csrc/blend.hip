@@ -95,6 +95,34 @@ struct Stage {
   uint16_t n[NW];
 };
 
+// Whether the ellipse {delta : delta^T Q delta <= R2}, Q = [[a, b], [b, c]]
+// positive definite, meets the box [x0, x1] x [y0, y1] (delta coordinates):
+// the minimum of the quadratic form over the box is 0 when the box holds the
+// centre, else it lies on an edge, where it is a clamped 1D minimum.  The
+// allowance 1e-5 * (|terms|) covers float rounding of the per-pixel test.
+__device__ __forceinline__ float edge_min_x(float a, float b, float c, float ic, float x, float y0,
+                                            float y1) {
+  const float y = fminf(fmaxf(-b * x * ic, y0), y1);
+  const float q = fmaf(a * x, x, fmaf(c * y, y, 2.0f * b * x * y));
+  const float mag = fmaf(a * x, x, fmaf(c * y, y, 2.0f * fabsf(b * x * y)));
+  return q - 1e-5f * mag;
+}
+__device__ __forceinline__ float edge_min_y(float a, float b, float c, float ia, float y, float x0,
+                                            float x1) {
+  const float x = fminf(fmaxf(-b * y * ia, x0), x1);
+  const float q = fmaf(a * x, x, fmaf(c * y, y, 2.0f * b * x * y));
+  const float mag = fmaf(a * x, x, fmaf(c * y, y, 2.0f * fabsf(b * x * y)));
+  return q - 1e-5f * mag;
+}
+__device__ __forceinline__ bool ellipse_meets_box(float a, float b, float c, float R2, float x0,
+                                                  float x1, float y0, float y1) {
+  if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
+  const float ia = __builtin_amdgcn_rcpf(a), ic = __builtin_amdgcn_rcpf(c);
+  const float m = fminf(fminf(edge_min_x(a, b, c, ic, x0, y0, y1), edge_min_x(a, b, c, ic, x1, y0, y1)),
+                        fminf(edge_min_y(a, b, c, ia, y0, x0, x1), edge_min_y(a, b, c, ia, y1, x0, x1)));
+  return m <= R2;
+}
+
 // Loads records [idx0, idx0 + cnt) of the tile list into the stage and builds
 // the per-wave lists.  Every thread of the block must call it.
 template <int TW, int TH, int B, bool ENH>
@@ -114,12 +142,11 @@ __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup&
       S.r1[k] = q1;
       S.r2[k] = q2;
       if (ENH) S.r3[k] = a.rec3[m];
-      // AABB of the ellipse delta^T Q delta <= -2 log_thr (pairs outside are skipped)
+      // the ellipse delta^T Q delta <= -2 log_thr outside which every pair
+      // is skipped, with the margins of the tile extent
       const float det = q0.z * q1.x - q0.w * q0.w;
-      const float R2 = -2.0f * q2.w;
-      const float ex = sqrtf(R2 * q1.x / det) * 1.001f + 0.01f;
-      const float ey = sqrtf(R2 * q0.z / det) * 1.001f + 0.01f;
-      if (!(det > 0.0f) || !(ex < 1e30f) || !(ey < 1e30f)) {
+      const float R2 = -2.0f * q2.w * 1.002f + 1e-3f;
+      if (!(det > 0.0f) || !(q0.z > 0.0f) || !(R2 > 0.0f) || !(R2 < 1e30f) || !(det < 1e30f)) {
         msk = (1u << St::NW) - 1u;
       } else {
         // skew half-plane: alpha <= d (1 + erf(z)) stays below alpha_min
@@ -131,7 +158,8 @@ __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup&
         for (int w = 0; w < St::NW; ++w) {
           const float lx = (float)(ts.ox + (w % (TW / 8)) * 8) + 0.5f;
           const float ly = (float)(ts.oy + (w / (TW / 8)) * 8) + 0.5f;
-          bool hit = q0.x + ex >= lx && q0.x - ex <= lx + 7.0f && q0.y + ey >= ly && q0.y - ey <= ly + 7.0f;
+          bool hit = ellipse_meets_box(q0.z, q0.w, q1.x, R2, lx - q0.x - 0.01f, lx + 7.0f - q0.x + 0.01f,
+                                       ly - q0.y - 0.01f, ly + 7.0f - q0.y + 0.01f);
           if (hit && zc > -1e29f) {
             const float top = skew_box_max(q1.y, q1.z, lx + 3.5f, ly + 3.5f, q0.x, q0.y, 3.5f, 3.5f);
             hit = top + 1e-3f * (1.0f + fabsf(top) + fabsf(need)) >= need;
@@ -203,18 +231,22 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
     if (__syncthreads_and(done)) break;
     const int cnt = (int)min((uint32_t)B, rg.y - base);
     stage_batch<TW, TH, B, ENH>(a, ts, base, cnt, S);
+    // the wave walks its list together: control flow is wave-uniform, lanes
+    // that are finished or outside a record's ellipse are masked
     const int nw = S.n[w];
+    int jn = nw > 0 ? S.list[w][0] : 0;
     for (int i = 0; i < nw; ++i) {
-      if (done) break;
-      const int j = S.list[w][i];
+      const int j = __builtin_amdgcn_readfirstlane(jn);
+      if (i + 1 < nw) jn = S.list[w][i + 1];
       const float4 r0 = S.r0[j];
       const float4 r1 = S.r1[j];
+      const float4 r2 = S.r2[j];
       const float dx = fx - r0.x, dy = fy - r0.y;
       const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
-      const float4 r2 = S.r2[j];
-      if (power < r2.w) continue;
+      const bool in = !done && power >= r2.w;
+      if (!__any(in)) continue;
       Pair p;
-      pair_eval(power, r1.w, r1.y, r1.z, dx, dy, (r1.y != 0.0f) || (r1.z != 0.0f), p);
+      pair_eval(power, r1.w, r1.y, r1.z, dx, dy, uniform_skew(r1), p);
       float at = p.at;
       if (ENH) {
         const float4 r3 = S.r3[j];
@@ -222,19 +254,20 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
         at *= enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
       }
       const float alpha = fminf(a.alpha_max, at);
-      if (alpha < a.alpha_min) continue;
+      const bool take = in && alpha >= a.alpha_min;
       const float Tn = T * (1.0f - alpha);
-      if (Tn < a.t_min) {
-        done = true;
-        break;
+      const bool stop = take && Tn < a.t_min;
+      if (take && !stop) {
+        const float wgt = alpha * T;
+        C0 = fmaf(r2.x, wgt, C0);
+        C1 = fmaf(r2.y, wgt, C1);
+        C2 = fmaf(r2.z, wgt, C2);
+        T = Tn;
+        last = base - rg.x + (uint32_t)j + 1u;
+        ++count;
       }
-      const float wgt = alpha * T;
-      C0 = fmaf(r2.x, wgt, C0);
-      C1 = fmaf(r2.y, wgt, C1);
-      C2 = fmaf(r2.z, wgt, C2);
-      T = Tn;
-      last = base - rg.x + (uint32_t)j + 1u;
-      ++count;
+      done = done || stop;
+      if (__any(stop) && __all(done)) break;
     }
   }
   if (ts.inside) {
@@ -322,7 +355,7 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
         const float4 r2 = S.r2[j];
         if (power >= r2.w) {
           Pair p;
-          pair_eval(power, r1.w, r1.y, r1.z, dx, dy, (r1.y != 0.0f) || (r1.z != 0.0f), p);
+          pair_eval(power, r1.w, r1.y, r1.z, dx, dy, uniform_skew(r1), p);
           float at = p.at, o = 1.0f, eu = 0.0f, ee = 1.0f;
           float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
           if (ENH) {

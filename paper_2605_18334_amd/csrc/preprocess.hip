@@ -218,10 +218,11 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
             const float zc = has_skew ? skew_zcut(a.opt.alpha_min, d) : -1e30f;
             // tiles of the rect that the evaluation ellipse (cut by the skew
             // half-plane) reaches, row by row
+            Span sp;
+            span_setup(P.mux, P.muy, P.a, P.b, P.c, thr, P.b2x, P.b2y, zc, sp);
             for (int row = ty0; row < ty1; ++row) {
               int c0, c1;
-              row_span(P.mux, P.muy, P.a, P.b, P.c, thr, P.b2x, P.b2y, zc, row, a.opt.tile_w,
-                       a.opt.tile_h, tx0, tx1, c0, c1);
+              span_row(sp, row, a.opt.tile_w, a.opt.tile_h, tx0, tx1, c0, c1);
               ntiles += (uint32_t)(c1 - c0);
             }
             const int64_t M = a.m;
@@ -234,7 +235,8 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
         }
       }
     }
-    a.depth[m] = P.valid ? P.tz : 0.0f;
+    // records without tiles get all-ones bits: they sort after every finite depth
+    a.depth[m] = ntiles ? P.tz : __uint_as_float(0xffffffffu);
     a.tiles[m] = ntiles;
     reinterpret_cast<uint2*>(a.rect)[m] = make_uint2(rx, ry);
   }
@@ -524,12 +526,6 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(PreBwdArgs a) {
 }
 
 // ------------------------------------------------------------------ launchers
-sgs_status launch_scan_blocks(const uint32_t* in, uint32_t* out, int64_t nb, hipStream_t s) {
-  k_scan_blocks<<<1, 1024, 0, s>>>(in, out, nb);
-  SGS_LAUNCH_CHECK();
-  return SGS_OK;
-}
-
 sgs_status launch_preprocess(const sgs_params* p, const sgs_camera* cams_dev, int32_t n_views,
                              const sgs_options* opt, const sgs_geom* g, hipStream_t s) {
   PreArgs a;

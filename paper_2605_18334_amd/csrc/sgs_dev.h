@@ -44,7 +44,7 @@ struct Pair {
 // erfc(-x) = 2 - erfc(x).  Also returns exp(-z^2), which the backward needs.
 __device__ __forceinline__ float one_plus_erf(float z, float& ez) {
   const float x = fabsf(z);
-  const float t = __frcp_rn(fmaf(0.3275911f, x, 1.0f));
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));   // v_rcp_f32 (1 ulp)
   float poly = fmaf(1.061405429f, t, -1.453152027f);
   poly = fmaf(poly, t, 1.421413741f);
   poly = fmaf(poly, t, -0.284496736f);
@@ -52,6 +52,15 @@ __device__ __forceinline__ float one_plus_erf(float z, float& ez) {
   ez = __expf(-x * x);
   const float q = (poly * t) * ez;      // erfc(|z|)
   return z < 0.0f ? q : 2.0f - q;
+}
+
+// Whether a staged record has a nonzero 2D skew, as a wave-uniform value
+// (every lane of the wave reads the same record): the same truth value as
+// (beta_x != 0) || (beta_y != 0), NaN counting as nonzero.
+__device__ __forceinline__ bool uniform_skew(const float4& r1) {
+  const uint32_t bx = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(r1.y));
+  const uint32_t by = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(r1.z));
+  return ((bx | by) << 1) != 0u;
 }
 
 __device__ __forceinline__ float pair_power(float a, float b, float c, float dx, float dy) {
@@ -85,13 +94,6 @@ __device__ __forceinline__ float enh_opacity(float o1, float o2, float wx, float
 }
 
 // ---------------------------------------------------------------- tiles
-// Columns [c0, c1) of tile row `row` that the evaluation ellipse of a record
-// can reach: the ellipse {delta : a dx^2 + 2 b dx dy + c dy^2 <= R2} around
-// (mx, my), R2 = -2 log_thr (outside it every pair is skipped), sampled at
-// pixel centres (i + 0.5), widened by a small margin and clipped to the
-// record's rect [x0, x1).  Counting (preprocess) and enumeration (duplicate)
-// call this same contraction-free code with the same stored record values, so
-// they agree exactly.
 // Skew cut: pairs whose z = beta.delta/sqrt2 is below the returned value have
 // alpha <= d (1 + erf z) < alpha_min (G' <= 1), d the record's largest
 // opacity factor.  1e-3 below the exact root of 1 + erf(z0) = alpha_min/d;
@@ -112,58 +114,87 @@ __device__ __forceinline__ float skew_box_max(float bx, float by, float cx, floa
   return bx * (cx - mx) + by * (cy - my) + fabsf(bx) * hx + fabsf(by) * hy;
 }
 
-__device__ __forceinline__ void row_span(float mx, float my, float a, float b, float c,
-                                         float log_thr, float bx, float by, float zcut, int row,
-                                         int tw, int th, int x0, int x1, int& c0, int& c1) {
+// Per-record extent of the pairs that can reach alpha_min, tile row by tile
+// row.  Columns [c0, c1) of tile row `row` are those whose pixel centres
+// (i + 0.5) the ellipse {delta : a dx^2 + 2 b dx dy + c dy^2 <= R2} around
+// (mx, my), R2 = -2 log_thr (outside it every pair is skipped), reaches,
+// widened by a small margin, clipped to the record's rect [x0, x1) and cut
+// by the skew half-plane beta.delta >= sqrt2 zcut (linear in the column, so
+// the kept tiles stay one interval).  span_setup does the per-record work
+// once; span_row is cheap.  Counting (preprocess) and enumeration (duplicate,
+// expand) call this same contraction-free code on the same stored record
+// values, so they agree exactly.
+struct Span {
+  float mx, my, b, det, ia, aR2;
+  float ey, ex, yx;
+  float bx, by, need;    // skew cut (cut == false: none)
+  bool ok, cut;
+};
+
+__device__ __forceinline__ void span_setup(float mx, float my, float a, float b, float c,
+                                           float log_thr, float bx, float by, float zcut,
+                                           Span& s) {
+#pragma clang fp contract(off)
+  s.mx = mx;
+  s.my = my;
+  s.b = b;
+  const float R2 = -2.0f * log_thr * 1.002f + 1e-3f;
+  s.det = a * c - b * b;
+  s.ok = (s.det > 0.0f) && (R2 > 0.0f) && (a > 0.0f) && (c > 0.0f);
+  s.ia = 1.0f / a;
+  s.aR2 = a * R2;
+  s.ey = sqrtf(R2 * a / s.det);
+  s.ex = sqrtf(R2 * c / s.det);
+  s.yx = -b * sqrtf(R2) / sqrtf(c * s.det);   // dy where x is largest on the ellipse
+  s.bx = bx;
+  s.by = by;
+  s.need = zcut * 1.41421356f;                // beta.delta >= need
+  s.cut = zcut > -1e29f && (bx != 0.0f || by != 0.0f);
+}
+
+__device__ __forceinline__ void span_row(const Span& s, int row, int tw, int th, int x0, int x1,
+                                         int& c0, int& c1) {
 #pragma clang fp contract(off)
   c0 = x0;
   c1 = x0;
-  const float R2 = -2.0f * log_thr * 1.002f + 1e-3f;
-  const float det = a * c - b * b;
-  if (!(det > 0.0f) || !(R2 > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) {
+  if (!s.ok) {
     c1 = x1;                                   // degenerate: keep the whole rect row
     return;
   }
-  const float ey = sqrtf(R2 * a / det);
-  float u0 = ((float)(row * th) + 0.5f - 0.01f) - my;
-  float u1 = ((float)(row * th + th) - 0.5f + 0.01f) - my;
-  u0 = fmaxf(u0, -ey);
-  u1 = fminf(u1, ey);
+  float u0 = ((float)(row * th) + 0.5f - 0.01f) - s.my;
+  float u1 = ((float)(row * th + th) - 0.5f + 0.01f) - s.my;
+  u0 = fmaxf(u0, -s.ey);
+  u1 = fminf(u1, s.ey);
   if (!(u0 <= u1)) return;
-  const float ex = sqrtf(R2 * c / det);
-  const float R = sqrtf(R2);
-  const float yx = -b * R / sqrtf(c * det);    // dy where x is largest on the ellipse
-  const float r0 = sqrtf(fmaxf(a * R2 - det * u0 * u0, 0.0f));
-  const float r1 = sqrtf(fmaxf(a * R2 - det * u1 * u1, 0.0f));
-  float xr = fmaxf((-b * u0 + r0) / a, (-b * u1 + r1) / a);
-  float xl = fminf((-b * u0 - r0) / a, (-b * u1 - r1) / a);
-  if (yx >= u0 && yx <= u1) xr = ex;
-  if (-yx >= u0 && -yx <= u1) xl = -ex;
+  const float r0 = sqrtf(fmaxf(s.aR2 - s.det * u0 * u0, 0.0f));
+  const float r1 = sqrtf(fmaxf(s.aR2 - s.det * u1 * u1, 0.0f));
+  float xr = fmaxf((-s.b * u0 + r0) * s.ia, (-s.b * u1 + r1) * s.ia);
+  float xl = fminf((-s.b * u0 - r0) * s.ia, (-s.b * u1 - r1) * s.ia);
+  if (s.yx >= u0 && s.yx <= u1) xr = s.ex;
+  if (-s.yx >= u0 && -s.yx <= u1) xl = -s.ex;
   xr = xr * 1.001f + 0.01f;
   xl = xl * 1.001f - 0.01f;
-  const float px0 = ceilf(mx + xl - 0.5f), px1 = floorf(mx + xr - 0.5f);
+  const float px0 = ceilf(s.mx + xl - 0.5f), px1 = floorf(s.mx + xr - 0.5f);
   if (!(px0 <= px1) || !(px1 >= 0.0f)) return;
   const float lo = fmaxf(px0, 0.0f);
   const int t0 = (int)fminf(lo, 1e9f) / tw;
   const int t1 = (int)fminf(px1, 1e9f) / tw + 1;
   c0 = max(x0, t0);
   c1 = min(x1, t1);
-  // skew cut: beta.delta over a tile of this row is linear in the column, so
-  // the tiles it keeps are an interval; half extents widened by half a pixel
-  if (zcut > -1e29f && (bx != 0.0f || by != 0.0f) && c0 < c1) {
+  // skew cut over the tiles of this row (tile boxes: half extents tw/2, th/2)
+  if (s.cut && c0 < c1) {
     const float hx = 0.5f * (float)tw, hy = 0.5f * (float)th;
     const float cy = (float)(row * th) + hy;
-    const float need = zcut * 1.41421356f;                 // beta.delta >= need
-    const float base = skew_box_max(bx, by, hx, cy, mx, my, hx, hy);   // column 0
-    const float step = bx * (float)tw;                      // per column
-    const float slack = 1e-3f * (1.0f + fabsf(base) + fabsf(need) + fabsf(step) * (float)c1);
+    const float base = skew_box_max(s.bx, s.by, hx, cy, s.mx, s.my, hx, hy);   // column 0
+    const float step = s.bx * (float)tw;                                        // per column
+    const float slack = 1e-3f * (1.0f + fabsf(base) + fabsf(s.need) + fabsf(step) * (float)c1);
     if (step > 0.0f) {
-      const float k = (need - base - slack) / step;
+      const float k = (s.need - base - slack) / step;
       if (k > (float)c0) c0 = min(c1, (int)ceilf(fminf(k, 1e9f)));
     } else if (step < 0.0f) {
-      const float k = (need - base - slack) / step;      // columns <= k survive
+      const float k = (s.need - base - slack) / step;    // columns <= k survive
       if (k < (float)(c1 - 1)) c1 = max(c0, (int)floorf(fmaxf(k, -1e9f)) + 1);
-    } else if (base + slack < need) {
+    } else if (base + slack < s.need) {
       c1 = c0;
     }
   }

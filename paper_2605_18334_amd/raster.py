@@ -395,7 +395,10 @@ class Renderer:
         return int(self.bufs["n_inst"].item()) & 0xFFFFFFFF
 
     def overflowed(self) -> bool:
-        return self.n_inst() > self.capacity
+        n = self.n_inst()
+        if n == 0xFFFFFFFF:
+            raise _abi.SgsError("sgs_bin_sort: a sort look-back did not complete; outputs invalid", 3)
+        return n > self.capacity
 
     def image(self, v: int = 0) -> torch.Tensor:
         c = self.cams.view(v)
