@@ -133,6 +133,14 @@ typedef struct {
                               duplicate in depth order, LSD sort of 32-bit
                               tile keys.  Both give the identical order.    */
   int32_t blend_batch;     /* [256] records staged in LDS per batch: 64, 128, 256 */
+  int32_t split_tiles;     /* [-1] with 16x16 tiles and a tile order (and no
+                              work counter): both blends run the first
+                              split_tiles tiles of the order (the longest
+                              lists) as four 8x8 quarters, four lanes per
+                              pixel evaluating four records at once; same
+                              images (gradients up to the order of float
+                              sums), more parallelism per tile.  -1:
+                              total_tiles / 32; 0: off.                     */
 } sgs_options;
 
 /* Projected per-record data written by sgs_preprocess, record m = v*N + i for
@@ -155,10 +163,12 @@ typedef struct {
 } sgs_geom;
 
 /* Optional tile scheduling for the blend kernels (device pointers).
- *  tile_order    [total_tiles] u32: written by sgs_bin_sort when non-NULL, the
- *                tile ids ordered by decreasing list length (longest first, so
- *                the slowest tiles start first); read by the blends, which
- *                then take tiles in this order.
+ *  tile_order    [total_tiles] u32: written by sgs_bin_sort when non-NULL, a
+ *                permutation of the tile ids by decreasing list length on a
+ *                quarter-octave scale (longest first, so the slowest tiles
+ *                start first; the order inside a length bucket is
+ *                unspecified); read by the blends, which then take tiles in
+ *                this order.  It changes scheduling only, never results.
  *  work_counter  [1] u32: when non-NULL the blends run persistent workgroups
  *                (as many as fit on the device) that take the next tile from
  *                this counter until all tiles are done; the call resets it on

@@ -1,12 +1,13 @@
 // Tile binning: one instance per (record, covered tile), a stable LSD radix
 // sort by (global tile, depth), and per-tile ranges of the sorted list.
 //
-// Radix sort (hand-written, stable, 8-bit digits, 256-thread blocks of 4096
-// keys), one kernel per pass in the onesweep style (Adinets & Merrill 2022):
+// Radix sort (hand-written, stable, digits of at most 8 bits spread evenly
+// over the passes, 256-thread blocks of 4096 keys), one kernel per pass in
+// the onesweep style (Adinets & Merrill 2022):
 // a single histogram kernel reads the keys once and counts the digits of
 // every pass; each pass kernel takes a block id from an atomic counter (so
 // every lower id is already running), ranks its keys inside each wave64 with
-// 8 ballots per key (lanes hold consecutive keys, so ranks are stable),
+// one ballot per digit bit (lanes hold consecutive keys, so ranks are stable),
 // publishes its per-digit counts, and finds its global offsets by looking
 // back over the published counts of the blocks before it (decoupled
 // look-back, eight predecessors read at once).  The look-back spin is
@@ -35,13 +36,16 @@
 namespace sgs {
 
 constexpr int RS_T = 256;          // threads per block
-constexpr int RS_IPT = 16;         // keys per thread
-constexpr int RS_TILE = RS_T * RS_IPT;
+// keys per thread (a template parameter of the kernels).  16 measured best
+// from 0.3M to 50M keys: fewer, longer blocks keep look-back chains short
+// (4 doubled the time of a pass over 1M keys).
+constexpr int RS_IPT = 16;
 constexpr int RS_MAX_PASSES = 8;
 constexpr uint64_t ST_AGG = 1ull << 32;    // status: block's own digit count
 constexpr uint64_t ST_INC = 2ull << 32;    // status: inclusive prefix over blocks
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 constexpr int LB_W = 8;            // look-back: predecessor statuses read at once
+constexpr int HC = 64;             // copies of the digit histograms (atomic contention)
 constexpr uint32_t N_INVALID = 0xffffffffu;   // instance count after a failed look-back
 
 __device__ __forceinline__ uint32_t count_of(const uint32_t* n_dev, uint32_t n_host, uint32_t cap) {
@@ -81,34 +85,50 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* ws4
   return e;
 }
 
-// Digit histograms of every pass in one read of the keys.
-template <typename K>
+// Digit histograms of every pass in one read of the keys, added into copy
+// (block % HC) of the partial histograms [HC][passes][256]: many blocks
+// adding into one set of 256 words serialise on those addresses.
+template <typename K, int RS_IPT>
 __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, const uint32_t* n_dev,
-                                                  uint32_t n_host, uint32_t cap, int bits,
-                                                  uint32_t* __restrict__ ghist) {
+                                                  uint32_t n_host, uint32_t cap, int passes,
+                                                  int width, uint32_t* __restrict__ hpart) {
   __shared__ uint32_t h[RS_MAX_PASSES][256];
   const int t = threadIdx.x;
-  const int passes = (bits + 7) / 8;
+  const uint32_t dmask = (1u << width) - 1u;
   for (int k = t; k < RS_MAX_PASSES * 256; k += RS_T) (&h[0][0])[k] = 0;
   __syncthreads();
   const uint32_t n = count_of(n_dev, n_host, cap);
+  constexpr int RS_TILE = RS_T * RS_IPT;
   const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
   for (int i = 0; i < RS_IPT; ++i) {
     const uint64_t idx = base + (uint64_t)i * RS_T + t;
     if (idx < n) {
       const K key = keys[idx];
-      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][digit_of<K>(key, 8 * p, 0xffu)], 1u);
+      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][digit_of<K>(key, width * p, dmask)], 1u);
     }
   }
   __syncthreads();
+  uint32_t* dst = hpart + (size_t)(blockIdx.x % HC) * passes * 256;
   for (int p = 0; p < passes; ++p)
-    if (h[p][t]) atomicAdd(&ghist[p * 256 + t], h[p][t]);
+    if (h[p][t]) atomicAdd(&dst[p * 256 + t], h[p][t]);
+}
+
+// Sums the HC partial copies of the digit histograms: ghist[p][d].
+__global__ void __launch_bounds__(256) k_hist_final(const uint32_t* __restrict__ hpart, int passes,
+                                                    uint32_t* __restrict__ ghist) {
+  const int p = blockIdx.x, t = threadIdx.x;
+  uint32_t sum = 0;
+  for (int c = 0; c < HC; ++c) sum += hpart[((size_t)c * passes + p) * 256 + t];
+  ghist[p * 256 + t] = sum;
 }
 
 // vin == nullptr: the values are the input positions (0, 1, 2, ...).
 // On a look-back that does not finish in bounded time: err |= 1 and, when
 // n_fold is given, *n_fold = N_INVALID.
-template <typename K>
+// ranges != nullptr (last pass over tile keys): every run of equal keys in
+// the block's output lowers ranges[2 key] to its first position and raises
+// ranges[2 key + 1] to its end (ranges start as [0xffffffff, 0)).
+template <typename K, int RS_IPT>
 __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
                                                   const uint32_t* __restrict__ vin,
                                                   K* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -116,12 +136,15 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
                                                   uint32_t cap, int shift, int nbits,
                                                   const uint32_t* __restrict__ ghist,
                                                   uint64_t* status, uint32_t* counter,
-                                                  uint32_t* err, uint32_t* n_fold) {
+                                                  uint32_t* err, uint32_t* n_fold,
+                                                  uint32_t* ranges, uint32_t n_tiles) {
   __shared__ uint32_t wc[4][256];
   __shared__ uint32_t lstart[256];
+  __shared__ uint32_t lend[256];
   __shared__ uint32_t goff[256];
   __shared__ uint32_t ws[4];
   __shared__ uint32_t s_bid;
+  constexpr int RS_TILE = RS_T * RS_IPT;
   __shared__ K skey[RS_TILE];
   __shared__ uint32_t sval[RS_TILE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -136,49 +159,65 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
   const uint64_t base = bbase + (uint64_t)w * (RS_IPT * 64) + lane;
   const uint64_t lt = lanemask_lt();
   K key[RS_IPT];
-  uint32_t val[RS_IPT];
   uint32_t rank[RS_IPT];
 #pragma unroll
   for (int i = 0; i < RS_IPT; ++i) {
     const uint64_t idx = base + (uint64_t)i * 64;
-    const bool valid = idx < n;
-    key[i] = valid ? kin[idx] : (K)0;
-    val[i] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
+    key[i] = idx < n ? kin[idx] : (K)0;
   }
   // rank inside the wave: the lowest lane of each digit's peers reserves
   // their slots with one LDS atomic (the atomics of the RS_IPT rounds are in
   // flight together), then every lane fetches its leader's base
+  // (rank holds the rank among the peers in its low 8 bits and the
+  // leader's lane above them until the bases are fetched)
   uint32_t lead_base[RS_IPT];
-  int leader[RS_IPT];
 #pragma unroll
   for (int i = 0; i < RS_IPT; ++i) {
     const bool valid = base + (uint64_t)i * 64 < n;
     const uint32_t d = digit_of<K>(key[i], shift, mask);
     const uint64_t peers = match_digit(d, valid, nbits);
-    rank[i] = (uint32_t)__popcll(peers & lt);
-    leader[i] = peers ? __builtin_ctzll(peers) : lane;
+    const uint32_t r = (uint32_t)__popcll(peers & lt);
+    rank[i] = r | ((uint32_t)(peers ? __builtin_ctzll(peers) : lane) << 8);
     lead_base[i] = 0;
-    if (valid && rank[i] == 0) lead_base[i] = atomicAdd(&wc[w][d], (uint32_t)__popcll(peers));
+    if (valid && r == 0) lead_base[i] = atomicAdd(&wc[w][d], (uint32_t)__popcll(peers));
   }
 #pragma unroll
-  for (int i = 0; i < RS_IPT; ++i) rank[i] += __shfl(lead_base[i], leader[i]);
+  for (int i = 0; i < RS_IPT; ++i) rank[i] = (rank[i] & 255u) + __shfl(lead_base[i], (int)(rank[i] >> 8));
   __syncthreads();
   const uint32_t c0 = wc[0][t], c1 = wc[1][t], c2 = wc[2][t], c3 = wc[3][t];
   const uint32_t tot = c0 + c1 + c2 + c3;
   const uint32_t ls = block_excl_scan256(tot, ws);
   const uint32_t ds = block_excl_scan256(ghist[t], ws);   // start of digit t in the output
   lstart[t] = ls;
+  lend[t] = ls + tot;
   wc[0][t] = ls;
   wc[1][t] = ls + c0;
   wc[2][t] = ls + c0 + c1;
   wc[3][t] = ls + c0 + c1 + c2;
-  // publish this block's count of digit t, then look back for the prefix
+  // publish this block's count of digit t as early as possible (later
+  // blocks' look-backs wait for it); threads past the last digit idle
+  const bool has_digit = t < (1 << nbits);
   uint64_t* st = status + (uint64_t)b * 256 + t;
-  if (b == 0) {
-    __hip_atomic_store(st, ST_INC | (uint64_t)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (has_digit)
+    __hip_atomic_store(st, (b == 0 ? ST_INC : ST_AGG) | (uint64_t)tot, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  // stage the block's keys in digit order (local ranks only), so that no key
+  // or value stays in registers during the look-back
+#pragma unroll
+  for (int i = 0; i < RS_IPT; ++i) {
+    const uint64_t idx = base + (uint64_t)i * 64;
+    if (idx < n) {
+      const uint32_t d = digit_of<K>(key[i], shift, mask);
+      const uint32_t pos = wc[w][d] + rank[i];
+      skey[pos] = key[i];
+      sval[pos] = vin ? vin[idx] : (uint32_t)idx;
+    }
+  }
+  // look back for the prefix over the blocks before this one
+  if (b == 0 || !has_digit) {
     goff[t] = ds;
   } else {
-    __hip_atomic_store(st, ST_AGG | (uint64_t)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // walk back LB_W predecessors at a time (their loads are in flight
     // together), summing published counts until an inclusive prefix
     uint32_t excl = 0, spins = 0;
@@ -222,17 +261,6 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
     goff[t] = ds + excl;
   }
   __syncthreads();
-#pragma unroll
-  for (int i = 0; i < RS_IPT; ++i) {
-    const uint64_t idx = base + (uint64_t)i * 64;
-    if (idx < n) {
-      const uint32_t d = digit_of<K>(key[i], shift, mask);
-      const uint32_t pos = wc[w][d] + rank[i];
-      skey[pos] = key[i];
-      sval[pos] = val[i];
-    }
-  }
-  __syncthreads();
   const uint32_t cnt = (uint32_t)min((uint64_t)RS_TILE, (uint64_t)n - bbase);
   for (uint32_t j = t; j < cnt; j += RS_T) {
     const K k = skey[j];
@@ -241,6 +269,11 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
     if (g < n) {
       kout[g] = k;
       vout[g] = sval[j];
+      if (ranges && (uint64_t)k < n_tiles) {
+        const uint32_t tile = (uint32_t)k;
+        if (j == lstart[d] || skey[j - 1] != k) atomicMin(&ranges[2 * (uint64_t)tile], g);
+        if (j + 1 == lend[d] || skey[j + 1] != k) atomicMax(&ranges[2 * (uint64_t)tile + 1], g + 1);
+      }
     }
   }
 }
@@ -267,8 +300,9 @@ struct DupArgs {
   uint32_t* n_inst;
   const uint32_t* order; // mode 1: records in depth order
   const uint32_t* offs;  // mode 1: exclusive instance offset of order[j]
-  uint32_t* ghist;       // mode 1: digit histograms [hpasses][256] of the tile keys
-  int32_t hpasses;
+  uint32_t* hpart;       // mode 1: partial digit histograms [HC][hpasses][256] of the tile keys
+  int32_t hpasses;       //         digits of hwidth bits
+  int32_t hwidth;
   int64_t m;
 };
 
@@ -438,6 +472,7 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
   if (o0 >= n) return;
   const uint64_t o1 = min(o0 + (uint64_t)EX_TILE, (uint64_t)n);
   const int t = threadIdx.x;
+  const uint32_t dmask = (1u << a.hwidth) - 1u;
   for (int k = t; k < 4 * 256; k += 256) (&hist[0][0])[k] = 0u;
   // last j with offs[j] <= o0 (offs is non-decreasing, offs[0] = 0): a
   // 256-way search, one sample per thread and round (about log_256 M rounds)
@@ -455,10 +490,16 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
     s_w = (uint32_t)min((uint64_t)EX_W, (uint64_t)a.m - jlo);
   }
   __syncthreads();
-  const uint32_t j0 = s_j0, W = s_w;
-  // rows of the window's records (records starting at or past o1: none)
+  const uint32_t j0 = s_j0;
+  uint32_t W = s_w;
+  // rows of the window's records (records starting at or past o1: none);
+  // the window ends at the first chunk of 256 records that starts past o1
   uint32_t carry = 0;
   for (uint32_t c = 0; c < W; c += 256) {
+    if (c > 0 && a.offs[j0 + c] >= o1) {   // the same value in every thread
+      W = c;
+      break;
+    }
     const uint32_t k = c + t;
     uint32_t rows = 0;
     if (k < W) {
@@ -511,21 +552,23 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
       const uint32_t key = tlo + (uint32_t)(o - lo);
       a.keys32[o] = key;
       a.vals[o] = rec;
-      atomicAdd(&hist[0][key & 255u], 1u);
+      atomicAdd(&hist[0][key & dmask], 1u);
     }
     if (a.hpasses > 1 && hi > lo) {
       const uint32_t thi = tlo + (uint32_t)(hi - lo);
       for (uint32_t seg = tlo; seg < thi;) {
-        const uint32_t end = min(thi, (seg | 255u) + 1u);
-        for (int p = 1; p < a.hpasses; ++p) atomicAdd(&hist[p][(seg >> (8 * p)) & 255u], end - seg);
+        const uint32_t end = min(thi, (seg | dmask) + 1u);
+        for (int p = 1; p < a.hpasses; ++p)
+          atomicAdd(&hist[p][(seg >> (a.hwidth * p)) & dmask], end - seg);
         seg = end;
       }
     }
     run += s_tot;
     __syncthreads();
   }
+  uint32_t* hdst = a.hpart + (size_t)(blockIdx.x % HC) * a.hpasses * 256;
   for (int p = 0; p < a.hpasses; ++p)
-    if (hist[p][t]) atomicAdd(&a.ghist[p * 256 + t], hist[p][t]);
+    if (hist[p][t]) atomicAdd(&hdst[p * 256 + t], hist[p][t]);
 }
 
 // 64-bit keys from sorted tile keys and the record depths (mode 1, optional).
@@ -540,18 +583,21 @@ __global__ void __launch_bounds__(256) k_make_keys64(const uint32_t* __restrict_
   out[i] = ((uint64_t)tk[i] << 32) | (v < m ? (uint64_t)__float_as_uint(depth[v]) : 0ull);
 }
 
-// Zeroes up to ZL_MAX regions (words), one grid row per region.
+// Fills up to ZL_MAX regions (words), one grid row per region: even words
+// get ev[region], odd words 0 (ev = 0: plain zeroing).
 constexpr int ZL_MAX = 8;
 struct ZeroList {
   uint32_t* p[ZL_MAX];
   uint64_t n[ZL_MAX];
+  uint32_t ev[ZL_MAX];
 };
 
 __global__ void __launch_bounds__(256) k_zero(ZeroList z) {
   uint32_t* p = z.p[blockIdx.y];
   const uint64_t n = z.n[blockIdx.y];
+  const uint32_t ev = z.ev[blockIdx.y];
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
-    p[i] = 0u;
+    p[i] = (i & 1) ? 0u : ev;
 }
 
 template <typename K>
@@ -572,34 +618,76 @@ __global__ void __launch_bounds__(256) k_tile_ranges(const K* __restrict__ keys,
   }
 }
 
-// Keys that order tiles by decreasing list length (16 bits, saturating).
-__global__ void __launch_bounds__(256) k_tile_len_keys(const uint32_t* __restrict__ ranges,
-                                                       uint32_t total_tiles,
-                                                       uint32_t* __restrict__ k,
-                                                       uint32_t* __restrict__ v) {
-  const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= total_tiles) return;
-  const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-  k[t] = 0xffffu - min(len, 0xffffu);
-  v[t] = t;
+// Tile order for the blend, longest lists first: one workgroup buckets the
+// tiles by list length on a quarter-octave scale (bucket 0: empty) and
+// writes them bucket by bucket, longest bucket first.  Inside a bucket the
+// order is whatever the LDS atomics give: it only schedules work, every
+// tile's pixels are computed the same way in any order.
+constexpr int OT_BUCKETS = 128;
+
+__device__ __forceinline__ int len_bucket(uint32_t len) {
+  if (len == 0) return 0;
+  const int lg = 31 - __clz((int)len);                          // floor(log2 len)
+  const int frac = lg >= 2 ? (int)((len >> (lg - 2)) & 3u) : (int)((len << (2 - lg)) & 3u);
+  return min(OT_BUCKETS - 1, 1 + 4 * lg + frac);
+}
+
+// Also rewrites empty ranges (start >= end, as the fused range writer leaves
+// tiles without instances) to [0, 0).  order == nullptr: normalising only.
+__global__ void __launch_bounds__(1024) k_order_tiles(uint32_t* __restrict__ ranges,
+                                                      uint32_t total_tiles,
+                                                      uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[OT_BUCKETS];
+  __shared__ uint32_t pos[OT_BUCKETS];
+  const uint32_t t = threadIdx.x;
+  if (t < OT_BUCKETS) cnt[t] = 0;
+  __syncthreads();
+  for (uint32_t i = t; i < total_tiles; i += 1024) {
+    const uint32_t a = ranges[2 * i], b = ranges[2 * i + 1];
+    if (a >= b && (a | b) != 0u) {
+      ranges[2 * i] = 0u;
+      ranges[2 * i + 1] = 0u;
+    }
+    if (order) atomicAdd(&cnt[len_bucket(b > a ? b - a : 0u)], 1u);
+  }
+  if (!order) return;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0;
+    for (int k = OT_BUCKETS - 1; k >= 0; --k) {
+      pos[k] = run;
+      run += cnt[k];
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < total_tiles; i += 1024) {
+    const uint32_t a = ranges[2 * i], b = ranges[2 * i + 1];
+    const uint32_t p = atomicAdd(&pos[len_bucket(b > a ? b - a : 0u)], 1u);
+    if (p < total_tiles) order[p] = i;
+  }
 }
 
 // ------------------------------------------------------------------ host side
 static inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+// Passes of at most 8 bits; the digit width spreads the bits evenly over
+// them (13 bits: 7 + 6, not 8 + 5): fewer digits per block, longer runs.
 static int rs_passes(int bits) { return (bits + 7) / 8; }
-static uint64_t rs_blocks(uint64_t cap) { return std::max<uint64_t>(1, cdiv(cap, RS_TILE)); }
+static int rs_width(int bits) { return (bits + rs_passes(bits) - 1) / rs_passes(bits); }
+static uint64_t rs_blocks(uint64_t cap) { return std::max<uint64_t>(1, cdiv(cap, (uint64_t)RS_T * RS_IPT)); }
 
 // Scratch of one sort of up to `cap` keys in `passes` passes, contiguous so
 // that it is zeroed as one region: block counters [64] (one per pass), digit
-// histograms [passes][256] u32, look-back status [passes][blocks][256] u64.
+// histograms [passes][256] u32, their partial copies [HC][passes][256] u32,
+// look-back status [passes][blocks][256] u64.
 static size_t rs_words(uint64_t cap, int passes) {
-  return 64 + (size_t)passes * 256 + (size_t)passes * rs_blocks(cap) * 256 * 2;
+  return 64 + (size_t)passes * 256 * (1 + HC) + (size_t)passes * rs_blocks(cap) * 256 * 2;
 }
 
 struct RsScratch {
   uint32_t* counters;
   uint32_t* ghist;
+  uint32_t* hpart;
   uint64_t* status;
   uint32_t* err;        // shared error word of the bin_sort call
   uint32_t* n_fold;     // instance count to mark N_INVALID on failure, or null
@@ -609,35 +697,43 @@ static RsScratch rs_carve(uint32_t* p, int passes, uint32_t* err, uint32_t* n_fo
   RsScratch s;
   s.counters = p;
   s.ghist = p + 64;
-  s.status = reinterpret_cast<uint64_t*>(p + 64 + (size_t)passes * 256);
+  s.hpart = s.ghist + (size_t)passes * 256;
+  s.status = reinterpret_cast<uint64_t*>(p + 64 + (size_t)passes * 256 * (1 + HC));
   s.err = err;
   s.n_fold = n_fold;
   return s;
 }
 
-// Sorts by bits [0, bits), one kernel per 8-bit pass.  Pass 0 reads
+// Sorts by bits [0, bits), one kernel per pass of rs_width(bits) bits.  Pass 0 reads
 // (kin, vin) (vin == nullptr: values are the positions); the result lands in
 // (kb[0], vb[0]).  kin may be kb[passes & 1] (sorting in place) or another
-// buffer.  The scratch must be zero, except that with hist_done its digit
-// histograms already hold the counts of the keys.
+// buffer.  The scratch must be zero, except that with hist_done its partial
+// digit histograms already hold the counts of the keys.  With ranges, the last
+// pass also writes the tile ranges of the sorted keys (see k_os_pass).
 template <typename K>
 static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32_t* vb[2],
                              const uint32_t* n_dev, uint32_t n_host, uint64_t cap, int bits,
-                             RsScratch sc, hipStream_t s, bool hist_done = false) {
+                             RsScratch sc, hipStream_t s, bool hist_done = false,
+                             uint32_t* ranges = nullptr, uint32_t n_tiles = 0) {
   const uint64_t blocks = rs_blocks(cap);
   const int passes = rs_passes(bits);
+  const int width = rs_width(bits);
   if (!hist_done) {
-    k_os_hist<K><<<(unsigned)blocks, RS_T, 0, s>>>(kin, n_dev, n_host, (uint32_t)cap, bits, sc.ghist);
+    k_os_hist<K, RS_IPT><<<(unsigned)blocks, RS_T, 0, s>>>(kin, n_dev, n_host, (uint32_t)cap, passes,
+                                                            width, sc.hpart);
     SGS_LAUNCH_CHECK();
   }
+  k_hist_final<<<passes, 256, 0, s>>>(sc.hpart, passes, sc.ghist);
+  SGS_LAUNCH_CHECK();
   for (int p = 0; p < passes; ++p) {
-    const int nb = std::min(8, bits - 8 * p);
+    const int nb = std::min(width, bits - width * p);
     const int dst = (passes - 1 - p) & 1;
     const K* ki = p == 0 ? kin : kb[dst ^ 1];
     const uint32_t* vi = p == 0 ? vin : vb[dst ^ 1];
-    k_os_pass<K><<<(unsigned)blocks, RS_T, 0, s>>>(
-        ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, 8 * p, nb, sc.ghist + p * 256,
-        sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold);
+    k_os_pass<K, RS_IPT><<<(unsigned)blocks, RS_T, 0, s>>>(
+        ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
+        sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
+        p == passes - 1 ? ranges : nullptr, n_tiles);
     SGS_LAUNCH_CHECK();
   }
   return SGS_OK;
@@ -656,11 +752,8 @@ struct BinLayout {
   uint32_t* rs_main;              // main sort (64-bit keys, or tile keys)
   int main_passes;
   uint32_t* rs_depth;             // mode 1: depth presort
-  uint32_t* rs_order;             // tile order sort
   uint32_t* so_status;            // mode 1: offsets scan: [64] counter, then u64 status
   size_t so_words;
-  uint32_t* ok[2];                // tile order keys
-  uint32_t* ov_alt;               // tile order values (alternate)
   uint64_t* kalt;                 // mode 0: alternate 64-bit keys
   uint32_t* valt;                 // alternate values
   uint32_t* dk[2];                // mode 1: depth keys
@@ -680,10 +773,6 @@ static BinLayout bin_layout(uintptr_t base, int64_t m, int64_t cap, int64_t tota
   L.main_passes = rs_passes(mode == 0 ? 32 + tb : tb);
   L.misc = reinterpret_cast<uint32_t*>(take(64 * 4));
   L.rs_main = reinterpret_cast<uint32_t*>(take(rs_words(C, L.main_passes) * 4));
-  L.rs_order = reinterpret_cast<uint32_t*>(take(rs_words(T, 2) * 4));
-  L.ok[0] = reinterpret_cast<uint32_t*>(take(T * 4));
-  L.ok[1] = reinterpret_cast<uint32_t*>(take(T * 4));
-  L.ov_alt = reinterpret_cast<uint32_t*>(take(T * 4));
   if (mode == 0) {
     L.kalt = reinterpret_cast<uint64_t*>(take(C * 8));
     L.valt = reinterpret_cast<uint32_t*>(take(C * 4));
@@ -718,12 +807,17 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   // one fill zeroes the ranges, the instance count and every sort's state
   ZeroList z = {};
   int nz = 0;
-  auto zero = [&](uint32_t* ptr, uint64_t words) { z.p[nz] = ptr; z.n[nz] = words; ++nz; };
-  zero(ranges, 2 * T);
+  auto zero = [&](uint32_t* ptr, uint64_t words, uint32_t ev = 0u) {
+    z.p[nz] = ptr;
+    z.n[nz] = words;
+    z.ev[nz] = ev;
+    ++nz;
+  };
+  // mode 1 writes ranges from the last sort pass by atomic min / max
+  zero(ranges, 2 * T, mode == 1 ? 0xffffffffu : 0u);
   zero(n_inst, 1);
   zero(L.misc, 64);
   if (C > 0) zero(L.rs_main, rs_words(C, L.main_passes));
-  if (tile_order) zero(L.rs_order, rs_words(T, 2));
   if (mode == 1 && m > 0) {
     zero(L.rs_depth, rs_words((uint64_t)m, 4));
     zero(L.so_status, L.so_words);
@@ -735,13 +829,10 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
 
   // tiles by decreasing list length (after the ranges are known)
   auto order_tiles = [&]() -> sgs_status {
-    if (!tile_order) return SGS_OK;
-    uint32_t* ok[2] = {L.ok[0], L.ok[1]};
-    uint32_t* ov[2] = {tile_order, L.ov_alt};
-    k_tile_len_keys<<<(unsigned)cdiv(T, 256), 256, 0, s>>>(ranges, (uint32_t)T, ok[0], ov[0]);
+    if (!tile_order && mode == 0) return SGS_OK;
+    k_order_tiles<<<1, 1024, 0, s>>>(ranges, (uint32_t)T, tile_order);
     SGS_LAUNCH_CHECK();
-    return radix_sort<uint32_t>(ok[0], ov[0], ok, ov, nullptr, (uint32_t)T, T, 16,
-                                rs_carve(L.rs_order, 2, err, n_inst), s);
+    return SGS_OK;
   };
   DupArgs a = {};
   const uint64_t mm = (uint64_t)m;
@@ -806,16 +897,15 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   a.offs = L.offs;
   a.keys32 = tk[src];
   a.vals = vb[src];
-  a.ghist = sc_main.ghist;
+  a.hpart = sc_main.hpart;
   a.hpasses = passes;
+  a.hwidth = rs_width(tb);
   if (cap > 0) {
     k_expand32<<<(unsigned)cdiv(C, EX_TILE), 256, 0, s>>>(a);
     SGS_LAUNCH_CHECK();
-    st = radix_sort<uint32_t>(tk[src], vb[src], tk, vb, n_inst, 0, C, tb, sc_main, s, true);
+    st = radix_sort<uint32_t>(tk[src], vb[src], tk, vb, n_inst, 0, C, tb, sc_main, s, true, ranges,
+                              (uint32_t)T);
     if (st != SGS_OK) return st;
-    k_tile_ranges<uint32_t><<<(unsigned)cdiv(C, 256), 256, 0, s>>>(tk[0], 0, n_inst, (uint32_t)C,
-                                                                      (uint32_t)T, ranges);
-    SGS_LAUNCH_CHECK();
     if (keys) {
       k_make_keys64<<<(unsigned)cdiv(C, 256), 256, 0, s>>>(tk[0], vals, g->depth, mm, n_inst,
                                                             (uint32_t)C, keys);

@@ -45,6 +45,7 @@ struct BlendArgs {
   uint32_t* out_count;     // optional: contributing pairs per pixel
   const uint32_t* tile_order;  // optional: tiles in this order (longest lists first)
   uint32_t* work_counter;      // optional: persistent workgroups take tiles from it
+  int32_t n_quad;              // forward: the first n_quad tiles of tile_order run split
   // backward
   const float* cT;
   const uint32_t* clast;
@@ -59,6 +60,7 @@ struct TileSetup {
   int tile, view;
   int px, py;      // this thread's pixel
   int ox, oy;      // tile origin in pixels
+  int gx, gy;      // origin of the grid of wave blocks
   bool inside;
   const sgs_camera* cam;
 };
@@ -74,6 +76,8 @@ __device__ __forceinline__ bool setup_tile(const BlendArgs& a, int tile, TileSet
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   s.ox = tx * TW;
   s.oy = ty * TH;
+  s.gx = s.ox;
+  s.gy = s.oy;
   s.px = s.ox + (w % (TW / 8)) * 8 + (l & 7);
   s.py = s.oy + (w / (TW / 8)) * 8 + (l >> 3);
   s.inside = s.px < s.cam->width && s.py < s.cam->height;
@@ -124,10 +128,16 @@ __device__ __forceinline__ bool ellipse_meets_box(float a, float b, float c, flo
 }
 
 // Loads records [idx0, idx0 + cnt) of the tile list into the stage and builds
-// the per-wave lists.  Every thread of the block must call it.
-template <int TW, int TH, int B, bool ENH>
+// the per-wave lists.  Wave w owns the BS x BS pixel block at
+// (gx, gy) + BS * (w % GW, w / GW): 8x8 blocks covering the tile (GW = TW/8),
+// or 4x4 blocks covering an 8x8 quarter (GW = 2).  Every thread of the block
+// must call it.
+template <int TW, int TH, int B, bool ENH, int BS = 8>
 __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup& ts, uint32_t idx0,
                                             int cnt, Stage<TW, TH, B, ENH>& S) {
+  constexpr int GW = BS == 8 ? TW / 8 : 2;
+  constexpr float EXT = (float)(BS - 1);      // pixel-centre span of a block
+  constexpr float HALF = 0.5f * EXT;
   using St = Stage<TW, TH, B, ENH>;
   const int t = threadIdx.x, lane = t & 63;
   const uint64_t lt = lanemask_lt();
@@ -156,12 +166,12 @@ __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup&
         const float need = zc * 1.41421356f;
 #pragma unroll
         for (int w = 0; w < St::NW; ++w) {
-          const float lx = (float)(ts.ox + (w % (TW / 8)) * 8) + 0.5f;
-          const float ly = (float)(ts.oy + (w / (TW / 8)) * 8) + 0.5f;
-          bool hit = ellipse_meets_box(q0.z, q0.w, q1.x, R2, lx - q0.x - 0.01f, lx + 7.0f - q0.x + 0.01f,
-                                       ly - q0.y - 0.01f, ly + 7.0f - q0.y + 0.01f);
+          const float lx = (float)(ts.gx + (w % GW) * BS) + 0.5f;
+          const float ly = (float)(ts.gy + (w / GW) * BS) + 0.5f;
+          bool hit = ellipse_meets_box(q0.z, q0.w, q1.x, R2, lx - q0.x - 0.01f, lx + EXT - q0.x + 0.01f,
+                                       ly - q0.y - 0.01f, ly + EXT - q0.y + 0.01f);
           if (hit && zc > -1e29f) {
-            const float top = skew_box_max(q1.y, q1.z, lx + 3.5f, ly + 3.5f, q0.x, q0.y, 3.5f, 3.5f);
+            const float top = skew_box_max(q1.y, q1.z, lx + HALF, ly + HALF, q0.x, q0.y, HALF, HALF);
             hit = top + 1e-3f * (1.0f + fabsf(top) + fabsf(need)) >= need;
           }
           if (hit) msk |= 1u << w;
@@ -198,9 +208,13 @@ __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup&
 }
 
 // Tile of a one-workgroup-per-tile launch: the given order, else XCD bands.
+// (Forward with split tiles: the first 4 * n_quad workgroups run the quarters
+// of the first n_quad tiles of the order; the rest take the following ones.)
 __device__ __forceinline__ int launch_tile(const BlendArgs& a) {
-  if (a.tile_order)
-    return blockIdx.x < (uint32_t)a.total_tiles ? (int)a.tile_order[blockIdx.x] : a.total_tiles;
+  if (a.tile_order) {
+    const uint32_t idx = blockIdx.x - 3u * (uint32_t)a.n_quad;
+    return idx < (uint32_t)a.total_tiles ? (int)a.tile_order[idx] : a.total_tiles;
+  }
   return xcd_tile(blockIdx.x, a.total_tiles, gridDim.x);
 }
 
@@ -281,11 +295,117 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
   }
 }
 
+// Value of lane 4*(lane/4) + S (the same quad) in every lane of the quad.
+template <int S>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), S * 0x55, 0xf, 0xf, false));
+}
+template <int S>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_mov_dpp(v, S * 0x55, 0xf, 0xf, false);
+}
+
+// Forward of one 8x8 quarter of a 16x16 tile with four lanes per pixel: wave
+// w owns a 4x4 block; per round the four lanes of a pixel evaluate four
+// consecutive records of the wave's list (one each), then every lane of the
+// quad composites the four in list order.  Same decisions and the same
+// floating-point operations in the same order as fwd_tile: identical results.
+template <int B, bool ENH>
+__device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quarter,
+                                         Stage<16, 16, B, ENH>& S) {
+  TileSetup ts;
+  if (!setup_tile<16, 16>(a, tile, ts)) return;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, sub = lane & 3, pq = lane >> 2;
+  ts.gx = ts.ox + (quarter & 1) * 8;
+  ts.gy = ts.oy + (quarter >> 1) * 8;
+  ts.px = ts.gx + (w & 1) * 4 + (pq & 3);
+  ts.py = ts.gy + (w >> 1) * 4 + (pq >> 2);
+  ts.inside = ts.px < ts.cam->width && ts.py < ts.cam->height;
+  const float fx = (float)ts.px + 0.5f, fy = (float)ts.py + 0.5f;
+  uint2 rg = a.ranges[ts.tile];
+  rg.y = min(rg.y, a.n_vals);
+  rg.x = min(rg.x, rg.y);
+  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  uint32_t last = 0, count = 0;
+  bool done = !ts.inside;
+  for (uint32_t base = rg.x; base < rg.y; base += B) {
+    if (__syncthreads_and(done)) break;
+    const int cnt = (int)min((uint32_t)B, rg.y - base);
+    stage_batch<16, 16, B, ENH, 4>(a, ts, base, cnt, S);
+    const int nw = S.n[w];
+    for (int i = 0; i < nw; i += 4) {
+      const int k = i + sub;
+      const bool has = k < nw;
+      const int j = has ? S.list[w][k] : 0;
+      const float4 r0 = S.r0[j];
+      const float4 r1 = S.r1[j];
+      const float4 r2 = S.r2[j];
+      const float dx = fx - r0.x, dy = fy - r0.y;
+      const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
+      const bool in = has && !done && power >= r2.w;
+      float alpha = 0.0f;
+      if (__any(in)) {
+        Pair p;
+        pair_eval(power, r1.w, r1.y, r1.z, dx, dy, (r1.y != 0.0f) || (r1.z != 0.0f), p);
+        float at = p.at;
+        if (ENH) {
+          const float4 r3 = S.r3[j];
+          float eu, ee;
+          at *= enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
+        }
+        alpha = fminf(a.alpha_max, at);
+      }
+      const int take = (in && alpha >= a.alpha_min) ? 1 : 0;
+      const int jj = j;
+      const float cr = r2.x, cg = r2.y, cb = r2.z;
+#define SGS_QUAD_STEP(Q)                                                     \
+      {                                                                      \
+        const float al = quad_bcast<Q>(alpha);                               \
+        if (quad_bcast<Q>(take) && !done) {                                  \
+          const float Tn = T * (1.0f - al);                                  \
+          if (Tn < a.t_min) {                                                \
+            done = true;                                                     \
+          } else {                                                           \
+            const float wgt = al * T;                                        \
+            C0 = fmaf(quad_bcast<Q>(cr), wgt, C0);                           \
+            C1 = fmaf(quad_bcast<Q>(cg), wgt, C1);                           \
+            C2 = fmaf(quad_bcast<Q>(cb), wgt, C2);                           \
+            T = Tn;                                                          \
+            last = base - rg.x + (uint32_t)quad_bcast<Q>(jj) + 1u;           \
+            ++count;                                                         \
+          }                                                                  \
+        }                                                                    \
+      }
+      SGS_QUAD_STEP(0)
+      SGS_QUAD_STEP(1)
+      SGS_QUAD_STEP(2)
+      SGS_QUAD_STEP(3)
+#undef SGS_QUAD_STEP
+      if (__all(done)) break;
+    }
+  }
+  if (ts.inside && sub == 0) {
+    const int64_t pix = ts.cam->pix_base + (int64_t)ts.py * ts.cam->width + ts.px;
+    a.out_rgb[pix] = fmaf(T, ts.cam->bg[0], C0);
+    a.out_rgb[a.P + pix] = fmaf(T, ts.cam->bg[1], C1);
+    a.out_rgb[2 * a.P + pix] = fmaf(T, ts.cam->bg[2], C2);
+    a.out_T[pix] = T;
+    a.out_last[pix] = last;
+    if (a.out_count) a.out_count[pix] = count;
+  }
+}
+
 template <int TW, int TH, int B, bool ENH>
 __global__ void __launch_bounds__(TW * TH) k_blend_fwd(BlendArgs a) {
   __shared__ Stage<TW, TH, B, ENH> S;
   __shared__ uint32_t s_next;
   if (!a.work_counter) {
+    if constexpr (TW == 16 && TH == 16) {
+      if (blockIdx.x < 4u * (uint32_t)a.n_quad) {
+        fwd_quad<B, ENH>(a, (int)a.tile_order[blockIdx.x >> 2], (int)(blockIdx.x & 3u), S);
+        return;
+      }
+    }
     fwd_tile<TW, TH, B, ENH>(a, launch_tile(a), S);
     return;
   }
@@ -300,6 +420,45 @@ struct BwdShared {
   float sg[NG][B];
   uint32_t smax;
 };
+
+// Writes a batch's per-record sums (LDS) to the 2D gradient planes.
+template <int TW, int TH, int B, bool ENH>
+__device__ __forceinline__ void flush_batch(const BlendArgs& a, int cnt, BwdShared<TW, TH, B, ENH>& X) {
+  constexpr int NT = TW * TH;
+  constexpr int NG = BwdShared<TW, TH, B, ENH>::NG;
+  for (int k = threadIdx.x; k < cnt; k += NT) {
+    float v[NG];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      v[q] = X.sg[q][k];
+      any |= v[q] != 0.0f;
+    }
+    if (!any) continue;
+    const uint32_t m = X.S.rid[k];
+    float* p0 = reinterpret_cast<float*>(a.g0 + m);
+    float* p1 = reinterpret_cast<float*>(a.g1 + m);
+    float* p2 = reinterpret_cast<float*>(a.g2 + m);
+    atomicAdd(p0 + 0, v[0]);
+    atomicAdd(p0 + 1, v[1]);
+    atomicAdd(p0 + 2, v[2]);
+    atomicAdd(p0 + 3, v[3]);
+    atomicAdd(p1 + 0, v[4]);
+    atomicAdd(p1 + 1, v[5]);
+    atomicAdd(p1 + 2, v[6]);
+    atomicAdd(p1 + 3, v[7]);
+    atomicAdd(p2 + 0, v[8]);
+    atomicAdd(p2 + 1, v[9]);
+    atomicAdd(p2 + 2, v[10]);
+    if (ENH) {
+      float* p3 = reinterpret_cast<float*>(a.g3 + m);
+      atomicAdd(p3 + 0, v[11]);
+      atomicAdd(p3 + 1, v[12]);
+      atomicAdd(p3 + 2, v[13]);
+      atomicAdd(p3 + 3, v[14]);
+    }
+  }
+}
 
 template <int TW, int TH, int B, bool ENH>
 __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared<TW, TH, B, ENH>& X) {
@@ -412,38 +571,161 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
       }
     }
     __syncthreads();
-    for (int k = t; k < cnt; k += NT) {
-      float v[NG];
-      bool any = false;
+    flush_batch<TW, TH, B, ENH>(a, cnt, X);
+  }
+}
+
+// Backward of one 8x8 quarter of a 16x16 tile with four lanes per pixel
+// (the counterpart of fwd_quad).  Per round the four lanes of a pixel take
+// four consecutive records of the wave's list, walking backwards: each lane
+// evaluates its record's alpha, the quad then runs the transmittance and
+// colour-behind recursion over the four in list order (replicated, so T and
+// S are those of bwd_tile bit for bit), and each lane computes its record's
+// partial derivatives with the T and S in front of it.  Sums over the 16
+// pixels that share a record take four shuffles.
+template <int B, bool ENH>
+__device__ __forceinline__ void bwd_quad(const BlendArgs& a, int tile, int quarter,
+                                         BwdShared<16, 16, B, ENH>& X) {
+  constexpr int NT = 256;
+  constexpr int NG = BwdShared<16, 16, B, ENH>::NG;
+  auto& S = X.S;
+  auto& sg = X.sg;
+  TileSetup ts;
+  if (!setup_tile<16, 16>(a, tile, ts)) return;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, sub = lane & 3, pq = lane >> 2;
+  ts.gx = ts.ox + (quarter & 1) * 8;
+  ts.gy = ts.oy + (quarter >> 1) * 8;
+  ts.px = ts.gx + (w & 1) * 4 + (pq & 3);
+  ts.py = ts.gy + (w >> 1) * 4 + (pq >> 2);
+  ts.inside = ts.px < ts.cam->width && ts.py < ts.cam->height;
+  const float fx = (float)ts.px + 0.5f, fy = (float)ts.py + 0.5f;
+  uint2 rg = a.ranges[ts.tile];
+  rg.y = min(rg.y, a.n_vals);
+  rg.x = min(rg.x, rg.y);
+  float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+  uint32_t last = 0;
+  if (ts.inside) {
+    const int64_t pix = ts.cam->pix_base + (int64_t)ts.py * ts.cam->width + ts.px;
+    T = a.cT[pix];
+    last = min(a.clast[pix], rg.y - rg.x);
+    g0 = a.dL[pix];
+    g1 = a.dL[a.P + pix];
+    g2 = a.dL[2 * a.P + pix];
+  }
+  const float bgdot = ts.cam->bg[0] * g0 + ts.cam->bg[1] * g1 + ts.cam->bg[2] * g2;
+  const float Tfinal = T;
+  float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
+  if (t == 0) X.smax = 0;
+  __syncthreads();
+  if (last) atomicMax(&X.smax, last);
+  __syncthreads();
+  const int nmax = (int)X.smax;
+  for (int end = nmax; end > 0; end -= B) {
+    const int start = end > B ? end - B : 0;
+    const int cnt = end - start;
+    __syncthreads();
+    stage_batch<16, 16, B, ENH, 4>(a, ts, rg.x + start, cnt, S);
+    for (int k = t; k < NG * B; k += NT) (&sg[0][0])[k] = 0.0f;
+    __syncthreads();
+    const int nw = S.n[w];
+    for (int i = nw - 1; i >= 0; i -= 4) {
+      const int k = i - sub;
+      const bool has = k >= 0;
+      const int j = has ? S.list[w][k] : 0;
+      const float4 r0 = S.r0[j];
+      const float4 r1 = S.r1[j];
+      const float4 r2 = S.r2[j];
+      const float dx = fx - r0.x, dy = fy - r0.y;
+      const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
+      const bool in = has && (uint32_t)(start + j) < last && power >= r2.w;
+      Pair p;
+      p.G = p.E = p.ez = 1.0f;
+      float at = 0.0f, o = 1.0f, eu = 0.0f, ee = 1.0f, alpha = 0.0f;
+      float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (__any(in)) {
+        pair_eval(power, r1.w, r1.y, r1.z, dx, dy, (r1.y != 0.0f) || (r1.z != 0.0f), p);
+        at = p.at;
+        if (ENH) {
+          r3 = S.r3[j];
+          o = enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
+          at *= o;
+        }
+        alpha = fminf(a.alpha_max, at);
+      }
+      const bool hit = in && alpha >= a.alpha_min;
+      if (!__any(hit)) continue;
+      // transmittance and colour-behind recursion, records in list order
+      // (latest first), replicated on the quad
+      const int hi = hit ? 1 : 0;
+      const float cr = r2.x, cg = r2.y, cb = r2.z;
+      float Tm = 0.0f, Sm0 = 0.0f, Sm1 = 0.0f, Sm2 = 0.0f;
+#define SGS_QUAD_BACK(Q)                                                     \
+      if (quad_bcast<Q>(hi)) {                                               \
+        const float al = quad_bcast<Q>(alpha);                               \
+        T = T / (1.0f - al);                                                 \
+        if (sub == Q) {                                                      \
+          Tm = T;                                                            \
+          Sm0 = S0;                                                          \
+          Sm1 = S1;                                                          \
+          Sm2 = S2;                                                          \
+        }                                                                    \
+        S0 = fmaf(al, quad_bcast<Q>(cr) - S0, S0);                           \
+        S1 = fmaf(al, quad_bcast<Q>(cg) - S1, S1);                           \
+        S2 = fmaf(al, quad_bcast<Q>(cb) - S2, S2);                           \
+      }
+      SGS_QUAD_BACK(0)
+      SGS_QUAD_BACK(1)
+      SGS_QUAD_BACK(2)
+      SGS_QUAD_BACK(3)
+#undef SGS_QUAD_BACK
+      float gv[NG];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) gv[q] = 0.0f;
+      if (hit) {
+        const float wgt = alpha * Tm;
+        gv[8] = wgt * g0;
+        gv[9] = wgt * g1;
+        gv[10] = wgt * g2;
+        float dLda = ((r2.x - Sm0) * g0 + (r2.y - Sm1) * g1 + (r2.z - Sm2) * g2) * Tm;
+        dLda -= Tfinal / (1.0f - alpha) * bgdot;
+        if (at <= a.alpha_max) {
+          const float dd = r1.w * o;
+          const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
+          const float common = dLda * dd * p.G;
+          const float qa = fmaf(r0.z, dx, r0.w * dy), qc = fmaf(r0.w, dx, r1.x * dy);
+          gv[0] = common * (qa * p.E - s2pi * r1.y);
+          gv[1] = common * (qc * p.E - s2pi * r1.z);
+          gv[2] = -0.5f * dx * dx * dLda * at;
+          gv[3] = -dx * dy * dLda * at;
+          gv[4] = -0.5f * dy * dy * dLda * at;
+          gv[5] = common * s2pi * dx;
+          gv[6] = common * s2pi * dy;
+          gv[7] = dLda * p.G * p.E * o;
+          if (ENH) {
+            const float base = p.at;
+            const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
+            gv[0] -= dLda * base * dodw * r3.z;
+            gv[1] -= dLda * base * dodw * r3.w;
+            gv[11] = dLda * base * 0.5f * (1.0f + eu);
+            gv[12] = dLda * base * 0.5f * (1.0f - eu);
+            gv[13] = dLda * base * dodw * dx;
+            gv[14] = dLda * base * dodw * dy;
+          }
+        }
+      }
+      // sums over the 16 pixels of each sublane; lanes 0..3 hold sublanes 0..3
 #pragma unroll
       for (int q = 0; q < NG; ++q) {
-        v[q] = sg[q][k];
-        any |= v[q] != 0.0f;
-      }
-      if (!any) continue;
-      const uint32_t m = S.rid[k];
-      float* p0 = reinterpret_cast<float*>(a.g0 + m);
-      float* p1 = reinterpret_cast<float*>(a.g1 + m);
-      float* p2 = reinterpret_cast<float*>(a.g2 + m);
-      atomicAdd(p0 + 0, v[0]);   // mu_x
-      atomicAdd(p0 + 1, v[1]);   // mu_y
-      atomicAdd(p0 + 2, v[2]);   // a
-      atomicAdd(p0 + 3, v[3]);   // b
-      atomicAdd(p1 + 0, v[4]);   // c
-      atomicAdd(p1 + 1, v[5]);   // beta_x
-      atomicAdd(p1 + 2, v[6]);   // beta_y
-      atomicAdd(p1 + 3, v[7]);   // d (rho with enhanced opacity)
-      atomicAdd(p2 + 0, v[8]);   // r
-      atomicAdd(p2 + 1, v[9]);   // g
-      atomicAdd(p2 + 2, v[10]);  // b
-      if (ENH) {
-        float* p3 = reinterpret_cast<float*>(a.g3 + m);
-        atomicAdd(p3 + 0, v[11]);  // alpha_1
-        atomicAdd(p3 + 1, v[12]);  // alpha_2
-        atomicAdd(p3 + 2, v[13]);  // w_x
-        atomicAdd(p3 + 3, v[14]);  // w_y
+        float v = gv[q];
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (lane < 4 && has && v != 0.0f) atomicAdd(&sg[q][j], v);
       }
     }
+    __syncthreads();
+    flush_batch<16, 16, B, ENH>(a, cnt, X);
   }
 }
 
@@ -452,6 +734,12 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(BlendArgs a) {
   __shared__ BwdShared<TW, TH, B, ENH> X;
   __shared__ uint32_t s_next;
   if (!a.work_counter) {
+    if constexpr (TW == 16 && TH == 16) {
+      if (blockIdx.x < 4u * (uint32_t)a.n_quad) {
+        bwd_quad<B, ENH>(a, (int)a.tile_order[blockIdx.x >> 2], (int)(blockIdx.x & 3u), X);
+        return;
+      }
+    }
     bwd_tile<TW, TH, B, ENH>(a, launch_tile(a), X);
     return;
   }
@@ -546,6 +834,16 @@ static BlendArgs make_args(const sgs_geom* g, int64_t m, const uint32_t* vals, i
 
 static unsigned blend_grid(int64_t total_tiles) { return (unsigned)((total_tiles + 7) / 8 * 8); }
 
+// Split tiles (16x16 tiles with a tile order, no work counter): the first
+// n_quad tiles of the order get four workgroups each, ahead of the others.
+static void split_setup(BlendArgs& a, const sgs_options* opt, int64_t total_tiles, unsigned& grid) {
+  if (a.tile_order && !a.work_counter && opt->tile_w == 16 && opt->tile_h == 16 && opt->split_tiles != 0) {
+    const int64_t q = opt->split_tiles < 0 ? total_tiles / 32 : std::min<int64_t>(opt->split_tiles, total_tiles);
+    a.n_quad = (int32_t)q;
+    grid += 3u * (unsigned)q;
+  }
+}
+
 sgs_status launch_blend_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals, int64_t cap,
                             const uint32_t* ranges, const sgs_schedule* sched,
                             const sgs_camera* cams_dev, int32_t n_views,
@@ -557,7 +855,8 @@ sgs_status launch_blend_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals, 
   a.out_T = out_T;
   a.out_last = out_last;
   a.out_count = out_count;
-  const unsigned grid = blend_grid(total_tiles);
+  unsigned grid = blend_grid(total_tiles);
+  split_setup(a, opt, total_tiles, grid);
   return enhanced ? dispatch_tile<false, true>(a, opt, grid, s)
                   : dispatch_tile<false, false>(a, opt, grid, s);
 }
@@ -577,7 +876,8 @@ sgs_status launch_blend_bwd(const sgs_geom* g, int64_t m, const uint32_t* vals, 
   a.g1 = gr + m;
   a.g2 = gr + 2 * m;
   a.g3 = gr + 3 * m;
-  const unsigned grid = blend_grid(total_tiles);
+  unsigned grid = blend_grid(total_tiles);
+  split_setup(a, opt, total_tiles, grid);
   return enhanced ? dispatch_tile<true, true>(a, opt, grid, s)
                   : dispatch_tile<true, false>(a, opt, grid, s);
 }

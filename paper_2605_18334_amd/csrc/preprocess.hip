@@ -177,17 +177,28 @@ __device__ __forceinline__ void project_fwd(const sgs_params& p, const sgs_camer
             isfinite(P.w2y);
 }
 
+// Tile counting runs per wave over (record, tile row) items: each lane
+// projects its record and sets up its span, then the wave enumerates the
+// rows of its 64 records 64 at a time (the owner's span is fetched with
+// shuffles), so records with tall rects do not hold their wave back.
 template <int DEG>
 __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
+  __shared__ uint32_t s_pref[4][65];   // per wave: exclusive prefix of the records' rows
+  __shared__ uint32_t s_cnt[256];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int v = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 256 + t;
+  const int64_t m = (int64_t)v * a.n + i;
   const sgs_camera& cam = a.cams[v];
-  uint32_t ntiles = 0;
+  Span sp;
+  sp.ok = sp.cut = false;
+  int tx0 = 0, tx1 = 0, ty0 = 0;
+  uint32_t rows = 0, rx = 0, ry = 0;
+  float tz = 0.0f;
   if (i < a.n) {
-    const int64_t m = (int64_t)v * a.n + i;
     Proj P;
     project_fwd<DEG>(a.p, cam, a.opt, i, a.n, P);
-    uint32_t rx = 0, ry = 0;
+    tz = P.tz;
     if (P.valid) {
       const bool has_skew = (P.b2x != 0.0f) || (P.b2y != 0.0f);
       const float dmax = P.rho * fmaxf(P.o1, P.o2);
@@ -207,24 +218,19 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
           x1 = fminf(x1, (float)(cam.width - 1));
           y1 = fminf(y1, (float)(cam.height - 1));
           if (x0 <= x1 && y0 <= y1) {
-            const int tx0 = (int)x0 / a.opt.tile_w, tx1 = (int)x1 / a.opt.tile_w + 1;
-            const int ty0 = (int)y0 / a.opt.tile_h, ty1 = (int)y1 / a.opt.tile_h + 1;
+            tx0 = (int)x0 / a.opt.tile_w;
+            tx1 = (int)x1 / a.opt.tile_w + 1;
+            ty0 = (int)y0 / a.opt.tile_h;
+            const int ty1 = (int)y1 / a.opt.tile_h + 1;
             rx = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
             ry = (uint32_t)tx1 | ((uint32_t)ty1 << 16);
+            rows = (uint32_t)(ty1 - ty0);
             const float thr = -L - 1e-3f;   // power below thr => alpha < alpha_min
             // stored opacity factor: rho * alpha_1, or rho alone with enhanced
             // opacity (an upper bound of rho * o(delta), so the cut stays safe)
             const float d = a.enhanced ? P.rho : P.rho * P.o1;
             const float zc = has_skew ? skew_zcut(a.opt.alpha_min, d) : -1e30f;
-            // tiles of the rect that the evaluation ellipse (cut by the skew
-            // half-plane) reaches, row by row
-            Span sp;
             span_setup(P.mux, P.muy, P.a, P.b, P.c, thr, P.b2x, P.b2y, zc, sp);
-            for (int row = ty0; row < ty1; ++row) {
-              int c0, c1;
-              span_row(sp, row, a.opt.tile_w, a.opt.tile_h, tx0, tx1, c0, c1);
-              ntiles += (uint32_t)(c1 - c0);
-            }
             const int64_t M = a.m;
             float4* rec = reinterpret_cast<float4*>(a.rec);
             rec[m] = make_float4(P.mux, P.muy, P.a, P.b);
@@ -235,8 +241,57 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
         }
       }
     }
+  }
+  // tiles of each rect that the evaluation ellipse (cut by the skew
+  // half-plane) reaches, row by row, per wave
+  uint32_t incl = rows;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  s_pref[w][lane] = incl - rows;
+  if (lane == 63) s_pref[w][64] = incl;
+  s_cnt[t] = 0;
+  __syncthreads();
+  const uint32_t R = s_pref[w][64];
+  for (uint32_t base = 0; base < R; base += 64) {
+    const uint32_t it = base + lane;
+    int o = 0;
+    if (it < R) {   // owner: last lane whose first row is <= it
+      int lo = 0, hi = 64;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pref[w][mid] <= it) lo = mid; else hi = mid;
+      }
+      o = lo;
+    }
+    Span so;
+    so.mx = __shfl(sp.mx, o);
+    so.my = __shfl(sp.my, o);
+    so.b = __shfl(sp.b, o);
+    so.det = __shfl(sp.det, o);
+    so.ia = __shfl(sp.ia, o);
+    so.aR2 = __shfl(sp.aR2, o);
+    so.ey = __shfl(sp.ey, o);
+    so.ex = __shfl(sp.ex, o);
+    so.yx = __shfl(sp.yx, o);
+    so.bx = __shfl(sp.bx, o);
+    so.by = __shfl(sp.by, o);
+    so.need = __shfl(sp.need, o);
+    so.ok = __shfl((int)sp.ok, o) != 0;
+    so.cut = __shfl((int)sp.cut, o) != 0;
+    const int ox0 = __shfl(tx0, o), ox1 = __shfl(tx1, o), oy0 = __shfl(ty0, o);
+    if (it < R) {
+      int c0, c1;
+      span_row(so, oy0 + (int)(it - s_pref[w][o]), a.opt.tile_w, a.opt.tile_h, ox0, ox1, c0, c1);
+      if (c1 > c0) atomicAdd(&s_cnt[w * 64 + o], (uint32_t)(c1 - c0));
+    }
+  }
+  __syncthreads();
+  const uint32_t ntiles = s_cnt[t];
+  if (i < a.n) {
     // records without tiles get all-ones bits: they sort after every finite depth
-    a.depth[m] = ntiles ? P.tz : __uint_as_float(0xffffffffu);
+    a.depth[m] = ntiles ? tz : __uint_as_float(0xffffffffu);
     a.tiles[m] = ntiles;
     reinterpret_cast<uint2*>(a.rect)[m] = make_uint2(rx, ry);
   }
@@ -244,10 +299,9 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
   uint32_t s = ntiles;
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   __shared__ uint32_t ws[4];
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  if (lane == 0) ws[w] = s;
   __syncthreads();
-  if (threadIdx.x == 0)
-    a.block_sums[(int64_t)v * a.nbx + blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+  if (t == 0) a.block_sums[(int64_t)v * a.nbx + blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
 // Exclusive scan of nb block sums into out[0..nb], out[nb] = total.  One

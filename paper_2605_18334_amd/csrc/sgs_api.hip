@@ -38,7 +38,7 @@ bool options_ok(const sgs_options* o) {
   return tile && batch && isfinite(o->filter_s) && o->filter_s >= 0.0f && isfinite(o->guard) &&
          o->guard > 0.0f && o->alpha_min > 0.0f && o->alpha_min < o->alpha_max &&
          o->alpha_max < 1.0f && o->t_min > 0.0f && o->t_min < 1.0f &&
-         (o->sort_mode == 0 || o->sort_mode == 1);
+         (o->sort_mode == 0 || o->sort_mode == 1) && o->split_tiles >= -1;
 }
 
 bool params_ok(const sgs_params* p) {
@@ -89,6 +89,7 @@ void sgs_default_options(sgs_options* o) {
   o->t_min = 1e-4f;
   o->sort_mode = 1;
   o->blend_batch = 256;
+  o->split_tiles = -1;
 }
 
 size_t sgs_struct_size(int32_t which) {

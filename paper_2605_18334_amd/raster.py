@@ -306,7 +306,7 @@ class Renderer:
 
     def __init__(self, gs: GaussianSet, cams: CameraBatch, opt: _abi.Options | None = None,
                  capacity: int | None = None, headroom: float = 1.25, keep_keys: bool = False,
-                 count: bool = False, tile_order: bool = False, persistent: bool = False):
+                 count: bool = False, tile_order: bool = True, persistent: bool = False):
         self.lib = load()
         self.gs, self.cams = gs, cams
         self.opt = opt if opt is not None else _abi.default_options()

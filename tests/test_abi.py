@@ -46,6 +46,7 @@ def test_default_options_and_status_strings():
     _abi, lib = _lib()
     o = _abi.default_options()
     assert (o.tile_w, o.tile_h, o.blend_batch, o.sort_mode, o.compensate) == (16, 16, 256, 1, 1)
+    assert o.split_tiles == -1
     assert o.alpha_min == pytest.approx(1 / 255) and o.alpha_max == pytest.approx(0.99)
     assert o.t_min == pytest.approx(1e-4) and o.filter_s == pytest.approx(0.3)
     assert lib.sgs_status_string(0) == b"ok"
@@ -125,3 +126,19 @@ def test_entry_points_reject_null_arguments_without_gpu():
                               None, 0, None) == 1
     assert lib.sgs_render_bwd(None, None, 0, None, 0, None, None, None, None, 1, C.byref(o), None, None, None,
                               0, None, None, None) == 1
+
+
+def test_options_are_validated_on_the_host():
+    """sgs_camera_layout checks the options (no GPU needed): unsupported tile
+    shapes, LDS batches, sort modes and split counts are rejected."""
+    _abi, lib = _lib()
+    cams = (_abi.Camera * 1)()
+    cams[0].width, cams[0].height = 64, 48
+    tt, tp = C.c_int64(), C.c_int64()
+    ok = _abi.default_options()
+    assert lib.sgs_camera_layout(cams, 1, C.byref(ok), C.byref(tt), C.byref(tp)) == 0
+    assert (tt.value, tp.value) == (4 * 3, 64 * 48)
+    for bad in (dict(tile_w=32), dict(blend_batch=100), dict(sort_mode=2), dict(split_tiles=-2),
+                dict(alpha_min=0.0), dict(t_min=1.0)):
+        o = _abi.default_options(**bad)
+        assert lib.sgs_camera_layout(cams, 1, C.byref(o), C.byref(tt), C.byref(tp)) == 1, bad
