@@ -145,14 +145,16 @@ typedef struct {
 
 /* Projected per-record data written by sgs_preprocess, record m = v*N + i for
  * view v and Gaussian i (M = n_views * N records).  Device pointers; sizes
- * from sgs_geom_floats.  `rec` holds R float4 planes of M entries:
- *   plane 0: (mu_x, mu_y, a, b)   2D mean in pixels, conic (Sigma'+sI)^-1 = [[a,b],[b,c]]
- *   plane 1: (c, beta_x, beta_y, d)  2D skew; d = rho*alpha_1 (rho with enhanced opacity)
- *   plane 2: (r, g, b, log_thr)   colour; log_thr: below this exponent a pair is skipped
- *   plane 3: (alpha_1, alpha_2, w_x, w_y)  only with enhanced opacity (R = 4)
+ * from sgs_geom_rec_floats.  `rec` holds one 64-byte entry of four float4
+ * slots per record (a record is gathered whole by index, so one entry is
+ * one cache line):
+ *   slot 0: (mu_x, mu_y, a, b)   2D mean in pixels, conic (Sigma'+sI)^-1 = [[a,b],[b,c]]
+ *   slot 1: (c, beta_x, beta_y, d)  2D skew; d = rho*alpha_1 (rho with enhanced opacity)
+ *   slot 2: (r, g, b, log_thr)   colour; log_thr: below this exponent a pair is skipped
+ *   slot 3: (alpha_1, alpha_2, w_x, w_y)  with enhanced opacity; unspecified otherwise
  */
 typedef struct {
-  float* rec;              /* [R][M][4]                                     */
+  float* rec;              /* [M][4][4]                                     */
   float* depth;            /* [M] camera-space z (the sort key); all-ones
                               bits (a NaN) for records without tiles       */
   uint32_t* rect;          /* [M][2] tile rect: (x0 | y0<<16, x1 | y1<<16), half-open */
@@ -179,7 +181,9 @@ typedef struct {
 } sgs_schedule;
 
 /* Accumulated (+=) gradient of the loss w.r.t. the projected records, same
- * [R][M][4] layout as sgs_geom.rec (plane 2 .w unused).  Device pointer. */
+ * [R][M][4] planes (R = 3, or 4 with enhanced opacity): plane k holds the
+ * gradients of record slot k of sgs_geom.rec (plane 2 .w unused).  Device
+ * pointer, sgs_geom_rec_floats(M, enhanced) floats. */
 typedef struct {
   float* rec;
 } sgs_geom_grad;

@@ -44,8 +44,11 @@ constexpr int RS_MAX_PASSES = 8;
 constexpr uint64_t ST_AGG = 1ull << 32;    // status: block's own digit count
 constexpr uint64_t ST_INC = 2ull << 32;    // status: inclusive prefix over blocks
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
-constexpr int LB_W = 8;            // look-back: predecessor statuses read at once
+// look-back: predecessor statuses read at once (a template parameter of the
+// pass kernel; 8 measured best: 32 slowed both small and large sorts)
+constexpr int LB_W = 8;
 constexpr int HC = 64;             // copies of the digit histograms (atomic contention)
+constexpr uint64_t HC_MIN_BLOCKS = 1024;   // fewer blocks: one copy, no final sum
 constexpr uint32_t N_INVALID = 0xffffffffu;   // instance count after a failed look-back
 
 __device__ __forceinline__ uint32_t count_of(const uint32_t* n_dev, uint32_t n_host, uint32_t cap) {
@@ -86,12 +89,14 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* ws4
 }
 
 // Digit histograms of every pass in one read of the keys, added into copy
-// (block % HC) of the partial histograms [HC][passes][256]: many blocks
-// adding into one set of 256 words serialise on those addresses.
+// (block % ncopies) of the partial histograms [ncopies][passes][256]: many
+// blocks adding into one set of 256 words serialise on those addresses
+// (ncopies = 1 adds straight into the final histograms).
 template <typename K, int RS_IPT>
 __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, const uint32_t* n_dev,
                                                   uint32_t n_host, uint32_t cap, int passes,
-                                                  int width, uint32_t* __restrict__ hpart) {
+                                                  int width, uint32_t* __restrict__ hpart,
+                                                  int ncopies) {
   __shared__ uint32_t h[RS_MAX_PASSES][256];
   const int t = threadIdx.x;
   const uint32_t dmask = (1u << width) - 1u;
@@ -108,7 +113,7 @@ __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, co
     }
   }
   __syncthreads();
-  uint32_t* dst = hpart + (size_t)(blockIdx.x % HC) * passes * 256;
+  uint32_t* dst = hpart + (size_t)(blockIdx.x % (unsigned)ncopies) * passes * 256;
   for (int p = 0; p < passes; ++p)
     if (h[p][t]) atomicAdd(&dst[p * 256 + t], h[p][t]);
 }
@@ -128,7 +133,7 @@ __global__ void __launch_bounds__(256) k_hist_final(const uint32_t* __restrict__
 // ranges != nullptr (last pass over tile keys): every run of equal keys in
 // the block's output lowers ranges[2 key] to its first position and raises
 // ranges[2 key + 1] to its end (ranges start as [0xffffffff, 0)).
-template <typename K, int RS_IPT>
+template <typename K, int RS_IPT, int LB_W>
 __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
                                                   const uint32_t* __restrict__ vin,
                                                   K* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -280,9 +285,7 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
 
 // ------------------------------------------------------------- duplicate
 struct DupArgs {
-  const float4* rec0;    // record planes: (mu_x, mu_y, a, b), (c, beta, d), (..., log_thr)
-  const float4* rec1;
-  const float4* rec2;
+  const float4* rec;     // [M][4] record slots: (mu_x, mu_y, a, b), (c, beta, d), (..., log_thr), ...
   float alpha_min;
   int32_t tile_w, tile_h;
   const uint32_t* rect;
@@ -301,8 +304,9 @@ struct DupArgs {
   const uint32_t* order; // mode 1: records in depth order
   const uint32_t* offs;  // mode 1: exclusive instance offset of order[j]
   uint32_t* hpart;       // mode 1: partial digit histograms [HC][hpasses][256] of the tile keys
-  int32_t hpasses;       //         digits of hwidth bits
+  int32_t hpasses;       //         digits of hwidth bits, hcopies copies
   int32_t hwidth;
+  int32_t hcopies;
   int64_t m;
 };
 
@@ -327,7 +331,8 @@ __global__ void __launch_bounds__(256) k_duplicate64(DupArgs a) {
   const int x0 = r.x & 0xffffu, y0 = r.x >> 16, x1 = r.y & 0xffffu, y1 = r.y >> 16;
   const sgs_camera& cam = a.cams[v];
   const uint64_t lo = (uint64_t)__float_as_uint(a.depth[m]);
-  const float4 q0 = a.rec0[m], q1 = a.rec1[m], q2 = a.rec2[m];
+  const float4* rp = a.rec + 4 * (uint64_t)m;
+  const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2];
   Span sp;
   span_setup(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, record_zcut(a, q1), sp);
   uint32_t k = off;
@@ -535,7 +540,8 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
       const uint2 r = reinterpret_cast<const uint2*>(a.rect)[rm];
       const int x0 = r.x & 0xffffu, x1 = r.y & 0xffffu;
       const int row = (int)(r.x >> 16) + (int)(i - s_rows[lo]);
-      const float4 q0 = a.rec0[rm], q1 = a.rec1[rm], q2 = a.rec2[rm];
+      const float4* rp = a.rec + 4 * rm;
+      const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2];
       Span sp;
       span_setup(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, record_zcut(a, q1), sp);
       int c1;
@@ -566,7 +572,7 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
     run += s_tot;
     __syncthreads();
   }
-  uint32_t* hdst = a.hpart + (size_t)(blockIdx.x % HC) * a.hpasses * 256;
+  uint32_t* hdst = a.hpart + (size_t)(blockIdx.x % (unsigned)a.hcopies) * a.hpasses * 256;
   for (int p = 0; p < a.hpasses; ++p)
     if (hist[p][t]) atomicAdd(&hdst[p * 256 + t], hist[p][t]);
 }
@@ -707,30 +713,38 @@ static RsScratch rs_carve(uint32_t* p, int passes, uint32_t* err, uint32_t* n_fo
 // Sorts by bits [0, bits), one kernel per pass of rs_width(bits) bits.  Pass 0 reads
 // (kin, vin) (vin == nullptr: values are the positions); the result lands in
 // (kb[0], vb[0]).  kin may be kb[passes & 1] (sorting in place) or another
-// buffer.  The scratch must be zero, except that with hist_done its partial
-// digit histograms already hold the counts of the keys.  With ranges, the last
+// buffer.  The scratch must be zero, except that with hist_done the digit
+// histograms already hold the counts of the keys: in the partial copies when
+// the hist_blocks_done blocks that counted them exceed HC_MIN_BLOCKS, else in
+// the final histograms.  With ranges, the last
 // pass also writes the tile ranges of the sorted keys (see k_os_pass).
 template <typename K>
 static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32_t* vb[2],
                              const uint32_t* n_dev, uint32_t n_host, uint64_t cap, int bits,
                              RsScratch sc, hipStream_t s, bool hist_done = false,
-                             uint32_t* ranges = nullptr, uint32_t n_tiles = 0) {
+                             uint64_t hist_blocks_done = 0, uint32_t* ranges = nullptr,
+                             uint32_t n_tiles = 0) {
   const uint64_t blocks = rs_blocks(cap);
   const int passes = rs_passes(bits);
   const int width = rs_width(bits);
+  const uint64_t hist_blocks = hist_done ? hist_blocks_done : blocks;
+  const bool copies = hist_blocks > HC_MIN_BLOCKS;
   if (!hist_done) {
     k_os_hist<K, RS_IPT><<<(unsigned)blocks, RS_T, 0, s>>>(kin, n_dev, n_host, (uint32_t)cap, passes,
-                                                            width, sc.hpart);
+                                                            width, copies ? sc.hpart : sc.ghist,
+                                                            copies ? HC : 1);
     SGS_LAUNCH_CHECK();
   }
-  k_hist_final<<<passes, 256, 0, s>>>(sc.hpart, passes, sc.ghist);
-  SGS_LAUNCH_CHECK();
+  if (copies) {
+    k_hist_final<<<passes, 256, 0, s>>>(sc.hpart, passes, sc.ghist);
+    SGS_LAUNCH_CHECK();
+  }
   for (int p = 0; p < passes; ++p) {
     const int nb = std::min(width, bits - width * p);
     const int dst = (passes - 1 - p) & 1;
     const K* ki = p == 0 ? kin : kb[dst ^ 1];
     const uint32_t* vi = p == 0 ? vin : vb[dst ^ 1];
-    k_os_pass<K, RS_IPT><<<(unsigned)blocks, RS_T, 0, s>>>(
+    k_os_pass<K, RS_IPT, LB_W><<<(unsigned)blocks, RS_T, 0, s>>>(
         ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
         sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
         p == passes - 1 ? ranges : nullptr, n_tiles);
@@ -836,9 +850,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   };
   DupArgs a = {};
   const uint64_t mm = (uint64_t)m;
-  a.rec0 = reinterpret_cast<const float4*>(g->rec);
-  a.rec1 = a.rec0 + mm;
-  a.rec2 = a.rec0 + 2 * mm;
+  a.rec = reinterpret_cast<const float4*>(g->rec);
   a.tile_w = opt->tile_w;
   a.tile_h = opt->tile_h;
   a.alpha_min = opt->alpha_min;
@@ -897,14 +909,16 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   a.offs = L.offs;
   a.keys32 = tk[src];
   a.vals = vb[src];
-  a.hpart = sc_main.hpart;
+  const uint64_t ex_blocks = cdiv(C, EX_TILE);
+  a.hcopies = ex_blocks > HC_MIN_BLOCKS ? HC : 1;
+  a.hpart = a.hcopies > 1 ? sc_main.hpart : sc_main.ghist;
   a.hpasses = passes;
   a.hwidth = rs_width(tb);
   if (cap > 0) {
     k_expand32<<<(unsigned)cdiv(C, EX_TILE), 256, 0, s>>>(a);
     SGS_LAUNCH_CHECK();
-    st = radix_sort<uint32_t>(tk[src], vb[src], tk, vb, n_inst, 0, C, tb, sc_main, s, true, ranges,
-                              (uint32_t)T);
+    st = radix_sort<uint32_t>(tk[src], vb[src], tk, vb, n_inst, 0, C, tb, sc_main, s, true, ex_blocks,
+                              ranges, (uint32_t)T);
     if (st != SGS_OK) return st;
     if (keys) {
       k_make_keys64<<<(unsigned)cdiv(C, 256), 256, 0, s>>>(tk[0], vals, g->depth, mm, n_inst,

@@ -26,10 +26,7 @@
 namespace sgs {
 
 struct BlendArgs {
-  const float4* rec0;
-  const float4* rec1;
-  const float4* rec2;
-  const float4* rec3;
+  const float4* rec;       // [M][4] record slots
   const uint32_t* vals;
   const uint2* ranges;
   const sgs_camera* cams;
@@ -146,12 +143,13 @@ __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup&
     if (k < cnt) {
       uint32_t m = a.vals[idx0 + k];
       if (m >= a.m) m = 0;
-      const float4 q0 = a.rec0[m], q1 = a.rec1[m], q2 = a.rec2[m];
+      const float4* rp = a.rec + 4 * (uint64_t)m;
+      const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2];
       S.rid[k] = m;
       S.r0[k] = q0;
       S.r1[k] = q1;
       S.r2[k] = q2;
-      if (ENH) S.r3[k] = a.rec3[m];
+      if (ENH) S.r3[k] = rp[3];
       // the ellipse delta^T Q delta <= -2 log_thr outside which every pair
       // is skipped, with the margins of the tile extent
       const float det = q0.z * q1.x - q0.w * q0.w;
@@ -813,11 +811,7 @@ static BlendArgs make_args(const sgs_geom* g, int64_t m, const uint32_t* vals, i
     a.tile_order = sched->tile_order;
     a.work_counter = sched->work_counter;
   }
-  const float4* rec = reinterpret_cast<const float4*>(g->rec);
-  a.rec0 = rec;
-  a.rec1 = rec + m;
-  a.rec2 = rec + 2 * m;
-  a.rec3 = rec + 3 * m;
+  a.rec = reinterpret_cast<const float4*>(g->rec);
   a.vals = vals;
   a.n_vals = (uint32_t)cap;
   a.ranges = reinterpret_cast<const uint2*>(ranges);

@@ -231,12 +231,11 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
             const float d = a.enhanced ? P.rho : P.rho * P.o1;
             const float zc = has_skew ? skew_zcut(a.opt.alpha_min, d) : -1e30f;
             span_setup(P.mux, P.muy, P.a, P.b, P.c, thr, P.b2x, P.b2y, zc, sp);
-            const int64_t M = a.m;
-            float4* rec = reinterpret_cast<float4*>(a.rec);
-            rec[m] = make_float4(P.mux, P.muy, P.a, P.b);
-            rec[M + m] = make_float4(P.c, P.b2x, P.b2y, d);
-            rec[2 * M + m] = make_float4(P.rgb[0], P.rgb[1], P.rgb[2], thr);
-            if (a.enhanced) rec[3 * M + m] = make_float4(P.o1, P.o2, P.w2x, P.w2y);
+            float4* rec = reinterpret_cast<float4*>(a.rec) + 4 * m;
+            rec[0] = make_float4(P.mux, P.muy, P.a, P.b);
+            rec[1] = make_float4(P.c, P.b2x, P.b2y, d);
+            rec[2] = make_float4(P.rgb[0], P.rgb[1], P.rgb[2], thr);
+            if (a.enhanced) rec[3] = make_float4(P.o1, P.o2, P.w2x, P.w2y);
           }
         }
       }

@@ -187,7 +187,10 @@ sgs_status sgs_camera_layout(sgs_camera* cams, int32_t n_views, const sgs_option
   return SGS_OK;
 }
 
-int64_t sgs_geom_rec_floats(int64_t m, int32_t enhanced) { return m * 4 * (enhanced ? 4 : 3); }
+int64_t sgs_geom_rec_floats(int64_t m, int32_t enhanced) {
+  (void)enhanced;   // records: 16 floats each; gradient planes: at most 4 x 4
+  return m * 16;
+}
 
 int64_t sgs_geom_block_entries(int64_t n, int32_t n_views) {
   return (int64_t)n_views * ((n + 255) / 256) + 1;

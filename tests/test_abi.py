@@ -104,7 +104,7 @@ def test_camera_layout_tiles_and_pixels():
 
 def test_size_helpers():
     _abi, lib = _lib()
-    assert lib.sgs_geom_rec_floats(10, 0) == 120 and lib.sgs_geom_rec_floats(10, 1) == 160
+    assert lib.sgs_geom_rec_floats(10, 0) == 160 and lib.sgs_geom_rec_floats(10, 1) == 160   # 64 B per record
     assert lib.sgs_geom_block_entries(300, 2) == 2 * 2 + 1
     o = _abi.default_options()
     a = lib.sgs_bin_sort_scratch_bytes(1000, 5000, 64, C.byref(o))

@@ -64,7 +64,7 @@ def test_preprocess_matches_oracle_projection():
     sc, pose = S.tiny_config()
     fr = _render(sc, pose)
     m = sc.n
-    rec = _np(fr.bufs["rec"]).reshape(3, m, 4)
+    rec = _np(fr.bufs["rec"])[:16 * m].reshape(m, 4, 4).transpose(1, 0, 2)   # slot-major view
     tiles = _u32(fr.bufs["tiles"])[:m]
     ref = O.project_numpy(sc, pose)
     on = tiles > 0
