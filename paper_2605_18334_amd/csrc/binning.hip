@@ -40,6 +40,8 @@ constexpr int RS_T = 256;          // threads per block
 // from 0.3M to 50M keys: fewer, longer blocks keep look-back chains short
 // (4 doubled the time of a pass over 1M keys).
 constexpr int RS_IPT = 16;
+// sorts of at most this many blocks run their passes with 1024-thread blocks
+constexpr uint64_t RS_WIDE_MAX_BLOCKS = 4096;
 constexpr int RS_MAX_PASSES = 8;
 constexpr uint64_t ST_AGG = 1ull << 32;    // status: block's own digit count
 constexpr uint64_t ST_INC = 2ull << 32;    // status: inclusive prefix over blocks
@@ -133,51 +135,77 @@ __global__ void __launch_bounds__(256) k_hist_final(const uint32_t* __restrict__
 // ranges != nullptr (last pass over tile keys): every run of equal keys in
 // the block's output lowers ranges[2 key] to its first position and raises
 // ranges[2 key + 1] to its end (ranges start as [0xffffffff, 0)).
-template <typename K, int RS_IPT, int LB_W>
-__global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
-                                                  const uint32_t* __restrict__ vin,
-                                                  K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                  const uint32_t* n_dev, uint32_t n_host,
-                                                  uint32_t cap, int shift, int nbits,
-                                                  const uint32_t* __restrict__ ghist,
-                                                  uint64_t* status, uint32_t* counter,
-                                                  uint32_t* err, uint32_t* n_fold,
-                                                  uint32_t* ranges, uint32_t n_tiles) {
-  __shared__ uint32_t wc[4][256];
+// Exclusive scan over the 256 digits held by threads 0..255 (one value
+// each); every thread of the block must call it (it holds the barriers).
+__device__ __forceinline__ uint32_t digit_excl_scan(uint32_t x, uint32_t* ws4) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint32_t inc = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63 && w < 4) ws4[w] = inc;
+  __syncthreads();
+  uint32_t e = inc - x;
+  for (int k = 0; k < w && k < 4; ++k) e += ws4[k];
+  __syncthreads();
+  return e;
+}
+
+// One pass over RS_TILE keys per block of NT threads (NT / 64 waves, each
+// ranking RS_TILE / NT keys per lane): 256 threads for large sorts, 1024 for
+// small ones, where a block's latency (mostly the per-wave ranking rounds)
+// is the pass time.
+template <typename K, int NT, int LB_W>
+__global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
+                                                const uint32_t* __restrict__ vin,
+                                                K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                const uint32_t* n_dev, uint32_t n_host,
+                                                uint32_t cap, int shift, int nbits,
+                                                const uint32_t* __restrict__ ghist,
+                                                uint64_t* status, uint32_t* counter,
+                                                uint32_t* err, uint32_t* n_fold,
+                                                uint32_t* ranges, uint32_t n_tiles) {
+  constexpr int NW = NT / 64;
+  constexpr int RS_TILE = RS_T * RS_IPT;
+  constexpr int IPT = RS_TILE / NT;
+  __shared__ uint32_t wc[NW][256];
   __shared__ uint32_t lstart[256];
   __shared__ uint32_t lend[256];
   __shared__ uint32_t goff[256];
   __shared__ uint32_t ws[4];
   __shared__ uint32_t s_bid;
-  constexpr int RS_TILE = RS_T * RS_IPT;
   __shared__ K skey[RS_TILE];
   __shared__ uint32_t sval[RS_TILE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   if (t == 0) s_bid = atomicAdd(counter, 1u);
-  for (int k = t; k < 1024; k += RS_T) (&wc[0][0])[k] = 0;
+  for (int k = t; k < NW * 256; k += NT) (&wc[0][0])[k] = 0;
   __syncthreads();
   const uint32_t b = s_bid;
   const uint32_t n = count_of(n_dev, n_host, cap);
   const uint64_t bbase = (uint64_t)b * RS_TILE;
   if (bbase >= n) return;   // ids past the data: no later block waits on them
   const uint32_t mask = (1u << nbits) - 1u;
-  const uint64_t base = bbase + (uint64_t)w * (RS_IPT * 64) + lane;
+  const uint64_t base = bbase + (uint64_t)w * (IPT * 64) + lane;
   const uint64_t lt = lanemask_lt();
-  K key[RS_IPT];
-  uint32_t rank[RS_IPT];
+  K key[IPT];
+  uint32_t val[IPT];
+  uint32_t rank[IPT];
 #pragma unroll
-  for (int i = 0; i < RS_IPT; ++i) {
+  for (int i = 0; i < IPT; ++i) {
     const uint64_t idx = base + (uint64_t)i * 64;
-    key[i] = idx < n ? kin[idx] : (K)0;
+    const bool valid = idx < n;
+    key[i] = valid ? kin[idx] : (K)0;
+    val[i] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
   }
   // rank inside the wave: the lowest lane of each digit's peers reserves
-  // their slots with one LDS atomic (the atomics of the RS_IPT rounds are in
+  // their slots with one LDS atomic (the atomics of the IPT rounds are in
   // flight together), then every lane fetches its leader's base
   // (rank holds the rank among the peers in its low 8 bits and the
   // leader's lane above them until the bases are fetched)
-  uint32_t lead_base[RS_IPT];
+  uint32_t lead_base[IPT];
 #pragma unroll
-  for (int i = 0; i < RS_IPT; ++i) {
+  for (int i = 0; i < IPT; ++i) {
     const bool valid = base + (uint64_t)i * 64 < n;
     const uint32_t d = digit_of<K>(key[i], shift, mask);
     const uint64_t peers = match_digit(d, valid, nbits);
@@ -187,42 +215,47 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
     if (valid && r == 0) lead_base[i] = atomicAdd(&wc[w][d], (uint32_t)__popcll(peers));
   }
 #pragma unroll
-  for (int i = 0; i < RS_IPT; ++i) rank[i] = (rank[i] & 255u) + __shfl(lead_base[i], (int)(rank[i] >> 8));
+  for (int i = 0; i < IPT; ++i) rank[i] = (rank[i] & 255u) + __shfl(lead_base[i], (int)(rank[i] >> 8));
   __syncthreads();
-  const uint32_t c0 = wc[0][t], c1 = wc[1][t], c2 = wc[2][t], c3 = wc[3][t];
-  const uint32_t tot = c0 + c1 + c2 + c3;
-  const uint32_t ls = block_excl_scan256(tot, ws);
-  const uint32_t ds = block_excl_scan256(ghist[t], ws);   // start of digit t in the output
-  lstart[t] = ls;
-  lend[t] = ls + tot;
-  wc[0][t] = ls;
-  wc[1][t] = ls + c0;
-  wc[2][t] = ls + c0 + c1;
-  wc[3][t] = ls + c0 + c1 + c2;
-  // publish this block's count of digit t as early as possible (later
-  // blocks' look-backs wait for it); threads past the last digit idle
-  const bool has_digit = t < (1 << nbits);
+  // digit t (threads 0..255): block total, start in the block, per-wave starts
+  uint32_t tot = 0;
+  if (t < 256)
+    for (int v = 0; v < NW; ++v) tot += wc[v][t];
+  const uint32_t ls = digit_excl_scan(tot, ws);
+  const uint32_t ds = digit_excl_scan(t < 256 ? ghist[t] : 0u, ws);   // start of digit t in the output
+  const bool has_digit = t < (1 << nbits);   // (nbits <= 8: implies t < 256)
   uint64_t* st = status + (uint64_t)b * 256 + t;
-  if (has_digit)
-    __hip_atomic_store(st, (b == 0 ? ST_INC : ST_AGG) | (uint64_t)tot, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+  if (t < 256) {
+    lstart[t] = ls;
+    lend[t] = ls + tot;
+    uint32_t run = ls;
+    for (int v = 0; v < NW; ++v) {
+      const uint32_t c = wc[v][t];
+      wc[v][t] = run;
+      run += c;
+    }
+    // publish this block's count of digit t as early as possible (later
+    // blocks' look-backs wait for it); threads past the last digit idle
+    if (has_digit)
+      __hip_atomic_store(st, (b == 0 ? ST_INC : ST_AGG) | (uint64_t)tot, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
   __syncthreads();
-  // stage the block's keys in digit order (local ranks only), so that no key
-  // or value stays in registers during the look-back
+  // stage the block's keys in digit order (local ranks only)
 #pragma unroll
-  for (int i = 0; i < RS_IPT; ++i) {
+  for (int i = 0; i < IPT; ++i) {
     const uint64_t idx = base + (uint64_t)i * 64;
     if (idx < n) {
       const uint32_t d = digit_of<K>(key[i], shift, mask);
       const uint32_t pos = wc[w][d] + rank[i];
       skey[pos] = key[i];
-      sval[pos] = vin ? vin[idx] : (uint32_t)idx;
+      sval[pos] = val[i];
     }
   }
   // look back for the prefix over the blocks before this one
-  if (b == 0 || !has_digit) {
+  if (t < 256 && (b == 0 || !has_digit)) {
     goff[t] = ds;
-  } else {
+  } else if (t < 256) {
     // walk back LB_W predecessors at a time (their loads are in flight
     // together), summing published counts until an inclusive prefix
     uint32_t excl = 0, spins = 0;
@@ -267,7 +300,7 @@ __global__ void __launch_bounds__(RS_T) k_os_pass(const K* __restrict__ kin,
   }
   __syncthreads();
   const uint32_t cnt = (uint32_t)min((uint64_t)RS_TILE, (uint64_t)n - bbase);
-  for (uint32_t j = t; j < cnt; j += RS_T) {
+  for (uint32_t j = t; j < cnt; j += NT) {
     const K k = skey[j];
     const uint32_t d = digit_of<K>(k, shift, mask);
     const uint32_t g = goff[d] + (j - lstart[d]);
@@ -744,7 +777,13 @@ static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32
     const int dst = (passes - 1 - p) & 1;
     const K* ki = p == 0 ? kin : kb[dst ^ 1];
     const uint32_t* vi = p == 0 ? vin : vb[dst ^ 1];
-    k_os_pass<K, RS_IPT, LB_W><<<(unsigned)blocks, RS_T, 0, s>>>(
+    if (blocks <= RS_WIDE_MAX_BLOCKS)
+      k_os_pass<K, 1024, LB_W><<<(unsigned)blocks, 1024, 0, s>>>(
+        ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
+        sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
+        p == passes - 1 ? ranges : nullptr, n_tiles);
+    else
+      k_os_pass<K, RS_T, LB_W><<<(unsigned)blocks, RS_T, 0, s>>>(
         ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
         sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
         p == passes - 1 ? ranges : nullptr, n_tiles);
