@@ -40,7 +40,9 @@ constexpr int RS_T = 256;          // threads per block
 // from 0.3M to 50M keys: fewer, longer blocks keep look-back chains short
 // (4 doubled the time of a pass over 1M keys).
 constexpr int RS_IPT = 16;
-// sorts of at most this many blocks run their passes with 1024-thread blocks
+// pass blocks: 1024 threads for sorts of at most this many blocks (their
+// time is one block's latency), 512 for larger ones (measured: 256 threads
+// ran 5% slower at 52M keys, 1024 slower still)
 constexpr uint64_t RS_WIDE_MAX_BLOCKS = 4096;
 constexpr int RS_MAX_PASSES = 8;
 constexpr uint64_t ST_AGG = 1ull << 32;    // status: block's own digit count
@@ -153,7 +155,7 @@ __device__ __forceinline__ uint32_t digit_excl_scan(uint32_t x, uint32_t* ws4) {
 }
 
 // One pass over RS_TILE keys per block of NT threads (NT / 64 waves, each
-// ranking RS_TILE / NT keys per lane): 256 threads for large sorts, 1024 for
+// ranking RS_TILE / NT keys per lane): 512 threads for large sorts, 1024 for
 // small ones, where a block's latency (mostly the per-wave ranking rounds)
 // is the pass time.
 template <typename K, int NT, int LB_W>
@@ -188,15 +190,16 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
   const uint32_t mask = (1u << nbits) - 1u;
   const uint64_t base = bbase + (uint64_t)w * (IPT * 64) + lane;
   const uint64_t lt = lanemask_lt();
+  // this lane's keys are base + 64 i for i < nv (the valid ones)
+  const int nv = base < n ? (int)min((uint64_t)IPT, (n - base + 63) / 64) : 0;
   K key[IPT];
   uint32_t val[IPT];
   uint32_t rank[IPT];
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const uint64_t idx = base + (uint64_t)i * 64;
-    const bool valid = idx < n;
-    key[i] = valid ? kin[idx] : (K)0;
-    val[i] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
+    key[i] = i < nv ? kin[idx] : (K)0;
+    val[i] = i < nv ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
   }
   // rank inside the wave: the lowest lane of each digit's peers reserves
   // their slots with one LDS atomic (the atomics of the IPT rounds are in
@@ -206,7 +209,7 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
   uint32_t lead_base[IPT];
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
-    const bool valid = base + (uint64_t)i * 64 < n;
+    const bool valid = i < nv;
     const uint32_t d = digit_of<K>(key[i], shift, mask);
     const uint64_t peers = match_digit(d, valid, nbits);
     const uint32_t r = (uint32_t)__popcll(peers & lt);
@@ -244,8 +247,7 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
   // stage the block's keys in digit order (local ranks only)
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
-    const uint64_t idx = base + (uint64_t)i * 64;
-    if (idx < n) {
+    if (i < nv) {
       const uint32_t d = digit_of<K>(key[i], shift, mask);
       const uint32_t pos = wc[w][d] + rank[i];
       skey[pos] = key[i];
@@ -336,6 +338,7 @@ struct DupArgs {
   uint32_t* n_inst;
   const uint32_t* order; // mode 1: records in depth order
   const uint32_t* offs;  // mode 1: exclusive instance offset of order[j]
+  const uint32_t* bstart;  // mode 1: record owning the first instance of each expansion block
   uint32_t* hpart;       // mode 1: partial digit histograms [HC][hpasses][256] of the tile keys
   int32_t hpasses;       //         digits of hwidth bits, hcopies copies
   int32_t hwidth;
@@ -381,12 +384,17 @@ __global__ void __launch_bounds__(256) k_duplicate64(DupArgs a) {
   }
 }
 
+// Instances per expansion block, and the most records one can span.
+constexpr int EX_TILE = 2048;
+constexpr int EX_W = EX_TILE + 1;
+
 // Mode 1, step 2: exclusive instance offset of every record in depth order,
 // one pass: each block of SO_TILE entries scans its tile counts, publishes
 // its total and looks back over the published totals of the blocks before
 // it, 64 at a time (one per lane of wave 0).  The block that takes the last
 // id writes the instance count (N_INVALID after a failed look-back, here or
-// in the depth sort; saturated at 2^32 - 2).
+// in the depth sort; saturated at 2^32 - 2).  Each record also marks the
+// expansion blocks whose first instance it owns: bstart[b] = its position.
 constexpr int SO_IPT = 8;
 constexpr int SO_TILE = 256 * SO_IPT;
 
@@ -395,7 +403,8 @@ __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restri
                                                         int64_t m, uint32_t* __restrict__ offs,
                                                         uint32_t* __restrict__ n_inst,
                                                         uint64_t* status, uint32_t* counter,
-                                                        uint32_t* err) {
+                                                        uint32_t* err, uint32_t* __restrict__ bstart,
+                                                        uint32_t n_bstart) {
   constexpr uint64_t VMASK = (1ull << 62) - 1;   // 62-bit running totals, 2 flag bits
   constexpr uint64_t F_AGG = 1ull << 62, F_INC = 2ull << 62;
   __shared__ uint32_t ws[4];
@@ -466,7 +475,11 @@ __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restri
 #pragma unroll
   for (int k = 0; k < SO_IPT; ++k) {
     const int64_t j = j0 + k;
-    if (j < m) offs[j] = (uint32_t)run;
+    if (j < m) {
+      offs[j] = (uint32_t)run;
+      for (uint64_t bb = (run + EX_TILE - 1) / EX_TILE; bb * EX_TILE < run + c[k] && bb < n_bstart; ++bb)
+        bstart[bb] = (uint32_t)j;
+    }
     run += c[k];
   }
   if (b == gridDim.x - 1 && t == 0) {
@@ -478,8 +491,8 @@ __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restri
 // Mode 1, step 3: load-balanced expansion.  Block b writes instances
 // [o0, o1) = [b*EX_TILE, (b+1)*EX_TILE).  Records in depth order with at least
 // one tile come first (culled ones sort last), so the records that own this
-// range are at most EX_TILE + 1 consecutive entries starting at the last
-// record j0 whose offset is <= o0.  The block enumerates (record, tile row)
+// range are at most EX_TILE + 1 consecutive entries starting at the record
+// j0 that owns instance o0 (bstart[b], from the offsets kernel).  The block enumerates (record, tile row)
 // items of those records in order, 256 at a time: each thread computes one
 // row's span once, a block scan turns the row counts into instance offsets
 // (a running sum from offs[j0]: records' instances are their rows' in order),
@@ -487,8 +500,6 @@ __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restri
 // The digit histograms of the tile-key sort are counted here as well: a
 // row's instances have consecutive tile keys, so the low digit is counted
 // per instance and every higher digit once per run of equal high bits.
-constexpr int EX_TILE = 2048;
-constexpr int EX_W = EX_TILE + 1;
 
 // Exclusive scan of one value per thread; *tot receives the block total.
 __device__ __forceinline__ uint32_t block_scan256_total(uint32_t x, uint32_t* ws4, uint32_t* tot) {
@@ -512,18 +523,9 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
   const int t = threadIdx.x;
   const uint32_t dmask = (1u << a.hwidth) - 1u;
   for (int k = t; k < 4 * 256; k += 256) (&hist[0][0])[k] = 0u;
-  // last j with offs[j] <= o0 (offs is non-decreasing, offs[0] = 0): a
-  // 256-way search, one sample per thread and round (about log_256 M rounds)
-  uint64_t jlo = 0, jhi = (uint64_t)a.m;   // offs[jlo] <= o0, answer in [jlo, jhi)
-  while (jhi - jlo > 1) {
-    const uint64_t step = (jhi - jlo + 255) / 256;
-    const uint64_t idx = jlo + (uint64_t)t * step;
-    const int below = __syncthreads_count(idx < jhi && a.offs[idx] <= o0);   // >= 1 (t = 0)
-    const uint64_t nlo = jlo + (uint64_t)(below - 1) * step;
-    jhi = min(jhi, nlo + step);
-    jlo = nlo;
-  }
   if (t == 0) {
+    // the record that owns instance o0 (marked by the offsets kernel)
+    const uint64_t jlo = min((uint64_t)a.bstart[blockIdx.x], (uint64_t)a.m - 1);
     s_j0 = (uint32_t)jlo;
     s_w = (uint32_t)min((uint64_t)EX_W, (uint64_t)a.m - jlo);
   }
@@ -783,7 +785,7 @@ static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32
         sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
         p == passes - 1 ? ranges : nullptr, n_tiles);
     else
-      k_os_pass<K, RS_T, LB_W><<<(unsigned)blocks, RS_T, 0, s>>>(
+      k_os_pass<K, 512, LB_W><<<(unsigned)blocks, 512, 0, s>>>(
         ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
         sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
         p == passes - 1 ? ranges : nullptr, n_tiles);
@@ -812,6 +814,8 @@ struct BinLayout {
   uint32_t* dk[2];                // mode 1: depth keys
   uint32_t* dv[2];                // mode 1: record order
   uint32_t* offs;                 // mode 1: per-record instance offsets
+  uint32_t* bstart;               // mode 1: first record of each expansion block
+  uint64_t n_bstart;
   uint32_t* tk[2];                // mode 1: tile keys
   size_t bytes;
 };
@@ -839,6 +843,8 @@ static BinLayout bin_layout(uintptr_t base, int64_t m, int64_t cap, int64_t tota
       L.tk[k] = reinterpret_cast<uint32_t*>(take(C * 4));
     }
     L.offs = reinterpret_cast<uint32_t*>(take(M * 4));
+    L.n_bstart = std::max<uint64_t>(cdiv(C, EX_TILE), 1);
+    L.bstart = reinterpret_cast<uint32_t*>(take(L.n_bstart * 4));
     L.valt = reinterpret_cast<uint32_t*>(take(C * 4));
   }
   L.bytes = (size_t)(p - p0) + 256;
@@ -874,6 +880,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   if (mode == 1 && m > 0) {
     zero(L.rs_depth, rs_words((uint64_t)m, 4));
     zero(L.so_status, L.so_words);
+    zero(L.bstart, L.n_bstart);
   }
   uint64_t zmax = 0;
   for (int k = 0; k < nz; ++k) zmax = std::max(zmax, z.n[k]);
@@ -938,7 +945,8 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   if (st != SGS_OK) return st;
   const uint32_t* order = dv[0];
   k_sorted_offsets<<<(unsigned)cdiv(mm, SO_TILE), 256, 0, s>>>(
-      order, g->tiles, m, L.offs, n_inst, reinterpret_cast<uint64_t*>(L.so_status + 64), L.so_status, err);
+      order, g->tiles, m, L.offs, n_inst, reinterpret_cast<uint64_t*>(L.so_status + 64), L.so_status, err,
+      L.bstart, (uint32_t)L.n_bstart);
   SGS_LAUNCH_CHECK();
   const int passes = L.main_passes;
   const int src = passes & 1;
@@ -946,6 +954,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   uint32_t* vb[2] = {vals, L.valt};
   a.order = order;
   a.offs = L.offs;
+  a.bstart = L.bstart;
   a.keys32 = tk[src];
   a.vals = vb[src];
   const uint64_t ex_blocks = cdiv(C, EX_TILE);
