@@ -16,9 +16,9 @@
 // C += c alpha T.  Backward (Alg. 2): each pixel walks its list from its last
 // contributor to the front, rebuilding T_k = T_{k+1} / (1 - alpha_k) from the
 // final transmittance (nothing per pair is stored), with the colour behind k
-// kept as a running sum.  Per-pair partial derivatives are summed over the
-// wave with DPP, over the waves in LDS, and written with one set of global
-// atomics per (record, tile).
+// kept as a running sum.  Per-pair partial derivatives are summed over each
+// 16-lane row with DPP, over rows and waves with LDS atomics, and written
+// with one set of global atomics per (record, tile).
 #include <algorithm>
 
 #include "sgs_dev.h"
@@ -96,32 +96,33 @@ struct Stage {
   uint16_t n[NW];
 };
 
-// Whether the ellipse {delta : delta^T Q delta <= R2}, Q = [[a, b], [b, c]]
-// positive definite, meets the box [x0, x1] x [y0, y1] (delta coordinates):
-// the minimum of the quadratic form over the box is 0 when the box holds the
-// centre, else it lies on an edge, where it is a clamped 1D minimum.  The
-// allowance 1e-5 * (|terms|) covers float rounding of the per-pixel test.
-__device__ __forceinline__ float edge_min_x(float a, float b, float c, float ic, float x, float y0,
-                                            float y1) {
-  const float y = fminf(fmaxf(-b * x * ic, y0), y1);
-  const float q = fmaf(a * x, x, fmaf(c * y, y, 2.0f * b * x * y));
-  const float mag = fmaf(a * x, x, fmaf(c * y, y, 2.0f * fabsf(b * x * y)));
-  return q - 1e-5f * mag;
-}
-__device__ __forceinline__ float edge_min_y(float a, float b, float c, float ia, float y, float x0,
-                                            float x1) {
-  const float x = fminf(fmaxf(-b * y * ia, x0), x1);
-  const float q = fmaf(a * x, x, fmaf(c * y, y, 2.0f * b * x * y));
-  const float mag = fmaf(a * x, x, fmaf(c * y, y, 2.0f * fabsf(b * x * y)));
-  return q - 1e-5f * mag;
-}
-__device__ __forceinline__ bool ellipse_meets_box(float a, float b, float c, float R2, float x0,
-                                                  float x1, float y0, float y1) {
-  if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
-  const float ia = __builtin_amdgcn_rcpf(a), ic = __builtin_amdgcn_rcpf(c);
-  const float m = fminf(fminf(edge_min_x(a, b, c, ic, x0, y0, y1), edge_min_x(a, b, c, ic, x1, y0, y1)),
-                        fminf(edge_min_y(a, b, c, ia, y0, x0, x1), edge_min_y(a, b, c, ia, y1, x0, x1)));
-  return m <= R2;
+// x-range [xl, xr] (delta coordinates) of the ellipse {delta : delta^T Q
+// delta <= R2}, Q = [[a, b], [b, c]] positive definite, over the band of
+// rows u in [u0, u1], widened by the margins of the tile extent; false if
+// the band misses the ellipse.  On a row u the ellipse spans
+// x = (-b u +- sqrt(a R2 - det u^2)) / a; over the band the extremes are at
+// the band's ends or where the ellipse's own x extremes lie (u = +-yx).
+// Approximate sqrt and reciprocal: their error is far inside the margins.
+__device__ __forceinline__ bool band_xrange(float a, float b, float c, float det, float R2,
+                                            float u0, float u1, float& xl, float& xr) {
+  const float ia = __builtin_amdgcn_rcpf(a);
+  const float idet = __builtin_amdgcn_rcpf(det);
+  const float ey = __builtin_amdgcn_sqrtf(R2 * a * idet);
+  u0 = fmaxf(u0, -ey);
+  u1 = fminf(u1, ey);
+  if (!(u0 <= u1)) return false;
+  const float aR2 = a * R2;
+  const float r0 = __builtin_amdgcn_sqrtf(fmaxf(aR2 - det * u0 * u0, 0.0f));
+  const float r1 = __builtin_amdgcn_sqrtf(fmaxf(aR2 - det * u1 * u1, 0.0f));
+  xr = fmaxf((-b * u0 + r0) * ia, (-b * u1 + r1) * ia);
+  xl = fminf((-b * u0 - r0) * ia, (-b * u1 - r1) * ia);
+  const float ex = __builtin_amdgcn_sqrtf(R2 * c * idet);          // the ellipse's largest x
+  const float yx = -b * ex * __builtin_amdgcn_rcpf(c);             // ... reached at dy = yx
+  if (yx >= u0 && yx <= u1) xr = ex;
+  if (-yx >= u0 && -yx <= u1) xl = -ex;
+  xr = xr * 1.001f + 0.01f;
+  xl = xl * 1.001f - 0.01f;
+  return true;
 }
 
 // Loads records [idx0, idx0 + cnt) of the tile list into the stage and builds
@@ -162,12 +163,22 @@ __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup&
         const bool skew = (q1.y != 0.0f) || (q1.z != 0.0f);
         const float zc = skew ? skew_zcut(a.alpha_min, q1.w) : -1e30f;
         const float need = zc * 1.41421356f;
+        // the ellipse's x-range over each row of wave blocks
+        constexpr int GR = St::NW / GW;
+        float bxl[GR], bxr[GR];
+        bool bok[GR];
+#pragma unroll
+        for (int r = 0; r < GR; ++r) {
+          const float ly = (float)(ts.gy + r * BS) + 0.5f;
+          bok[r] = band_xrange(q0.z, q0.w, q1.x, det, R2, ly - q0.y - 0.01f, ly + EXT - q0.y + 0.01f,
+                               bxl[r], bxr[r]);
+        }
 #pragma unroll
         for (int w = 0; w < St::NW; ++w) {
           const float lx = (float)(ts.gx + (w % GW) * BS) + 0.5f;
           const float ly = (float)(ts.gy + (w / GW) * BS) + 0.5f;
-          bool hit = ellipse_meets_box(q0.z, q0.w, q1.x, R2, lx - q0.x - 0.01f, lx + EXT - q0.x + 0.01f,
-                                       ly - q0.y - 0.01f, ly + EXT - q0.y + 0.01f);
+          const int r = w / GW;
+          bool hit = bok[r] && bxr[r] >= lx - q0.x && bxl[r] <= lx + EXT - q0.x;
           if (hit && zc > -1e29f) {
             const float top = skew_box_max(q1.y, q1.z, lx + HALF, ly + HALF, q0.x, q0.y, HALF, HALF);
             hit = top + 1e-3f * (1.0f + fabsf(top) + fabsf(need)) >= need;
@@ -523,13 +534,14 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
           const float alpha = fminf(a.alpha_max, at);
           if (alpha >= a.alpha_min) {
             hit = true;
-            T = T / (1.0f - alpha);           // transmittance in front of this pair
+            const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+            T = T * inv;                      // transmittance in front of this pair
             const float wgt = alpha * T;
             gv[8] = wgt * g0;
             gv[9] = wgt * g1;
             gv[10] = wgt * g2;
             float dLda = ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) * T;
-            dLda -= Tfinal / (1.0f - alpha) * bgdot;
+            dLda -= Tfinal * inv * bgdot;
             if (at <= a.alpha_max) {
               const float dd = r1.w * o;              // d, times o(delta) with enhanced opacity
               const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
@@ -561,10 +573,12 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
         }
       }
       if (__ballot(hit)) {
+        // sums over each 16-lane row (DPP), then one LDS atomic per row: the
+        // VALU is this kernel's bound, the LDS pipe has room
 #pragma unroll
         for (int q = 0; q < NG; ++q) {
-          const float s = wave_sum_to_lane63(gv[q]);
-          if (lane == 63 && s != 0.0f) atomicAdd(&sg[q][j], s);
+          const float s = row_sum16(gv[q]);
+          if ((lane & 15) == 0 && s != 0.0f) atomicAdd(&sg[q][j], s);
         }
       }
     }
@@ -660,7 +674,7 @@ __device__ __forceinline__ void bwd_quad(const BlendArgs& a, int tile, int quart
 #define SGS_QUAD_BACK(Q)                                                     \
       if (quad_bcast<Q>(hi)) {                                               \
         const float al = quad_bcast<Q>(alpha);                               \
-        T = T / (1.0f - al);                                                 \
+        T = T * __builtin_amdgcn_rcpf(1.0f - al);                            \
         if (sub == Q) {                                                      \
           Tm = T;                                                            \
           Sm0 = S0;                                                          \
@@ -685,7 +699,7 @@ __device__ __forceinline__ void bwd_quad(const BlendArgs& a, int tile, int quart
         gv[9] = wgt * g1;
         gv[10] = wgt * g2;
         float dLda = ((r2.x - Sm0) * g0 + (r2.y - Sm1) * g1 + (r2.z - Sm2) * g2) * Tm;
-        dLda -= Tfinal / (1.0f - alpha) * bgdot;
+        dLda -= Tfinal * __builtin_amdgcn_rcpf(1.0f - alpha) * bgdot;
         if (at <= a.alpha_max) {
           const float dd = r1.w * o;
           const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;

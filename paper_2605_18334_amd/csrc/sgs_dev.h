@@ -202,22 +202,21 @@ __device__ __forceinline__ void span_row(const Span& s, int row, int tw, int th,
 }
 
 // ---------------------------------------------------------------- wave ops
-// Sum over the 64 lanes of a wave with DPP; the total lands in lane 63.
-// All 64 lanes must be active.
+// v of the lane that the DPP control CTRL selects (0 where none).
 template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
 __device__ __forceinline__ float dpp_src(float v) {
   return __int_as_float(
       __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, false));
 }
 
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+// Sum over each 16-lane row of the wave; every lane of a row gets its row's
+// sum.  All 64 lanes must be active.
+__device__ __forceinline__ float row_sum16(float v) {
   v += dpp_src<0xB1>(v);          // quad_perm [1,0,3,2]
   v += dpp_src<0x4E>(v);          // quad_perm [2,3,0,1]
   v += dpp_src<0x141>(v);         // row_half_mirror
-  v += dpp_src<0x140>(v);         // row_mirror: every lane holds its row sum
-  v += dpp_src<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
-  v += dpp_src<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
-  return v;                       // lane 63: sum of all 64 lanes
+  v += dpp_src<0x140>(v);         // row_mirror
+  return v;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
