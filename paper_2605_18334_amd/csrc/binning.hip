@@ -40,6 +40,11 @@ constexpr int RS_T = 256;          // threads per block
 // from 0.3M to 50M keys: fewer, longer blocks keep look-back chains short
 // (4 doubled the time of a pass over 1M keys).
 constexpr int RS_IPT = 16;
+// Instances per expansion block (a pass block covers RS_TILE / EX_TILE of
+// them), and the most records one can span.
+constexpr int EX_TILE = 2048;
+constexpr int EX_W = EX_TILE + 1;
+constexpr int EC = 64;             // expansion blocks per chunk of the count scan
 // pass blocks: 1024 threads for sorts of at most this many blocks (their
 // time is one block's latency), 512 for larger ones (measured: 256 threads
 // ran 5% slower at 52M keys, 1024 slower still)
@@ -122,6 +127,56 @@ __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, co
     if (h[p][t]) atomicAdd(&dst[p * 256 + t], h[p][t]);
 }
 
+// Per-block digit counts cnt[e][256] of the expansion blocks, scanned in two
+// levels: k_chunk_scan turns each chunk of EC consecutive blocks into
+// exclusive prefixes within the chunk (one workgroup per chunk, one thread
+// per digit) and stores the chunk totals; k_chunk_totals scans those.  The
+// keys of digit d before block e number cnt[e][d] + tot[e / EC][d].
+__global__ void __launch_bounds__(256) k_chunk_scan(uint32_t* __restrict__ cnt, uint32_t n,
+                                                    uint32_t* __restrict__ tot) {
+  const uint32_t t = threadIdx.x, e0 = blockIdx.x * EC;
+  uint32_t x[EC];
+#pragma unroll
+  for (int i = 0; i < EC; ++i) x[i] = e0 + i < n ? cnt[(uint64_t)(e0 + i) * 256 + t] : 0u;
+  uint32_t run = 0;
+#pragma unroll
+  for (int i = 0; i < EC; ++i) {
+    if (e0 + i < n) cnt[(uint64_t)(e0 + i) * 256 + t] = run;
+    run += x[i];
+  }
+  tot[(uint64_t)blockIdx.x * 256 + t] = run;
+}
+
+// One workgroup per digit; thread t takes CT consecutive chunks of each
+// group of 256 * CT.
+constexpr int CT = 8;
+
+__global__ void __launch_bounds__(256) k_chunk_totals(uint32_t* __restrict__ tot, uint32_t nch) {
+  __shared__ uint32_t ws[4];
+  const uint32_t d = blockIdx.x, t = threadIdx.x;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nch; base += 256 * CT) {
+    const uint32_t c0 = base + t * CT;
+    uint32_t x[CT], sum = 0;
+#pragma unroll
+    for (int i = 0; i < CT; ++i) {
+      x[i] = c0 + i < nch ? tot[(uint64_t)(c0 + i) * 256 + d] : 0u;
+      sum += x[i];
+    }
+    uint32_t run = carry + block_excl_scan256(sum, ws);
+#pragma unroll
+    for (int i = 0; i < CT; ++i) {
+      if (c0 + i < nch) tot[(uint64_t)(c0 + i) * 256 + d] = run;
+      run += x[i];
+    }
+    // the last thread's running value is the carry into the next group
+    if (t == 255) ws[0] = run;
+    __syncthreads();
+    carry = ws[0];
+    __syncthreads();
+  }
+}
+
 // Sums the HC partial copies of the digit histograms: ghist[p][d].
 __global__ void __launch_bounds__(256) k_hist_final(const uint32_t* __restrict__ hpart, int passes,
                                                     uint32_t* __restrict__ ghist) {
@@ -137,6 +192,9 @@ __global__ void __launch_bounds__(256) k_hist_final(const uint32_t* __restrict__
 // ranges != nullptr (last pass over tile keys): every run of equal keys in
 // the block's output lowers ranges[2 key] to its first position and raises
 // ranges[2 key + 1] to its end (ranges start as [0xffffffff, 0)).
+// pre != nullptr: no look-back; the keys of digit d before this block are
+// counted by the scanned per-block counts of the expansion blocks that wrote
+// the input (k_chunk_scan; the first pass of sort mode 1).
 // Exclusive scan over the 256 digits held by threads 0..255 (one value
 // each); every thread of the block must call it (it holds the barriers).
 __device__ __forceinline__ uint32_t digit_excl_scan(uint32_t x, uint32_t* ws4) {
@@ -167,7 +225,9 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
                                                 const uint32_t* __restrict__ ghist,
                                                 uint64_t* status, uint32_t* counter,
                                                 uint32_t* err, uint32_t* n_fold,
-                                                uint32_t* ranges, uint32_t n_tiles) {
+                                                uint32_t* ranges, uint32_t n_tiles,
+                                                const uint32_t* __restrict__ pre,
+                                                const uint32_t* __restrict__ pre_tot) {
   constexpr int NW = NT / 64;
   constexpr int RS_TILE = RS_T * RS_IPT;
   constexpr int IPT = RS_TILE / NT;
@@ -255,7 +315,11 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
     }
   }
   // look back for the prefix over the blocks before this one
-  if (t < 256 && (b == 0 || !has_digit)) {
+  if (t < 256 && pre) {
+    // offsets of this block's keys within each digit were scanned beforehand
+    const uint64_t e = (uint64_t)b * (RS_TILE / EX_TILE);
+    goff[t] = ds + pre[e * 256 + t] + pre_tot[(e / EC) * 256 + t];
+  } else if (t < 256 && (b == 0 || !has_digit)) {
     goff[t] = ds;
   } else if (t < 256) {
     // walk back LB_W predecessors at a time (their loads are in flight
@@ -340,6 +404,7 @@ struct DupArgs {
   const uint32_t* offs;  // mode 1: exclusive instance offset of order[j]
   const uint32_t* bstart;  // mode 1: record owning the first instance of each expansion block
   uint32_t* hpart;       // mode 1: partial digit histograms [HC][hpasses][256] of the tile keys
+  uint32_t* cnt0;        // mode 1: per-block counts of the first digit [gridDim][256]
   int32_t hpasses;       //         digits of hwidth bits, hcopies copies
   int32_t hwidth;
   int32_t hcopies;
@@ -384,9 +449,6 @@ __global__ void __launch_bounds__(256) k_duplicate64(DupArgs a) {
   }
 }
 
-// Instances per expansion block, and the most records one can span.
-constexpr int EX_TILE = 2048;
-constexpr int EX_W = EX_TILE + 1;
 
 // Mode 1, step 2: exclusive instance offset of every record in depth order,
 // one pass: each block of SO_TILE entries scans its tile counts, publishes
@@ -518,7 +580,10 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
   const uint32_t total = *a.n_inst;
   const uint32_t n = total < a.cap ? total : a.cap;
   const uint64_t o0 = (uint64_t)blockIdx.x * EX_TILE;
-  if (o0 >= n) return;
+  if (o0 >= n) {   // no instances: zero counts for the first pass's column scan
+    if (a.cnt0) a.cnt0[(uint64_t)blockIdx.x * 256 + threadIdx.x] = 0u;
+    return;
+  }
   const uint64_t o1 = min(o0 + (uint64_t)EX_TILE, (uint64_t)n);
   const int t = threadIdx.x;
   const uint32_t dmask = (1u << a.hwidth) - 1u;
@@ -607,6 +672,7 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
     run += s_tot;
     __syncthreads();
   }
+  if (a.cnt0) a.cnt0[(uint64_t)blockIdx.x * 256 + t] = hist[0][t];
   uint32_t* hdst = a.hpart + (size_t)(blockIdx.x % (unsigned)a.hcopies) * a.hpasses * 256;
   for (int p = 0; p < a.hpasses; ++p)
     if (hist[p][t]) atomicAdd(&hdst[p * 256 + t], hist[p][t]);
@@ -748,7 +814,8 @@ static RsScratch rs_carve(uint32_t* p, int passes, uint32_t* err, uint32_t* n_fo
 // Sorts by bits [0, bits), one kernel per pass of rs_width(bits) bits.  Pass 0 reads
 // (kin, vin) (vin == nullptr: values are the positions); the result lands in
 // (kb[0], vb[0]).  kin may be kb[passes & 1] (sorting in place) or another
-// buffer.  The scratch must be zero, except that with hist_done the digit
+// buffer.  pre0: precomputed per-block digit offsets for the first pass (see
+// k_os_pass).  The scratch must be zero, except that with hist_done the digit
 // histograms already hold the counts of the keys: in the partial copies when
 // the hist_blocks_done blocks that counted them exceed HC_MIN_BLOCKS, else in
 // the final histograms.  With ranges, the last
@@ -758,7 +825,8 @@ static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32
                              const uint32_t* n_dev, uint32_t n_host, uint64_t cap, int bits,
                              RsScratch sc, hipStream_t s, bool hist_done = false,
                              uint64_t hist_blocks_done = 0, uint32_t* ranges = nullptr,
-                             uint32_t n_tiles = 0) {
+                             uint32_t n_tiles = 0, const uint32_t* pre0 = nullptr,
+                             const uint32_t* pre0_tot = nullptr) {
   const uint64_t blocks = rs_blocks(cap);
   const int passes = rs_passes(bits);
   const int width = rs_width(bits);
@@ -783,12 +851,12 @@ static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32
       k_os_pass<K, 1024, LB_W><<<(unsigned)blocks, 1024, 0, s>>>(
         ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
         sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
-        p == passes - 1 ? ranges : nullptr, n_tiles);
+        p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot);
     else
       k_os_pass<K, 512, LB_W><<<(unsigned)blocks, 512, 0, s>>>(
         ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
         sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
-        p == passes - 1 ? ranges : nullptr, n_tiles);
+        p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot);
     SGS_LAUNCH_CHECK();
   }
   return SGS_OK;
@@ -815,7 +883,9 @@ struct BinLayout {
   uint32_t* dv[2];                // mode 1: record order
   uint32_t* offs;                 // mode 1: per-record instance offsets
   uint32_t* bstart;               // mode 1: first record of each expansion block
-  uint64_t n_bstart;
+  uint64_t n_bstart;              //         (= number of expansion blocks)
+  uint32_t* cnt0;                 // mode 1: [expansion blocks][256] first-digit counts
+  uint32_t* ctot;                 // mode 1: [chunks][256] their chunk totals
   uint32_t* tk[2];                // mode 1: tile keys
   size_t bytes;
 };
@@ -845,6 +915,10 @@ static BinLayout bin_layout(uintptr_t base, int64_t m, int64_t cap, int64_t tota
     L.offs = reinterpret_cast<uint32_t*>(take(M * 4));
     L.n_bstart = std::max<uint64_t>(cdiv(C, EX_TILE), 1);
     L.bstart = reinterpret_cast<uint32_t*>(take(L.n_bstart * 4));
+    if (cdiv(C, (uint64_t)RS_T * RS_IPT) > RS_WIDE_MAX_BLOCKS) {
+      L.cnt0 = reinterpret_cast<uint32_t*>(take(L.n_bstart * 256 * 4));
+      L.ctot = reinterpret_cast<uint32_t*>(take(cdiv(L.n_bstart, EC) * 256 * 4));
+    }
     L.valt = reinterpret_cast<uint32_t*>(take(C * 4));
   }
   L.bytes = (size_t)(p - p0) + 256;
@@ -960,13 +1034,24 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   const uint64_t ex_blocks = cdiv(C, EX_TILE);
   a.hcopies = ex_blocks > HC_MIN_BLOCKS ? HC : 1;
   a.hpart = a.hcopies > 1 ? sc_main.hpart : sc_main.ghist;
+  // large sorts scan the expansion blocks' first-digit counts instead of
+  // looking back over the blocks of the first pass
+  const bool scan0 = cdiv(C, (uint64_t)RS_T * RS_IPT) > RS_WIDE_MAX_BLOCKS;
+  a.cnt0 = scan0 ? L.cnt0 : nullptr;
   a.hpasses = passes;
   a.hwidth = rs_width(tb);
   if (cap > 0) {
     k_expand32<<<(unsigned)cdiv(C, EX_TILE), 256, 0, s>>>(a);
     SGS_LAUNCH_CHECK();
+    if (scan0) {
+      const uint32_t nch = (uint32_t)cdiv(ex_blocks, EC);
+      k_chunk_scan<<<nch, 256, 0, s>>>(L.cnt0, (uint32_t)ex_blocks, L.ctot);
+      SGS_LAUNCH_CHECK();
+      k_chunk_totals<<<256, 256, 0, s>>>(L.ctot, nch);
+      SGS_LAUNCH_CHECK();
+    }
     st = radix_sort<uint32_t>(tk[src], vb[src], tk, vb, n_inst, 0, C, tb, sc_main, s, true, ex_blocks,
-                              ranges, (uint32_t)T);
+                              ranges, (uint32_t)T, a.cnt0, scan0 ? L.ctot : nullptr);
     if (st != SGS_OK) return st;
     if (keys) {
       k_make_keys64<<<(unsigned)cdiv(C, 256), 256, 0, s>>>(tk[0], vals, g->depth, mm, n_inst,
