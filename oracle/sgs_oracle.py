@@ -310,6 +310,21 @@ def alpha_tilde(pc: torch.Tensor, pr: Projected, idx: torch.Tensor, opt: Options
     return pr.rho[idx] * o * g * skew
 
 
+def power_terms(pc: torch.Tensor, pr: Projected, idx: torch.Tensor) -> torch.Tensor:
+    """Magnitude of the terms of the exponent of G' at pixel centres pc:
+    (|a| dx^2 + 2 |b dx dy| + |c| dy^2) / 2, [P, len(idx)].  A float32
+    pipeline stores the 2D mean and conic rounded to float32, which moves
+    the exponent by up to a few float32 ulps of this magnitude: for thin,
+    long ellipses far from their centre the terms are 1e4 times the
+    exponent itself.  Test infrastructure: it widens the ambiguity margins
+    of render(), nothing else."""
+    mu = pr.mu2d[idx]
+    dx = pc[:, None, 0] - mu[None, :, 0]
+    dy = pc[:, None, 1] - mu[None, :, 1]
+    a, b, c = pr.conic[idx].unbind(1)
+    return 0.5 * (a.abs() * dx * dx + 2.0 * (b * dx * dy).abs() + c.abs() * dy * dy)
+
+
 def depth_order(pr: Projected) -> torch.Tensor:
     """Valid Gaussians sorted near to far by camera z, ties by index."""
     idx = torch.nonzero(pr.valid).flatten()
@@ -357,13 +372,18 @@ class RenderResult:
     ambiguous: np.ndarray    # [P] bool: a decision within the margins below
 
 
-def _margins(at, order_depth, opt, rel):
+def _margins(at, order_depth, opt, rel, cond=None):
     """Per-pixel flag: some decision of the definition lies within a relative
     margin of its threshold, where float32 evaluation may legitimately
     decide the other way (alpha vs 1/255 or vs the 0.99 clamp, T(1-alpha) vs
-    the stop level, two reaching Gaussians at equal depth)."""
-    amb = ((at - opt.alpha_min).abs() <= rel["alpha"] * opt.alpha_min).any(1)
-    amb |= ((at - opt.alpha_max).abs() <= rel["alpha"] * opt.alpha_max).any(1)
+    the stop level, two reaching Gaussians at equal depth).  Alpha margins
+    are on the log scale, |ln(alpha~ / threshold)| <= margin, and a pair's
+    grows by rel["cond"] times its power_terms (cond): rounding the stored
+    exponent's terms scales alpha~ by exp(+-rel["cond"] * power_terms)."""
+    ra = rel["alpha"] if cond is None else rel["alpha"] + rel.get("cond", 0.0) * cond
+    la = torch.log(at.clamp_min(1e-300))
+    amb = ((la - math.log(opt.alpha_min)).abs() <= ra).any(1)
+    amb |= ((la - math.log(opt.alpha_max)).abs() <= ra).any(1)
     alpha = torch.clamp(at, max=opt.alpha_max)
     a = torch.where(alpha >= opt.alpha_min, alpha, torch.zeros_like(alpha))
     ta = torch.cumprod(1.0 - a, 1)
@@ -380,7 +400,8 @@ def _margins(at, order_depth, opt, rel):
     return amb
 
 
-DEFAULT_MARGINS = {"alpha": 2e-4, "T": 2e-3, "depth": 1e-6}
+# relative margins; "cond": 2^-23 (two float32 half-ulps) per unit of power_terms
+DEFAULT_MARGINS = {"alpha": 2e-4, "T": 2e-3, "depth": 1e-6, "cond": 2.0 ** -23}
 
 
 def render(scene, pose_or_cam, pixels: np.ndarray | None = None, opt: Options = Options(),
@@ -411,8 +432,50 @@ def render(scene, pose_or_cam, pixels: np.ndarray | None = None, opt: Options = 
             k = inc.shape[1]
             lastpos = torch.where(inc, torch.arange(k).expand_as(inc), torch.full_like(inc, -1, dtype=torch.int64)).max(1).values if k else torch.full((pcs.shape[0],), -1)
             last[s:s + step] = np.where(lastpos.numpy() >= 0, order.numpy()[np.maximum(lastpos.numpy(), 0)], -1)
-            amb[s:s + step] = _margins(at, od, opt, margins).numpy()
+            cond = power_terms(pcs, pr, order) if margins.get("cond", 0.0) > 0 else None
+            amb[s:s + step] = _margins(at, od, opt, margins, cond).numpy()
     return RenderResult(pixels, col, Tf, last, ncon, amb)
+
+
+def float32_error_bound(scene, pose_or_cam, pixels: np.ndarray | None = None, opt: Options = Options(),
+                        u: float = 2.0 ** -22, chunk_elems: int = 1 << 19):
+    """First-order bound of the image and transmittance error that a float32
+    pipeline may incur from storing each pair's 2D mean and conic rounded:
+    with every alpha~ of an included pair off by a relative u * power_terms,
+    |dC_p| <= sum_k |dC_p/d alpha~_pk| alpha~_pk u power_terms_pk (same for
+    T).  The derivatives come from autograd through the same compositing
+    definition as render(), with the inclusion decisions held fixed.  Test
+    infrastructure: it sizes tolerances for ill-conditioned inputs (thin,
+    long ellipses), and is negligible for ordinary ones.  Returns
+    (bound_C [P,3], bound_T [P])."""
+    cam = pose_or_cam if isinstance(pose_or_cam, Camera) else camera_from_pose(pose_or_cam)
+    with torch.no_grad():
+        P = to_tensors(scene)
+        pr = project(P, scene.sh_degree, cam, opt)
+        order = depth_order(pr)
+        pixels, pc = pixel_centres(cam, pixels)
+        bg = torch.from_numpy(cam.bg.astype(np.float64))
+        rgb = pr.rgb[order]
+    n_pix = pc.shape[0]
+    bC = np.zeros((n_pix, 3)); bT = np.zeros(n_pix)
+    step = max(1, chunk_elems // max(1, order.numel()))
+    for s in range(0, n_pix, step):
+        pcs = pc[s:s + step]
+        with torch.no_grad():
+            at0 = alpha_tilde(pcs, pr, order, opt)
+            inc = inclusion(at0, opt)
+            e = u * power_terms(pcs, pr, order) * at0
+        at = at0.clone().requires_grad_(True)
+        C, T = composite(at, rgb, bg, inc, opt)
+        for ch in range(4):
+            out = T if ch == 3 else C[:, ch]
+            g, = torch.autograd.grad(out.sum(), at, retain_graph=ch < 3)
+            b = (g.abs() * e).sum(1).detach().numpy()
+            if ch == 3:
+                bT[s:s + step] = b
+            else:
+                bC[s:s + step, ch] = b
+    return bC, bT
 
 
 def project_numpy(scene, pose_or_cam, opt: Options = Options()) -> dict:

@@ -40,10 +40,15 @@ constexpr int RS_T = 256;          // threads per block
 // from 0.3M to 50M keys: fewer, longer blocks keep look-back chains short
 // (4 doubled the time of a pass over 1M keys).
 constexpr int RS_IPT = 16;
-// Instances per expansion block (a pass block covers RS_TILE / EX_TILE of
-// them), and the most records one can span.
+// Instances per expansion block: EX_TILE for large capacities (a pass block
+// covers RS_TILE / EX_TILE of them), EX_TILE_S up to EX_SMALL_CAP, where the
+// blocks' serial chains of dependent loads would otherwise leave most of the
+// chip idle.  A block spans at most its tile + 1 records.
 constexpr int EX_TILE = 2048;
-constexpr int EX_W = EX_TILE + 1;
+constexpr int EX_TILE_S = 512;
+constexpr uint64_t EX_SMALL_CAP = (uint64_t)EX_TILE * EX_TILE;
+static inline int ex_shift_for(uint64_t cap) { return cap <= EX_SMALL_CAP ? 9 : 11; }
+static_assert((1 << 9) == EX_TILE_S && (1 << 11) == EX_TILE, "expansion tile shifts");
 constexpr int EC = 64;             // expansion blocks per chunk of the count scan
 // pass blocks: 1024 threads for sorts of at most this many blocks (their
 // time is one block's latency), 512 for larger ones (measured: 256 threads
@@ -466,7 +471,7 @@ __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restri
                                                         uint32_t* __restrict__ n_inst,
                                                         uint64_t* status, uint32_t* counter,
                                                         uint32_t* err, uint32_t* __restrict__ bstart,
-                                                        uint32_t n_bstart) {
+                                                        uint32_t n_bstart, int ex_shift) {
   constexpr uint64_t VMASK = (1ull << 62) - 1;   // 62-bit running totals, 2 flag bits
   constexpr uint64_t F_AGG = 1ull << 62, F_INC = 2ull << 62;
   __shared__ uint32_t ws[4];
@@ -539,7 +544,8 @@ __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restri
     const int64_t j = j0 + k;
     if (j < m) {
       offs[j] = (uint32_t)run;
-      for (uint64_t bb = (run + EX_TILE - 1) / EX_TILE; bb * EX_TILE < run + c[k] && bb < n_bstart; ++bb)
+      const uint64_t ext = 1ull << ex_shift;
+      for (uint64_t bb = (run + ext - 1) >> ex_shift; (bb << ex_shift) < run + c[k] && bb < n_bstart; ++bb)
         bstart[bb] = (uint32_t)j;
     }
     run += c[k];
@@ -550,10 +556,18 @@ __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restri
   }
 }
 
+// Exclusive scan of one value per thread; *tot receives the block total.
+__device__ __forceinline__ uint32_t block_scan256_total(uint32_t x, uint32_t* ws4, uint32_t* tot) {
+  const uint32_t e = block_excl_scan256(x, ws4);
+  if (threadIdx.x == 255) *tot = e + x;
+  __syncthreads();
+  return e;
+}
+
 // Mode 1, step 3: load-balanced expansion.  Block b writes instances
-// [o0, o1) = [b*EX_TILE, (b+1)*EX_TILE).  Records in depth order with at least
+// [o0, o1) = [b*EXT, (b+1)*EXT).  Records in depth order with at least
 // one tile come first (culled ones sort last), so the records that own this
-// range are at most EX_TILE + 1 consecutive entries starting at the record
+// range are at most EXT + 1 consecutive entries starting at the record
 // j0 that owns instance o0 (bstart[b], from the offsets kernel).  The block enumerates (record, tile row)
 // items of those records in order, 256 at a time: each thread computes one
 // row's span once, a block scan turns the row counts into instance offsets
@@ -563,15 +577,9 @@ __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restri
 // row's instances have consecutive tile keys, so the low digit is counted
 // per instance and every higher digit once per run of equal high bits.
 
-// Exclusive scan of one value per thread; *tot receives the block total.
-__device__ __forceinline__ uint32_t block_scan256_total(uint32_t x, uint32_t* ws4, uint32_t* tot) {
-  const uint32_t e = block_excl_scan256(x, ws4);
-  if (threadIdx.x == 255) *tot = e + x;
-  __syncthreads();
-  return e;
-}
-
+template <int EXT>
 __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
+  constexpr int EX_W = EXT + 1;
   __shared__ uint32_t s_rec[EX_W];
   __shared__ uint32_t s_rows[EX_W + 1];   // exclusive prefix of the records' rect rows
   __shared__ uint32_t hist[4][256];
@@ -579,12 +587,12 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
   __shared__ uint32_t s_tot, s_j0, s_w;
   const uint32_t total = *a.n_inst;
   const uint32_t n = total < a.cap ? total : a.cap;
-  const uint64_t o0 = (uint64_t)blockIdx.x * EX_TILE;
+  const uint64_t o0 = (uint64_t)blockIdx.x * EXT;
   if (o0 >= n) {   // no instances: zero counts for the first pass's column scan
     if (a.cnt0) a.cnt0[(uint64_t)blockIdx.x * 256 + threadIdx.x] = 0u;
     return;
   }
-  const uint64_t o1 = min(o0 + (uint64_t)EX_TILE, (uint64_t)n);
+  const uint64_t o1 = min(o0 + (uint64_t)EXT, (uint64_t)n);
   const int t = threadIdx.x;
   const uint32_t dmask = (1u << a.hwidth) - 1u;
   for (int k = t; k < 4 * 256; k += 256) (&hist[0][0])[k] = 0u;
@@ -913,7 +921,7 @@ static BinLayout bin_layout(uintptr_t base, int64_t m, int64_t cap, int64_t tota
       L.tk[k] = reinterpret_cast<uint32_t*>(take(C * 4));
     }
     L.offs = reinterpret_cast<uint32_t*>(take(M * 4));
-    L.n_bstart = std::max<uint64_t>(cdiv(C, EX_TILE), 1);
+    L.n_bstart = std::max<uint64_t>(cdiv(C, 1ull << ex_shift_for(C)), 1);
     L.bstart = reinterpret_cast<uint32_t*>(take(L.n_bstart * 4));
     if (cdiv(C, (uint64_t)RS_T * RS_IPT) > RS_WIDE_MAX_BLOCKS) {
       L.cnt0 = reinterpret_cast<uint32_t*>(take(L.n_bstart * 256 * 4));
@@ -1020,7 +1028,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   const uint32_t* order = dv[0];
   k_sorted_offsets<<<(unsigned)cdiv(mm, SO_TILE), 256, 0, s>>>(
       order, g->tiles, m, L.offs, n_inst, reinterpret_cast<uint64_t*>(L.so_status + 64), L.so_status, err,
-      L.bstart, (uint32_t)L.n_bstart);
+      L.bstart, (uint32_t)L.n_bstart, ex_shift_for(C));
   SGS_LAUNCH_CHECK();
   const int passes = L.main_passes;
   const int src = passes & 1;
@@ -1031,17 +1039,23 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   a.bstart = L.bstart;
   a.keys32 = tk[src];
   a.vals = vb[src];
-  const uint64_t ex_blocks = cdiv(C, EX_TILE);
+  const int ex_shift = ex_shift_for(C);
+  const uint64_t ex_blocks = cdiv(C, 1ull << ex_shift);
   a.hcopies = ex_blocks > HC_MIN_BLOCKS ? HC : 1;
   a.hpart = a.hcopies > 1 ? sc_main.hpart : sc_main.ghist;
   // large sorts scan the expansion blocks' first-digit counts instead of
   // looking back over the blocks of the first pass
+  // (their expansion blocks are EX_TILE long)
+  static_assert(RS_WIDE_MAX_BLOCKS * RS_T * RS_IPT >= EX_SMALL_CAP, "scanned first pass needs EX_TILE");
   const bool scan0 = cdiv(C, (uint64_t)RS_T * RS_IPT) > RS_WIDE_MAX_BLOCKS;
   a.cnt0 = scan0 ? L.cnt0 : nullptr;
   a.hpasses = passes;
   a.hwidth = rs_width(tb);
   if (cap > 0) {
-    k_expand32<<<(unsigned)cdiv(C, EX_TILE), 256, 0, s>>>(a);
+    if (ex_shift == 9)
+      k_expand32<EX_TILE_S><<<(unsigned)ex_blocks, 256, 0, s>>>(a);
+    else
+      k_expand32<EX_TILE><<<(unsigned)ex_blocks, 256, 0, s>>>(a);
     SGS_LAUNCH_CHECK();
     if (scan0) {
       const uint32_t nch = (uint32_t)cdiv(ex_blocks, EC);

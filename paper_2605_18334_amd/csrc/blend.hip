@@ -120,8 +120,9 @@ __device__ __forceinline__ bool band_xrange(float a, float b, float c, float det
   const float yx = -b * ex * __builtin_amdgcn_rcpf(c);             // ... reached at dy = yx
   if (yx >= u0 && yx <= u1) xr = ex;
   if (-yx >= u0 && -yx <= u1) xl = -ex;
-  xr = xr * 1.001f + 0.01f;
-  xl = xl * 1.001f - 0.01f;
+  // widen outwards on both sides: 0.1% of the offset plus 0.01 px
+  xr = xr + (fabsf(xr) * 1e-3f + 0.01f);
+  xl = xl - (fabsf(xl) * 1e-3f + 0.01f);
   return true;
 }
 

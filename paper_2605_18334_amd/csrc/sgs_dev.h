@@ -172,8 +172,9 @@ __device__ __forceinline__ void span_row(const Span& s, int row, int tw, int th,
   float xl = fminf((-s.b * u0 - r0) * s.ia, (-s.b * u1 - r1) * s.ia);
   if (s.yx >= u0 && s.yx <= u1) xr = s.ex;
   if (-s.yx >= u0 && -s.yx <= u1) xl = -s.ex;
-  xr = xr * 1.001f + 0.01f;
-  xl = xl * 1.001f - 0.01f;
+  // widen outwards on both sides: 0.1% of the offset plus 0.01 px
+  xr = xr + (fabsf(xr) * 1e-3f + 0.01f);
+  xl = xl - (fabsf(xl) * 1e-3f + 0.01f);
   const float px0 = ceilf(s.mx + xl - 0.5f), px1 = floorf(s.mx + xr - 0.5f);
   if (!(px0 <= px1) || !(px1 >= 0.0f)) return;
   const float lo = fmaxf(px0, 0.0f);

@@ -507,3 +507,37 @@ def test_densify_stats_match_central_differences():
     assert checked_z >= 16 and checked_uv >= 16
     # the statistics are not trivially zero
     assert st["z"][cand].max() > 0 and st["uv"][cand].max() > 0
+
+
+def test_power_terms_bound_the_exponent():
+    """power_terms (the scale of the float32 rounding margin) bounds |log G'|
+    by the triangle inequality, with equality for an axis-aligned conic, and
+    a 100:1 sliver along its long axis has terms (L/w)^2 = 1e4 times the
+    exponent."""
+    rng = np.random.default_rng(3)
+    n = 50
+    a_, c_ = rng.uniform(0.01, 0.3, n), rng.uniform(0.01, 0.3, n)
+    pr = O.Projected(
+        mu2d=torch.from_numpy(rng.uniform(40, 60, (n, 2))),
+        conic=torch.from_numpy(np.stack([a_, rng.uniform(-0.9, 0.9, n) * np.sqrt(a_ * c_), c_], 1)),
+        rho=torch.ones(n, dtype=torch.float64), o1=torch.ones(n, dtype=torch.float64),
+        o2=torch.ones(n, dtype=torch.float64), beta2d=torch.zeros(n, 2, dtype=torch.float64),
+        w2d=None, rgb=torch.zeros(n, 3, dtype=torch.float64), depth=torch.ones(n, dtype=torch.float64),
+        valid=torch.ones(n, dtype=torch.bool))
+    pc = torch.from_numpy(rng.uniform(35, 65, (30, 2)))
+    idx = torch.arange(n)
+    at = O.alpha_tilde(pc, pr, idx, O.Options(symmetric=True))
+    terms = O.power_terms(pc, pr, idx)
+    assert (terms >= -torch.log(at) * (1 - 1e-12)).all()
+    pr.conic[:, 1] = 0.0
+    at = O.alpha_tilde(pc, pr, idx, O.Options(symmetric=True))
+    np.testing.assert_allclose(O.power_terms(pc, pr, idx).numpy(), -torch.log(at).numpy(), rtol=1e-12)
+    # conic of a 100:1 ellipse at 45 degrees, 120 px along the long axis
+    s = 1 / np.sqrt(2)
+    R = np.array([[s, -s], [s, s]])
+    Q = R @ np.diag([1 / 50.0 ** 2, 1 / 0.5 ** 2]) @ R.T
+    pr.conic[0] = torch.tensor([Q[0, 0], Q[0, 1], Q[1, 1]])
+    p = pr.mu2d[0:1] + torch.tensor([[120 * s, 120 * s]])
+    t = float(O.power_terms(p, pr, idx[:1])[0, 0])
+    e = float(-torch.log(O.alpha_tilde(p, pr, idx[:1], O.Options(symmetric=True)))[0, 0])
+    assert abs(e - 0.5 * (120 / 50) ** 2) < 1e-9 and abs(t / e - 1e4) < 1e-3 * 1e4
