@@ -89,11 +89,7 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
 // Exclusive scan over the 256 threads of a block of x (one value per thread).
 __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* ws4) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  uint32_t inc = x;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(inc, off);
-    if (lane >= off) inc += y;
-  }
+  const uint32_t inc = wave_incl_scan(x);
   if (lane == 63) ws4[w] = inc;
   __syncthreads();
   uint32_t e = inc - x;
@@ -200,23 +196,6 @@ __global__ void __launch_bounds__(256) k_hist_final(const uint32_t* __restrict__
 // pre != nullptr: no look-back; the keys of digit d before this block are
 // counted by the scanned per-block counts of the expansion blocks that wrote
 // the input (k_chunk_scan; the first pass of sort mode 1).
-// Exclusive scan over the 256 digits held by threads 0..255 (one value
-// each); every thread of the block must call it (it holds the barriers).
-__device__ __forceinline__ uint32_t digit_excl_scan(uint32_t x, uint32_t* ws4) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  uint32_t inc = x;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(inc, off);
-    if (lane >= off) inc += y;
-  }
-  if (lane == 63 && w < 4) ws4[w] = inc;
-  __syncthreads();
-  uint32_t e = inc - x;
-  for (int k = 0; k < w && k < 4; ++k) e += ws4[k];
-  __syncthreads();
-  return e;
-}
-
 // One pass over RS_TILE keys per block of NT threads (NT / 64 waves, each
 // ranking RS_TILE / NT keys per lane): 512 threads for large sorts, 1024 for
 // small ones, where a block's latency (mostly the per-wave ranking rounds)
@@ -240,7 +219,7 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
   __shared__ uint32_t lstart[256];
   __shared__ uint32_t lend[256];
   __shared__ uint32_t goff[256];
-  __shared__ uint32_t ws[4];
+  __shared__ uint32_t ws[8];
   __shared__ uint32_t s_bid;
   __shared__ K skey[RS_TILE];
   __shared__ uint32_t sval[RS_TILE];
@@ -257,6 +236,7 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
   const uint64_t lt = lanemask_lt();
   // this lane's keys are base + 64 i for i < nv (the valid ones)
   const int nv = base < n ? (int)min((uint64_t)IPT, (n - base + 63) / 64) : 0;
+  const uint32_t gh = t < 256 ? ghist[t] : 0u;   // keys of digit t in the whole input
   K key[IPT];
   uint32_t val[IPT];
   uint32_t rank[IPT];
@@ -285,22 +265,39 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
 #pragma unroll
   for (int i = 0; i < IPT; ++i) rank[i] = (rank[i] & 255u) + __shfl(lead_base[i], (int)(rank[i] >> 8));
   __syncthreads();
-  // digit t (threads 0..255): block total, start in the block, per-wave starts
-  uint32_t tot = 0;
-  if (t < 256)
-    for (int v = 0; v < NW; ++v) tot += wc[v][t];
-  const uint32_t ls = digit_excl_scan(tot, ws);
-  const uint32_t ds = digit_excl_scan(t < 256 ? ghist[t] : 0u, ws);   // start of digit t in the output
+  // digit t (threads 0..255, the first four waves): block total, start in
+  // the block, per-wave starts, and start in the output (scan of ghist)
+  uint32_t cw[NW];
+  uint32_t tot = 0, ls = 0, ds = 0;
+  if (t < 256) {
+#pragma unroll
+    for (int v = 0; v < NW; ++v) {
+      cw[v] = wc[v][t];
+      tot += cw[v];
+    }
+    const uint32_t il = wave_incl_scan(tot), ig = wave_incl_scan(gh);
+    if (lane == 63) {
+      ws[w] = il;
+      ws[4 + w] = ig;
+    }
+    ls = il - tot;
+    ds = ig - gh;
+  }
+  __syncthreads();
   const bool has_digit = t < (1 << nbits);   // (nbits <= 8: implies t < 256)
   uint64_t* st = status + (uint64_t)b * 256 + t;
   if (t < 256) {
+    for (int k = 0; k < w; ++k) {
+      ls += ws[k];
+      ds += ws[4 + k];
+    }
     lstart[t] = ls;
     lend[t] = ls + tot;
     uint32_t run = ls;
+#pragma unroll
     for (int v = 0; v < NW; ++v) {
-      const uint32_t c = wc[v][t];
       wc[v][t] = run;
-      run += c;
+      run += cw[v];
     }
     // publish this block's count of digit t as early as possible (later
     // blocks' look-backs wait for it); threads past the last digit idle

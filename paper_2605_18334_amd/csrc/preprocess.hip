@@ -243,11 +243,7 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
   }
   // tiles of each rect that the evaluation ellipse (cut by the skew
   // half-plane) reaches, row by row, per wave
-  uint32_t incl = rows;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(incl, off);
-    if (lane >= off) incl += y;
-  }
+  const uint32_t incl = wave_incl_scan(rows);
   s_pref[w][lane] = incl - rows;
   if (lane == 63) s_pref[w][64] = incl;
   s_cnt[t] = 0;

@@ -210,6 +210,21 @@ __device__ __forceinline__ float dpp_src(float v) {
       __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, false));
 }
 
+// Inclusive prefix sum over the 64 lanes of the wave: within each row of 16
+// by row shifts of 1, 2, 4 and 8, then the last lane of row 0 (of row 2) is
+// broadcast into row 1 (row 3), and the last lane of row 1 into rows 2 and
+// 3.  Lanes a DPP step has no source for add 0.  All 64 lanes must be
+// active.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+  return v;
+}
+
 // Sum over each 16-lane row of the wave; every lane of a row gets its row's
 // sum.  All 64 lanes must be active.
 __device__ __forceinline__ float row_sum16(float v) {
