@@ -115,12 +115,17 @@ __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, co
   const uint32_t n = count_of(n_dev, n_host, cap);
   constexpr int RS_TILE = RS_T * RS_IPT;
   const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+  // all loads first (in flight together), then the LDS counts
+  K key[RS_IPT];
+#pragma unroll
   for (int i = 0; i < RS_IPT; ++i) {
     const uint64_t idx = base + (uint64_t)i * RS_T + t;
-    if (idx < n) {
-      const K key = keys[idx];
-      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][digit_of<K>(key, width * p, dmask)], 1u);
-    }
+    key[i] = idx < n ? keys[idx] : (K)0;
+  }
+#pragma unroll
+  for (int i = 0; i < RS_IPT; ++i) {
+    if (base + (uint64_t)i * RS_T + t < n)
+      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][digit_of<K>(key[i], width * p, dmask)], 1u);
   }
   __syncthreads();
   uint32_t* dst = hpart + (size_t)(blockIdx.x % (unsigned)ncopies) * passes * 256;

@@ -81,14 +81,22 @@ __device__ __forceinline__ bool setup_tile(const BlendArgs& a, int tile, TileSet
   return true;
 }
 
+// List entries: the record's slot in the batch, LIST_SKEW set when its 2D
+// skew is nonzero (NaN counting as nonzero); mask bit SKEW_BIT carries the
+// same flag while the lists are built.
+constexpr uint32_t LIST_SLOT = 0xffu, LIST_SKEW = 0x100u, SKEW_BIT = 0x80u;
+
 // Staged batch of B records and the per-wave compacted lists.
 template <int TW, int TH, int B, bool ENH>
 struct Stage {
   static constexpr int NT = TW * TH;
   static constexpr int NW = NT / 64;
   static constexpr int NG = B / 64;   // 64-record groups of the batch
+  // r0 = (mu_x, mu_y, A, B), r1 = (C, bxs, bys, D), r2 = (r, g, b, log2 e
+  // log_thr + D): the base-2 constants of pair_log2 / pair_eval2
   float4 r0[B], r1[B], r2[B];
   float4 r3[ENH ? B : 1];
+  float idv[B];           // 1/d (backward)
   uint32_t rid[B];
   uint8_t mask[B];
   uint16_t cnt[NW][NG];
@@ -148,16 +156,19 @@ __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup&
       const float4* rp = a.rec + 4 * (uint64_t)m;
       const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2];
       S.rid[k] = m;
-      S.r0[k] = q0;
-      S.r1[k] = q1;
-      S.r2[k] = q2;
+      const float D = __builtin_amdgcn_logf(q1.w);   // log2 d
+      S.r0[k] = make_float4(q0.x, q0.y, SGS_KA * q0.z, -SGS_L2E * q0.w);
+      S.r1[k] = make_float4(SGS_KA * q1.x, SGS_KZ * q1.y, SGS_KZ * q1.z, D);
+      S.r2[k] = make_float4(q2.x, q2.y, q2.z, fmaf(SGS_L2E, q2.w, D));
+      S.idv[k] = 1.0f / q1.w;
       if (ENH) S.r3[k] = rp[3];
+      if ((q1.y != 0.0f) || (q1.z != 0.0f)) msk = SKEW_BIT;
       // the ellipse delta^T Q delta <= -2 log_thr outside which every pair
       // is skipped, with the margins of the tile extent
       const float det = q0.z * q1.x - q0.w * q0.w;
       const float R2 = -2.0f * q2.w * 1.002f + 1e-3f;
       if (!(det > 0.0f) || !(q0.z > 0.0f) || !(R2 > 0.0f) || !(R2 < 1e30f) || !(det < 1e30f)) {
-        msk = (1u << St::NW) - 1u;
+        msk |= (1u << St::NW) - 1u;
       } else {
         // skew half-plane: alpha <= d (1 + erf(z)) stays below alpha_min
         // wherever beta.delta < sqrt2 * zcut
@@ -205,7 +216,7 @@ __device__ __forceinline__ void stage_batch(const BlendArgs& a, const TileSetup&
       if (bit) {
         uint32_t off = (uint32_t)__popcll(bal & lt);
         for (int g = 0; g < (k >> 6); ++g) off += S.cnt[w][g];
-        S.list[w][off] = (uint16_t)k;
+        S.list[w][off] = (uint16_t)(k | ((msk & SKEW_BIT) ? LIST_SKEW : 0u));
       }
     }
   }
@@ -257,20 +268,21 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
     stage_batch<TW, TH, B, ENH>(a, ts, base, cnt, S);
     // the wave walks its list together: control flow is wave-uniform, lanes
     // that are finished or outside a record's ellipse are masked
-    const int nw = S.n[w];
+    const int nw = __builtin_amdgcn_readfirstlane(S.n[w]);   // wave-uniform
     int jn = nw > 0 ? S.list[w][0] : 0;
     for (int i = 0; i < nw; ++i) {
-      const int j = __builtin_amdgcn_readfirstlane(jn);
+      const uint32_t e = (uint32_t)__builtin_amdgcn_readfirstlane(jn);
+      const int j = (int)(e & LIST_SLOT);
       if (i + 1 < nw) jn = S.list[w][i + 1];
       const float4 r0 = S.r0[j];
       const float4 r1 = S.r1[j];
       const float4 r2 = S.r2[j];
       const float dx = fx - r0.x, dy = fy - r0.y;
-      const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
-      const bool in = !done && power >= r2.w;
+      const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
+      const bool in = !done && l2 >= r2.w;
       if (!__any(in)) continue;
-      Pair p;
-      pair_eval(power, r1.w, r1.y, r1.z, dx, dy, uniform_skew(r1), p);
+      Pair2 p;
+      pair_eval2(l2, r1.y, r1.z, dx, dy, (e & LIST_SKEW) != 0u, p);
       float at = p.at;
       if (ENH) {
         const float4 r3 = S.r3[j];
@@ -342,21 +354,22 @@ __device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quart
     if (__syncthreads_and(done)) break;
     const int cnt = (int)min((uint32_t)B, rg.y - base);
     stage_batch<16, 16, B, ENH, 4>(a, ts, base, cnt, S);
-    const int nw = S.n[w];
+    const int nw = __builtin_amdgcn_readfirstlane(S.n[w]);   // wave-uniform
     for (int i = 0; i < nw; i += 4) {
       const int k = i + sub;
       const bool has = k < nw;
-      const int j = has ? S.list[w][k] : 0;
+      const uint32_t e = has ? S.list[w][k] : 0u;
+      const int j = (int)(e & LIST_SLOT);
       const float4 r0 = S.r0[j];
       const float4 r1 = S.r1[j];
       const float4 r2 = S.r2[j];
       const float dx = fx - r0.x, dy = fy - r0.y;
-      const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
-      const bool in = has && !done && power >= r2.w;
+      const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
+      const bool in = has && !done && l2 >= r2.w;
       float alpha = 0.0f;
       if (__any(in)) {
-        Pair p;
-        pair_eval(power, r1.w, r1.y, r1.z, dx, dy, (r1.y != 0.0f) || (r1.z != 0.0f), p);
+        Pair2 p;
+        pair_eval2(l2, r1.y, r1.z, dx, dy, (e & LIST_SKEW) != 0u, p);
         float at = p.at;
         if (ENH) {
           const float4 r3 = S.r3[j];
@@ -509,9 +522,13 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
     stage_batch<TW, TH, B, ENH>(a, ts, rg.x + start, cnt, S);
     for (int k = t; k < NG * B; k += NT) (&sg[0][0])[k] = 0.0f;
     __syncthreads();
-    const int nw = S.n[w];
+    const int nw = __builtin_amdgcn_readfirstlane(S.n[w]);   // wave-uniform
     for (int i = nw - 1; i >= 0; --i) {
-      const int j = S.list[w][i];
+      // j stays a per-lane value: with a wave-uniform LDS address the
+      // compiler turns the atomics below into serial per-lane loops
+      const uint32_t e = S.list[w][i];
+      const int j = (int)(e & LIST_SLOT);
+      const bool skew = ((uint32_t)__builtin_amdgcn_readfirstlane((int)e) & LIST_SKEW) != 0u;
       float gv[NG];
 #pragma unroll
       for (int q = 0; q < NG; ++q) gv[q] = 0.0f;
@@ -520,11 +537,11 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
         const float4 r0 = S.r0[j];
         const float4 r1 = S.r1[j];
         const float dx = fx - r0.x, dy = fy - r0.y;
-        const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
+        const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
         const float4 r2 = S.r2[j];
-        if (power >= r2.w) {
-          Pair p;
-          pair_eval(power, r1.w, r1.y, r1.z, dx, dy, uniform_skew(r1), p);
+        if (l2 >= r2.w) {
+          Pair2 p;
+          pair_eval2(l2, r1.y, r1.z, dx, dy, skew, p);
           float at = p.at, o = 1.0f, eu = 0.0f, ee = 1.0f;
           float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
           if (ENH) {
@@ -544,18 +561,20 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
             float dLda = ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) * T;
             dLda -= Tfinal * inv * bgdot;
             if (at <= a.alpha_max) {
-              const float dd = r1.w * o;              // d, times o(delta) with enhanced opacity
+              // common = dL/dalpha d o G'; (qa, qc) = Q delta and beta from
+              // the staged base-2 constants
               const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
-              const float common = dLda * dd * p.G;
-              const float qa = fmaf(r0.z, dx, r0.w * dy), qc = fmaf(r0.w, dx, r1.x * dy);
-              gv[0] = common * (qa * p.E - s2pi * r1.y);
-              gv[1] = common * (qc * p.E - s2pi * r1.z);
+              const float common = dLda * o * p.dG;
+              const float qa = -SGS_LN2 * fmaf(2.0f * r0.z, dx, r0.w * dy);
+              const float qc = -SGS_LN2 * fmaf(r0.w, dx, 2.0f * r1.x * dy);
+              gv[0] = common * (qa * p.E - s2pi * (SGS_IKZ * r1.y));
+              gv[1] = common * (qc * p.E - s2pi * (SGS_IKZ * r1.z));
               gv[2] = -0.5f * dx * dx * dLda * at;
               gv[3] = -dx * dy * dLda * at;
               gv[4] = -0.5f * dy * dy * dLda * at;
               gv[5] = common * s2pi * dx;
               gv[6] = common * s2pi * dy;
-              gv[7] = dLda * p.G * p.E * o;
+              gv[7] = common * p.E * S.idv[j];
               if (ENH) {
                 const float base = p.at;             // rho G' (1 + erf z)
                 const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
@@ -640,23 +659,25 @@ __device__ __forceinline__ void bwd_quad(const BlendArgs& a, int tile, int quart
     stage_batch<16, 16, B, ENH, 4>(a, ts, rg.x + start, cnt, S);
     for (int k = t; k < NG * B; k += NT) (&sg[0][0])[k] = 0.0f;
     __syncthreads();
-    const int nw = S.n[w];
+    const int nw = __builtin_amdgcn_readfirstlane(S.n[w]);   // wave-uniform
     for (int i = nw - 1; i >= 0; i -= 4) {
       const int k = i - sub;
       const bool has = k >= 0;
-      const int j = has ? S.list[w][k] : 0;
+      const uint32_t e = has ? S.list[w][k] : 0u;
+      const int j = (int)(e & LIST_SLOT);
       const float4 r0 = S.r0[j];
       const float4 r1 = S.r1[j];
       const float4 r2 = S.r2[j];
       const float dx = fx - r0.x, dy = fy - r0.y;
-      const float power = pair_power(r0.z, r0.w, r1.x, dx, dy);
-      const bool in = has && (uint32_t)(start + j) < last && power >= r2.w;
-      Pair p;
-      p.G = p.E = p.ez = 1.0f;
+      const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
+      const bool in = has && (uint32_t)(start + j) < last && l2 >= r2.w;
+      Pair2 p;
+      p.dG = p.E = p.ez = 1.0f;
+      p.at = 0.0f;
       float at = 0.0f, o = 1.0f, eu = 0.0f, ee = 1.0f, alpha = 0.0f;
       float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
       if (__any(in)) {
-        pair_eval(power, r1.w, r1.y, r1.z, dx, dy, (r1.y != 0.0f) || (r1.z != 0.0f), p);
+        pair_eval2(l2, r1.y, r1.z, dx, dy, (e & LIST_SKEW) != 0u, p);
         at = p.at;
         if (ENH) {
           r3 = S.r3[j];
@@ -702,18 +723,18 @@ __device__ __forceinline__ void bwd_quad(const BlendArgs& a, int tile, int quart
         float dLda = ((r2.x - Sm0) * g0 + (r2.y - Sm1) * g1 + (r2.z - Sm2) * g2) * Tm;
         dLda -= Tfinal * __builtin_amdgcn_rcpf(1.0f - alpha) * bgdot;
         if (at <= a.alpha_max) {
-          const float dd = r1.w * o;
           const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
-          const float common = dLda * dd * p.G;
-          const float qa = fmaf(r0.z, dx, r0.w * dy), qc = fmaf(r0.w, dx, r1.x * dy);
-          gv[0] = common * (qa * p.E - s2pi * r1.y);
-          gv[1] = common * (qc * p.E - s2pi * r1.z);
+          const float common = dLda * o * p.dG;
+          const float qa = -SGS_LN2 * fmaf(2.0f * r0.z, dx, r0.w * dy);
+          const float qc = -SGS_LN2 * fmaf(r0.w, dx, 2.0f * r1.x * dy);
+          gv[0] = common * (qa * p.E - s2pi * (SGS_IKZ * r1.y));
+          gv[1] = common * (qc * p.E - s2pi * (SGS_IKZ * r1.z));
           gv[2] = -0.5f * dx * dx * dLda * at;
           gv[3] = -dx * dy * dLda * at;
           gv[4] = -0.5f * dy * dy * dLda * at;
           gv[5] = common * s2pi * dx;
           gv[6] = common * s2pi * dy;
-          gv[7] = dLda * p.G * p.E * o;
+          gv[7] = common * p.E * S.idv[j];
           if (ENH) {
             const float base = p.at;
             const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;

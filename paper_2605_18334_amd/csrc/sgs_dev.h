@@ -9,6 +9,11 @@
 #define SGS_INV_SQRT2 0.70710678118654752f
 #define SGS_SQRT_2_OVER_PI 0.79788456080286536f   // sqrt(2/pi)
 #define SGS_INV_SQRT_2PI 0.39894228040143268f      // 1/sqrt(2 pi)
+#define SGS_L2E 1.44269504088896341f                // log2(e)
+#define SGS_LN2 0.69314718055994531f                // ln(2) = 1/log2(e)
+#define SGS_KA (-0.72134752044448170f)              // -log2(e)/2
+#define SGS_KZ 0.84932180028801904f                 // sqrt(log2(e)/2)
+#define SGS_IKZ 1.17741002251547466f                // 1/SGS_KZ
 
 namespace sgs {
 
@@ -30,14 +35,6 @@ __device__ __forceinline__ float4 ld4(const float* p, int64_t i) {
 // - b dx dy), z = (beta_x dx + beta_y dy)/sqrt 2, alpha~ = d G' (1 + erf z).
 // Written with explicit fma so that the forward and the backward kernels
 // evaluate bit-identical values (their decisions must agree).
-struct Pair {
-  float power;  // exponent of G'
-  float G;      // G'
-  float z;      // skew argument
-  float E;      // 1 + erf(z)
-  float ez;     // exp(-z^2) (1 when z = 0)
-  float at;     // unclamped alpha (without the enhanced-opacity factor)
-};
 
 // 1 + erf(z) = erfc(-z) with erfc(x) ~ t P(t) exp(-x^2), t = 1/(1 + p x),
 // x >= 0 (Abramowitz & Stegun 1964, formula 7.1.26, |error| <= 1.5e-7), and
@@ -54,33 +51,48 @@ __device__ __forceinline__ float one_plus_erf(float z, float& ez) {
   return z < 0.0f ? q : 2.0f - q;
 }
 
-// Whether a staged record has a nonzero 2D skew, as a wave-uniform value
-// (every lane of the wave reads the same record): the same truth value as
-// (beta_x != 0) || (beta_y != 0), NaN counting as nonzero.
-__device__ __forceinline__ bool uniform_skew(const float4& r1) {
-  const uint32_t bx = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(r1.y));
-  const uint32_t by = (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(r1.z));
-  return ((bx | by) << 1) != 0u;
+// The kernels evaluate it in base 2, with per-record constants staged once
+// per batch: log2(d G') = A dx^2 + B dx dy + C dy^2 + D with
+// A = -(log2 e)/2 a, B = -(log2 e) b, C = -(log2 e)/2 c, D = log2 d, and the
+// skew argument scaled by sqrt(log2 e): zs = bxs dx + bys dy = z sqrt(log2 e)
+// with (bxs, bys) = sqrt(log2(e)/2) (beta_x, beta_y), so exp(-z^2) = 2^-zs^2.
+// The skip test log2(d G') >= log2(e) log_thr + D is the exponent test of the
+// natural form.  Forward and backward evaluate these same expressions.
+struct Pair2 {
+  float dG;     // d G'
+  float E;      // 1 + erf(z)
+  float ez;     // exp(-z^2) (1 when z = 0)
+  float at;     // d G' (1 + erf z) (without the enhanced-opacity factor)
+};
+
+__device__ __forceinline__ float pair_log2(float A, float B, float C, float D, float dx, float dy) {
+  return fmaf(fmaf(A, dx, B * dy), dx, fmaf(C * dy, dy, D));
 }
 
-__device__ __forceinline__ float pair_power(float a, float b, float c, float dx, float dy) {
-  float q = fmaf(a * dx, dx, fmaf(c * dy, dy, (2.0f * b) * (dx * dy)));
-  return -0.5f * q;
+// one_plus_erf of z = zs / sqrt(log2 e): t = 1/(1 + p x) with p x =
+// (p / sqrt(log2 e)) |zs|, and exp(-x^2) = 2^(-zs^2).
+__device__ __forceinline__ float one_plus_erf_s(float zs, float& ez) {
+  const float x = fabsf(zs);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.27273747324943543f, x, 1.0f));
+  float poly = fmaf(1.061405429f, t, -1.453152027f);
+  poly = fmaf(poly, t, 1.421413741f);
+  poly = fmaf(poly, t, -0.284496736f);
+  poly = fmaf(poly, t, 0.254829592f);
+  ez = __builtin_amdgcn_exp2f(-(zs * zs));
+  const float q = (poly * t) * ez;      // erfc(|z|)
+  return zs < 0.0f ? q : 2.0f - q;
 }
 
-__device__ __forceinline__ void pair_eval(float power, float d, float bx, float by, float dx,
-                                          float dy, bool skew, Pair& p) {
-  p.power = power;
-  p.G = __expf(power);
+__device__ __forceinline__ void pair_eval2(float l2, float bxs, float bys, float dx, float dy,
+                                           bool skew, Pair2& p) {
+  p.dG = __builtin_amdgcn_exp2f(l2);
   if (skew) {
-    p.z = fmaf(bx, dx, by * dy) * SGS_INV_SQRT2;
-    p.E = one_plus_erf(p.z, p.ez);
+    p.E = one_plus_erf_s(fmaf(bxs, dx, bys * dy), p.ez);
   } else {
-    p.z = 0.0f;
     p.E = 1.0f;
     p.ez = 1.0f;
   }
-  p.at = (d * p.G) * p.E;
+  p.at = p.dG * p.E;
 }
 
 // Enhanced opacity factor o(delta) = ((o1+o2) + (o1-o2) erf(w.delta/sqrt2))/2
