@@ -48,6 +48,33 @@ struct Proj {
   bool valid;
 };
 
+// One Gaussian's parameters, loaded together at the start of a thread so
+// that their latencies overlap (the projection branches on the depth and on
+// the footprint before it would otherwise reach the later loads).
+template <int DEG>
+struct Raw {
+  static constexpr int K = (DEG + 1) * (DEG + 1);
+  float mean[3], ls[3], q[4], op, op2, sk[3], od[3];
+  float sh[K * 3];   // [k][channel]
+};
+
+template <int DEG>
+__device__ __forceinline__ void load_raw(const sgs_params& p, int64_t i, int64_t n, Raw<DEG>& r) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r.mean[k] = p.mean[k * n + i];
+    r.ls[k] = p.log_scale[k * n + i];
+    r.sk[k] = p.skew ? p.skew[k * n + i] : 0.0f;
+    r.od[k] = p.opa_dir ? p.opa_dir[k * n + i] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.q[k] = p.quat[k * n + i];
+  r.op = p.opa_logit[i];
+  r.op2 = p.opa2_logit ? p.opa2_logit[i] : 0.0f;
+#pragma unroll
+  for (int k = 0; k < Raw<DEG>::K * 3; ++k) r.sh[k] = p.sh[(int64_t)k * n + i];
+}
+
 __device__ __forceinline__ void skew_map(const Proj& P, const float g[3], int k, Proj& Q) {
   float u0 = P.M[0][0] * g[0] + P.M[1][0] * g[1] + P.M[2][0] * g[2];
   float u1 = P.M[0][1] * g[0] + P.M[1][1] * g[1] + P.M[2][1] * g[2];
@@ -68,10 +95,10 @@ __device__ __forceinline__ void skew_map(const Proj& P, const float g[3], int k,
 }
 
 template <int DEG>
-__device__ __forceinline__ void project_fwd(const sgs_params& p, const sgs_camera& cam,
-                                            const sgs_options& opt, int64_t i, int64_t n,
+__device__ __forceinline__ void project_fwd(const sgs_params& p, const Raw<DEG>& raw,
+                                            const sgs_camera& cam, const sgs_options& opt,
                                             Proj& P) {
-  const float mx = p.mean[i], my = p.mean[n + i], mz = p.mean[2 * n + i];
+  const float mx = raw.mean[0], my = raw.mean[1], mz = raw.mean[2];
   const float* W = cam.w2c;
   P.tz = fmaf(W[8], mx, fmaf(W[9], my, fmaf(W[10], mz, W[11])));
   P.valid = (P.tz > cam.near_z) && isfinite(P.tz);
@@ -79,8 +106,8 @@ __device__ __forceinline__ void project_fwd(const sgs_params& p, const sgs_camer
   P.tx = fmaf(W[0], mx, fmaf(W[1], my, fmaf(W[2], mz, W[3])));
   P.ty = fmaf(W[4], mx, fmaf(W[5], my, fmaf(W[6], mz, W[7])));
   // activations and M = R diag(s)
-  for (int k = 0; k < 3; ++k) P.s[k] = __expf(p.log_scale[k * n + i]);
-  float qw = p.quat[i], qx = p.quat[n + i], qy = p.quat[2 * n + i], qz = p.quat[3 * n + i];
+  for (int k = 0; k < 3; ++k) P.s[k] = __expf(raw.ls[k]);
+  float qw = raw.q[0], qx = raw.q[1], qy = raw.q[2], qz = raw.q[3];
   P.qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
   const float iq = 1.0f / P.qn;
   qw *= iq; qx *= iq; qy *= iq; qz *= iq;
@@ -138,13 +165,13 @@ __device__ __forceinline__ void project_fwd(const sgs_params& p, const sgs_camer
   P.rho = opt.compensate ? sqrtf(fmaxf(P.det2, 0.0f) * idet) : 1.0f;
   P.mux = fmaf(cam.fx, P.txr, cam.cx);
   P.muy = fmaf(cam.fy, P.tyr, cam.cy);
-  P.o1 = 1.0f / (1.0f + __expf(-p.opa_logit[i]));
-  P.o2 = p.opa2_logit ? 1.0f / (1.0f + __expf(-p.opa2_logit[i])) : P.o1;
+  P.o1 = 1.0f / (1.0f + __expf(-raw.op));
+  P.o2 = p.opa2_logit ? 1.0f / (1.0f + __expf(-raw.op2)) : P.o1;
   // 2D skew: exact marginal of the skew-normal under B and the blur
   P.b2x = P.b2y = 0.0f;
   float beta[3] = {0.f, 0.f, 0.f};
   if (p.skew) {
-    for (int k = 0; k < 3; ++k) beta[k] = p.skew[k * n + i];
+    for (int k = 0; k < 3; ++k) beta[k] = raw.sk[k];
     skew_map(P, beta, 0, P);
     P.b2x = P.qv[0][0] * P.rr[0];
     P.b2y = P.qv[0][1] * P.rr[0];
@@ -152,7 +179,7 @@ __device__ __forceinline__ void project_fwd(const sgs_params& p, const sgs_camer
   P.w2x = P.w2y = 0.0f;
   if (p.opa2_logit) {
     float g[3];
-    for (int k = 0; k < 3; ++k) g[k] = beta[k] + (p.opa_dir ? p.opa_dir[k * n + i] : 0.0f);
+    for (int k = 0; k < 3; ++k) g[k] = beta[k] + raw.od[k];
     skew_map(P, g, 1, P);
     P.w2x = P.qv[1][0] * P.rr[1];
     P.w2y = P.qv[1][1] * P.rr[1];
@@ -168,7 +195,7 @@ __device__ __forceinline__ void project_fwd(const sgs_params& p, const sgs_camer
   for (int ch = 0; ch < 3; ++ch) {
     float acc = 0.5f;
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc = fmaf(Y[k], p.sh[((int64_t)k * 3 + ch) * n + i], acc);
+    for (int k = 0; k < K; ++k) acc = fmaf(Y[k], raw.sh[k * 3 + ch], acc);
     P.raw[ch] = acc;
     P.rgb[ch] = fmaxf(acc, 0.0f);
   }
@@ -196,8 +223,10 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
   uint32_t rows = 0, rx = 0, ry = 0;
   float tz = 0.0f;
   if (i < a.n) {
+    Raw<DEG> raw;
+    load_raw<DEG>(a.p, i, a.n, raw);
     Proj P;
-    project_fwd<DEG>(a.p, cam, a.opt, i, a.n, P);
+    project_fwd<DEG>(a.p, raw, cam, a.opt, P);
     tz = P.tz;
     if (P.valid) {
       const bool has_skew = (P.b2x != 0.0f) || (P.b2y != 0.0f);
@@ -414,12 +443,14 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(PreBwdArgs a) {
   float st_uv = 0.0f, st_z = 0.0f;   // densification statistics over the views
   uint32_t st_n = 0;
   const float4* g2 = reinterpret_cast<const float4*>(a.g2d);
+  Raw<DEG> raw;
+  load_raw<DEG>(a.p, i, n, raw);
   for (int v = 0; v < a.n_views; ++v) {
     const int64_t m = (int64_t)v * n + i;
     if (a.tiles[m] == 0) continue;
     const sgs_camera& cam = a.cams[v];
     Proj P;
-    project_fwd<DEG>(a.p, cam, a.opt, i, n, P);
+    project_fwd<DEG>(a.p, raw, cam, a.opt, P);
     if (!P.valid) continue;
     const float4 G0 = g2[m], G1 = g2[M + m], G2 = g2[2 * M + m];
     const float4 G3 = a.enhanced ? g2[3 * M + m] : make_float4(0.f, 0.f, 0.f, 0.f);
