@@ -570,20 +570,27 @@ __device__ __forceinline__ uint32_t block_scan256_total(uint32_t x, uint32_t* ws
 // [o0, o1) = [b*EXT, (b+1)*EXT).  Records in depth order with at least
 // one tile come first (culled ones sort last), so the records that own this
 // range are at most EXT + 1 consecutive entries starting at the record
-// j0 that owns instance o0 (bstart[b], from the offsets kernel).  The block enumerates (record, tile row)
-// items of those records in order, 256 at a time: each thread computes one
-// row's span once, a block scan turns the row counts into instance offsets
-// (a running sum from offs[j0]: records' instances are their rows' in order),
-// and each thread writes the instances of its row that fall in [o0, o1).
+// j0 that owns instance o0 (bstart[b], from the offsets kernel).  They are
+// taken in chunks of 256: each thread gathers one record and sets up its
+// span once, into LDS; then the chunk's (record, tile row) items are
+// enumerated in order, 256 at a time, without global loads: each thread
+// evaluates one row's span, a block scan turns the row counts into instance
+// offsets (a running sum from offs[j0]: records' instances are their rows'
+// in order), and each thread writes the instances of its row that fall in
+// [o0, o1).
 // The digit histograms of the tile-key sort are counted here as well: a
 // row's instances have consecutive tile keys, so the low digit is counted
 // per instance and every higher digit once per run of equal high bits.
 
 template <int EXT>
 __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
-  constexpr int EX_W = EXT + 1;
-  __shared__ uint32_t s_rec[EX_W];
-  __shared__ uint32_t s_rows[EX_W + 1];   // exclusive prefix of the records' rect rows
+  constexpr int NSP = 13;                 // Span words per record
+  __shared__ float s_sp[NSP][256];        // the chunk's records' spans (set up once each)
+  __shared__ uint32_t s_r0[256], s_r1[256];   // rect corners (tx | ty << 16)
+  __shared__ uint32_t s_rec[256];
+  __shared__ uint32_t s_tb[256], s_tx[256];   // view's tile base and tiles per row
+  __shared__ uint32_t s_rows[257];        // exclusive prefix of the chunk's records' rows
+  __shared__ uint32_t s_e[256], s_k0[256], s_irec[256];   // items: output offset, first key, record
   __shared__ uint32_t hist[4][256];
   __shared__ uint32_t ws[4];
   __shared__ uint32_t s_tot, s_j0, s_w;
@@ -602,85 +609,111 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
     // the record that owns instance o0 (marked by the offsets kernel)
     const uint64_t jlo = min((uint64_t)a.bstart[blockIdx.x], (uint64_t)a.m - 1);
     s_j0 = (uint32_t)jlo;
-    s_w = (uint32_t)min((uint64_t)EX_W, (uint64_t)a.m - jlo);
+    s_w = (uint32_t)min((uint64_t)EXT + 1, (uint64_t)a.m - jlo);
   }
   __syncthreads();
-  const uint32_t j0 = s_j0;
-  uint32_t W = s_w;
-  // rows of the window's records (records starting at or past o1: none);
-  // the window ends at the first chunk of 256 records that starts past o1
-  uint32_t carry = 0;
-  for (uint32_t c = 0; c < W; c += 256) {
-    if (c > 0 && a.offs[j0 + c] >= o1) {   // the same value in every thread
-      W = c;
-      break;
-    }
+  const uint32_t j0 = s_j0, W = s_w;
+  uint64_t run = a.offs[j0];    // instance offset of the next item
+  // records in chunks of 256: each thread sets up one record's span (its
+  // loads are the chunk's only dependent gathers), then the chunk's (record,
+  // tile row) items are enumerated from LDS, 256 at a time
+  for (uint32_t c = 0; c < W && run < o1; c += 256) {
     const uint32_t k = c + t;
     uint32_t rows = 0;
     if (k < W) {
       const uint32_t rec = a.order[j0 + k];
-      s_rec[k] = rec;
+      s_rec[t] = rec;
       if ((k == 0 || a.offs[j0 + k] < o1) && rec < (uint64_t)a.m && a.tiles[rec] > 0) {
         const uint2 r = reinterpret_cast<const uint2*>(a.rect)[rec];
         rows = (r.y >> 16) - min(r.x >> 16, r.y >> 16);
+        s_r0[t] = r.x;
+        s_r1[t] = r.y;
+        const float4* rp = a.rec + 4 * (uint64_t)rec;
+        const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2];
+        Span sp;
+        span_setup(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, record_zcut(a, q1), sp);
+        s_sp[0][t] = sp.mx;  s_sp[1][t] = sp.my;  s_sp[2][t] = sp.b;   s_sp[3][t] = sp.det;
+        s_sp[4][t] = sp.ia;  s_sp[5][t] = sp.aR2; s_sp[6][t] = sp.ey;  s_sp[7][t] = sp.ex;
+        s_sp[8][t] = sp.yx;  s_sp[9][t] = sp.bx;  s_sp[10][t] = sp.by; s_sp[11][t] = sp.need;
+        s_sp[12][t] = __uint_as_float((sp.ok ? 1u : 0u) | (sp.cut ? 2u : 0u));
+        const sgs_camera& cam = a.cams[rec / (uint64_t)a.n];
+        s_tb[t] = (uint32_t)cam.tile_base;
+        s_tx[t] = (uint32_t)cam.tiles_x;
       }
     }
     const uint32_t e = block_scan256_total(rows, ws, &s_tot);
-    if (k < W) s_rows[k] = carry + e;
-    carry += s_tot;
+    s_rows[t] = e;
+    if (t == 255) s_rows[256] = e + rows;
     __syncthreads();
-  }
-  if (t == 0) s_rows[W] = carry;
-  __syncthreads();
-  const uint32_t R = carry;
-  uint64_t run = a.offs[j0];    // instance offset of the next item
-  for (uint32_t base = 0; base < R && run < o1; base += 256) {
-    const uint32_t i = base + t;
-    uint32_t cnt = 0, rec = 0, tk = 0;
-    int c0 = 0;
-    if (i < R) {
-      // record of item i: last k with s_rows[k] <= i
-      uint32_t lo = 0, hi = W;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_rows[mid] <= i) lo = mid; else hi = mid;
+    const uint32_t R = s_rows[256];
+    const uint32_t cw = min(256u, W - c);   // records of this chunk
+    for (uint32_t base = 0; base < R && run < o1; base += 256) {
+      const uint32_t i = base + t;
+      uint32_t cnt = 0, rec = 0, tk = 0;
+      int c0 = 0;
+      if (i < R) {
+        // record of item i: last k with s_rows[k] <= i
+        uint32_t lo = 0, hi = cw;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (s_rows[mid] <= i) lo = mid; else hi = mid;
+        }
+        rec = s_rec[lo];
+        Span sp;
+        sp.mx = s_sp[0][lo];  sp.my = s_sp[1][lo];  sp.b = s_sp[2][lo];   sp.det = s_sp[3][lo];
+        sp.ia = s_sp[4][lo];  sp.aR2 = s_sp[5][lo]; sp.ey = s_sp[6][lo];  sp.ex = s_sp[7][lo];
+        sp.yx = s_sp[8][lo];  sp.bx = s_sp[9][lo];  sp.by = s_sp[10][lo]; sp.need = s_sp[11][lo];
+        const uint32_t fl = __float_as_uint(s_sp[12][lo]);
+        sp.ok = (fl & 1u) != 0u;
+        sp.cut = (fl & 2u) != 0u;
+        const uint32_t r0 = s_r0[lo];
+        const int x0 = r0 & 0xffffu, x1 = s_r1[lo] & 0xffffu;
+        const int row = (int)(r0 >> 16) + (int)(i - s_rows[lo]);
+        int c1;
+        span_row(sp, row, a.tile_w, a.tile_h, x0, x1, c0, c1);
+        cnt = (uint32_t)(c1 - c0);
+        tk = s_tb[lo] + (uint32_t)row * s_tx[lo];
       }
-      rec = s_rec[lo];
-      const uint64_t rm = rec < (uint64_t)a.m ? rec : 0;
-      const uint2 r = reinterpret_cast<const uint2*>(a.rect)[rm];
-      const int x0 = r.x & 0xffffu, x1 = r.y & 0xffffu;
-      const int row = (int)(r.x >> 16) + (int)(i - s_rows[lo]);
-      const float4* rp = a.rec + 4 * rm;
-      const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2];
-      Span sp;
-      span_setup(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, record_zcut(a, q1), sp);
-      int c1;
-      span_row(sp, row, a.tile_w, a.tile_h, x0, x1, c0, c1);
-      cnt = (uint32_t)(c1 - c0);
-      const sgs_camera& cam = a.cams[rm / (uint64_t)a.n];
-      tk = (uint32_t)cam.tile_base + (uint32_t)row * (uint32_t)cam.tiles_x;
-    }
-    const uint32_t e = block_scan256_total(cnt, ws, &s_tot);
-    const uint64_t start = run + e;
-    const uint64_t lo = max(start, o0), hi = min(start + cnt, o1);
-    const uint32_t tlo = tk + (uint32_t)c0 + (uint32_t)(lo - start);
-    for (uint64_t o = lo; o < hi; ++o) {
-      const uint32_t key = tlo + (uint32_t)(o - lo);
-      a.keys32[o] = key;
-      a.vals[o] = rec;
-      atomicAdd(&hist[0][key & dmask], 1u);
-    }
-    if (a.hpasses > 1 && hi > lo) {
-      const uint32_t thi = tlo + (uint32_t)(hi - lo);
-      for (uint32_t seg = tlo; seg < thi;) {
-        const uint32_t end = min(thi, (seg | dmask) + 1u);
-        for (int p = 1; p < a.hpasses; ++p)
-          atomicAdd(&hist[p][(seg >> (a.hwidth * p)) & dmask], end - seg);
-        seg = end;
+      const uint32_t e2 = block_scan256_total(cnt, ws, &s_tot);
+      s_e[t] = e2;
+      s_k0[t] = tk + (uint32_t)c0;
+      s_irec[t] = rec;
+      __syncthreads();
+      // the items' instances are one contiguous output range: thread t
+      // writes every 256th of its part in [o0, o1) (coalesced), finding the
+      // item by a search that only moves forward
+      const uint32_t ni = min(256u, R - base);
+      const uint64_t blo = max(run, o0), bhi = min(run + s_tot, o1);
+      uint32_t it = 0;
+      for (uint64_t o = blo + t; o < bhi; o += 256) {
+        const uint32_t rel = (uint32_t)(o - run);
+        uint32_t lo = it, hi = ni;     // last item with s_e <= rel
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (s_e[mid] <= rel) lo = mid; else hi = mid;
+        }
+        it = lo;
+        const uint32_t key = s_k0[lo] + (rel - s_e[lo]);
+        a.keys32[o] = key;
+        a.vals[o] = s_irec[lo];
+        atomicAdd(&hist[0][key & dmask], 1u);
       }
+      // the higher digits once per run of equal high bits of each row
+      const uint64_t start = run + e2;
+      const uint64_t lo2 = max(start, o0), hi2 = min(start + cnt, o1);
+      const uint32_t tlo = tk + (uint32_t)c0 + (uint32_t)(lo2 - start);
+      if (a.hpasses > 1 && hi2 > lo2) {
+        const uint32_t thi = tlo + (uint32_t)(hi2 - lo2);
+        for (uint32_t seg = tlo; seg < thi;) {
+          const uint32_t end = min(thi, (seg | dmask) + 1u);
+          for (int p = 1; p < a.hpasses; ++p)
+            atomicAdd(&hist[p][(seg >> (a.hwidth * p)) & dmask], end - seg);
+          seg = end;
+        }
+      }
+      run += s_tot;
+      __syncthreads();
     }
-    run += s_tot;
-    __syncthreads();
   }
   if (a.cnt0) a.cnt0[(uint64_t)blockIdx.x * 256 + t] = hist[0][t];
   uint32_t* hdst = a.hpart + (size_t)(blockIdx.x % (unsigned)a.hcopies) * a.hpasses * 256;
