@@ -440,7 +440,8 @@ template <int TW, int TH, int B, bool ENH>
 struct BwdShared {
   static constexpr int NG = ENH ? 15 : 11;   // values per record: see the flush below
   Stage<TW, TH, B, ENH> S;
-  float sg[NG][B];
+  static constexpr int SGW = B + 1;         // row stride: a record's slots in distinct banks
+  float sg[NG][SGW];
   uint32_t smax;
 };
 
@@ -520,7 +521,7 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
     const int cnt = end - start;
     __syncthreads();
     stage_batch<TW, TH, B, ENH>(a, ts, rg.x + start, cnt, S);
-    for (int k = t; k < NG * B; k += NT) (&sg[0][0])[k] = 0.0f;
+    for (int k = t; k < NG * (B + 1); k += NT) (&sg[0][0])[k] = 0.0f;
     __syncthreads();
     const int nw = __builtin_amdgcn_readfirstlane(S.n[w]);   // wave-uniform
     for (int i = nw - 1; i >= 0; --i) {
@@ -593,13 +594,12 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
         }
       }
       if (__ballot(hit)) {
-        // sums over each 16-lane row (DPP), then one LDS atomic per row: the
+        // transposing sum over each 16-lane row (DPP): lane l of a row ends
+        // with the row's sum of value l, then one LDS atomic per lane; the
         // VALU is this kernel's bound, the LDS pipe has room
-#pragma unroll
-        for (int q = 0; q < NG; ++q) {
-          const float s = row_sum16(gv[q]);
-          if ((lane & 15) == 0 && s != 0.0f) atomicAdd(&sg[q][j], s);
-        }
+        const float s = row_transpose_sum<NG>(gv, lane);
+        const int q = lane & 15;
+        if (q < NG && s != 0.0f) atomicAdd(&sg[q][j], s);
       }
     }
     __syncthreads();
@@ -657,7 +657,7 @@ __device__ __forceinline__ void bwd_quad(const BlendArgs& a, int tile, int quart
     const int cnt = end - start;
     __syncthreads();
     stage_batch<16, 16, B, ENH, 4>(a, ts, rg.x + start, cnt, S);
-    for (int k = t; k < NG * B; k += NT) (&sg[0][0])[k] = 0.0f;
+    for (int k = t; k < NG * (B + 1); k += NT) (&sg[0][0])[k] = 0.0f;
     __syncthreads();
     const int nw = __builtin_amdgcn_readfirstlane(S.n[w]);   // wave-uniform
     for (int i = nw - 1; i >= 0; i -= 4) {

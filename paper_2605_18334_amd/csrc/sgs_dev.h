@@ -237,14 +237,31 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
-// Sum over each 16-lane row of the wave; every lane of a row gets its row's
-// sum.  All 64 lanes must be active.
-__device__ __forceinline__ float row_sum16(float v) {
-  v += dpp_src<0xB1>(v);          // quad_perm [1,0,3,2]
-  v += dpp_src<0x4E>(v);          // quad_perm [2,3,0,1]
-  v += dpp_src<0x141>(v);         // row_half_mirror
-  v += dpp_src<0x140>(v);         // row_mirror
-  return v;
+// Transposing sum over each 16-lane row of N <= 16 values per lane (missing
+// values are 0): afterwards lane l of a row holds the row's sum of value
+// l & 15.  Four butterfly steps halve the values per lane; at step h a lane
+// keeps the half selected by its lane bit h and adds the partner's copy of
+// that half, the partner being the lane DPP pairs it with (row mirror, half
+// mirror, quad reversal, quad swap), which has the other bit h and holds the
+// same set of values.  All 64 lanes must be active.
+template <int N>
+__device__ __forceinline__ float row_transpose_sum(const float (&g)[N], int lane) {
+  static_assert(N <= 16, "at most 16 values per lane");
+  float v16[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v16[k] = k < N ? g[k] : 0.0f;
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+  float v8[8], v4[4], v2[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    v8[k] = (b3 ? v16[k + 8] : v16[k]) + dpp_src<0x140>(b3 ? v16[k] : v16[k + 8]);   // row_mirror
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    v4[k] = (b2 ? v8[k + 4] : v8[k]) + dpp_src<0x141>(b2 ? v8[k] : v8[k + 4]);       // row_half_mirror
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    v2[k] = (b1 ? v4[k + 2] : v4[k]) + dpp_src<0x1B>(b1 ? v4[k] : v4[k + 2]);        // quad_perm [3,2,1,0]
+  return (b0 ? v2[1] : v2[0]) + dpp_src<0xB1>(b0 ? v2[0] : v2[1]);                   // quad_perm [1,0,3,2]
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
