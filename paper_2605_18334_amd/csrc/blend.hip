@@ -290,7 +290,9 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
         at *= enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
       }
       const float alpha = fminf(a.alpha_max, at);
-      const bool take = in && alpha >= a.alpha_min;
+      // the skip test again rather than `in`: a bool kept across the branch
+      // above costs two VALU instructions to rebuild as a lane mask
+      const bool take = !done && l2 >= r2.w && alpha >= a.alpha_min;
       const float Tn = T * (1.0f - alpha);
       const bool stop = take && Tn < a.t_min;
       if (take && !stop) {
