@@ -72,17 +72,23 @@ def sh_bytes(deg: int) -> int:
 
 
 def timed_forward(R, steps: int, warmup: int):
+    """Warm-up (W frames, then at least 0.3 s of frames so that clocks have
+    settled), a per-stage breakdown in a loop of its own (events between the
+    stages), then the timed region: exactly `steps` whole frames between two
+    synchronisations, with events around each blend launch only (its
+    duration for the roofline; events between every stage would add ~5% to
+    the step)."""
     import torch
     for _ in range(warmup):
         R.forward()
     torch.cuda.synchronize()
+    t_w = time.perf_counter()
+    while time.perf_counter() - t_w < 0.3:
+        for _ in range(10):
+            R.forward()
+        torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
-    t0 = time.perf_counter()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for k in range(steps):
-        e = ev[k]
+    for e in ev:
         e[0].record()
         R.preprocess()
         e[1].record()
@@ -90,16 +96,27 @@ def timed_forward(R, steps: int, warmup: int):
         e[2].record()
         R.blend()
         e[3].record()
+    torch.cuda.synchronize()
+    stages = {"preprocess": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
+              "bin_sort": float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
+              "blend_fwd": float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))}
+    bl = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for b in bl:
+        R.preprocess()
+        R.bin_sort()
+        b[0].record()
+        R.blend()
+        b[1].record()
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    total_ms = start.elapsed_time(end)
-    st = {"preprocess": [], "bin_sort": [], "blend_fwd": []}
-    for e in ev:
-        st["preprocess"].append(e[0].elapsed_time(e[1]))
-        st["bin_sort"].append(e[1].elapsed_time(e[2]))
-        st["blend_fwd"].append(e[2].elapsed_time(e[3]))
-    return total_ms / steps, wall, {k: float(np.mean(v)) for k, v in st.items()}
+    blend_ms = float(np.mean([b[0].elapsed_time(b[1]) for b in bl]))
+    return start.elapsed_time(end) / steps, wall, stages, blend_ms
 
 
 def cpu_baseline(sc, pose, target_s: float):
@@ -146,23 +163,25 @@ def fwd_bwd(steps: int, warmup: int):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    fwd_ms, bwd_ms = [], []
+    # steps back to back (a training loop does not wait per step); events at
+    # the step boundaries give the forward / backward split
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for e in ev:
         e[0].record()
         out = R.forward()
         e[1].record()
         dL = torch.sign(out - target).mul_(1.0 / npx)
         R.backward(dL)
         e[2].record()
-        torch.cuda.synchronize()
-        fwd_ms.append(e[0].elapsed_time(e[1]))
-        bwd_ms.append(e[1].elapsed_time(e[2]))
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gpu_ms = ev[0][0].elapsed_time(ev[-1][2])
     assert not R.overflowed()
-    return {"metric": "fwd+bwd iters/s at 1M Gaussians", "value": steps / wall, "unit": "iters/s",
-            "ms_fwd": float(np.mean(fwd_ms)), "ms_bwd": float(np.mean(bwd_ms)),
+    return {"metric": "fwd+bwd iters/s at 1M Gaussians", "value": steps / (gpu_ms / 1e3), "unit": "iters/s",
+            "wall_iters_s": steps / wall,
+            "ms_fwd": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
+            "ms_bwd": float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
             "n_inst": R.n_inst(),
             "config": {"workload": "1M skew Gaussians (4-blob generator, SH0), one 1600x1064 view, "
                                    "L1 loss vs a separately seeded 1M target"}}
@@ -264,8 +283,8 @@ def serving(duration_s: float, rates):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -309,7 +328,7 @@ def main():
     gs = P.GaussianSet.from_scene(sc)
     cams = P.CameraBatch.from_poses([pose], opt)
     R = P.Renderer(gs, cams, opt, count=True)
-    ms, wall, stages = timed_forward(R, args.steps, args.warmup)
+    ms, wall, stages, blend_ms = timed_forward(R, args.steps, args.warmup)
     assert not R.overflowed()
     n_inst = R.n_inst()
     pairs = int(R.bufs["count"].to(torch.int64).sum().item())
@@ -319,7 +338,7 @@ def main():
 
     # roofline of the dominant kernel: the blend forward is the longest single
     # launch (bin/sort is a dozen kernels, each far shorter; see profiles/)
-    achieved = pairs * FLOPS_PER_PAIR / (stages["blend_fwd"] / 1e3) / 1e12
+    achieved = pairs * FLOPS_PER_PAIR / (blend_ms / 1e3) / 1e12
     roof = {"kernel": "k_blend_fwd", "bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
             "traffic": measured_traffic("k_blend_fwd"),
