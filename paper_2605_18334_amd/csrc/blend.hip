@@ -17,8 +17,10 @@
 // contributor to the front, rebuilding T_k = T_{k+1} / (1 - alpha_k) from the
 // final transmittance (nothing per pair is stored), with the colour behind k
 // kept as a running sum.  Per-pair partial derivatives are summed over each
-// 16-lane row with DPP, over rows and waves with LDS atomics, and written
-// with one set of global atomics per (record, tile).
+// 16-lane row with a transposing DPP sum (afterwards each lane holds one of
+// the record's row sums), over rows and waves with LDS atomics, and written
+// with one set of global atomics per (record, tile).  Pairs are evaluated in
+// base 2 from per-record constants folded in when a batch is staged.
 #include <algorithm>
 
 #include "sgs_dev.h"
