@@ -534,77 +534,74 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
       const uint32_t e = S.list[w][i];
       const int j = (int)(e & LIST_SLOT);
       const bool skew = ((uint32_t)__builtin_amdgcn_readfirstlane((int)e) & LIST_SKEW) != 0u;
+      const float4 r0 = S.r0[j];
+      const float4 r1 = S.r1[j];
+      const float4 r2 = S.r2[j];
+      const float dx = fx - r0.x, dy = fy - r0.y;
+      const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
+      const bool in = (uint32_t)(start + j) < last && l2 >= r2.w;
+      if (!__any(in)) continue;
+      // from here on every lane computes; lanes without a contribution get
+      // zero weights through selects (nested branches made the compiler
+      // re-zero all gradient registers on every path)
+      Pair2 p;
+      pair_eval2(l2, r1.y, r1.z, dx, dy, skew, p);
+      float at = p.at, o = 1.0f, eu = 0.0f, ee = 1.0f;
+      float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (ENH) {
+        r3 = S.r3[j];
+        o = enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
+        at *= o;
+      }
+      const float alpha = fminf(a.alpha_max, at);
+      const bool hit = in && alpha >= a.alpha_min;
+      if (!__any(hit)) continue;
+      const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+      const float Tn = T * inv;                 // transmittance in front of this pair
+      T = hit ? Tn : T;
+      const float wgt = hit ? alpha * Tn : 0.0f;
+      const bool unc = hit && at <= a.alpha_max;   // alpha not clamped: gradients reach it
+      const float dLda = unc ? ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) * Tn -
+                                   Tfinal * inv * bgdot
+                             : 0.0f;
+      const float ath = unc ? at : 0.0f;
+      // common = dL/dalpha d o G'; (qa, qc) = Q delta and beta from the
+      // staged base-2 constants
+      const float common = unc ? dLda * o * p.dG : 0.0f;
+      const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
+      const float qa = -SGS_LN2 * fmaf(2.0f * r0.z, dx, r0.w * dy);
+      const float qc = -SGS_LN2 * fmaf(r0.w, dx, 2.0f * r1.x * dy);
       float gv[NG];
-#pragma unroll
-      for (int q = 0; q < NG; ++q) gv[q] = 0.0f;
-      bool hit = false;
-      if ((uint32_t)(start + j) < last) {
-        const float4 r0 = S.r0[j];
-        const float4 r1 = S.r1[j];
-        const float dx = fx - r0.x, dy = fy - r0.y;
-        const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
-        const float4 r2 = S.r2[j];
-        if (l2 >= r2.w) {
-          Pair2 p;
-          pair_eval2(l2, r1.y, r1.z, dx, dy, skew, p);
-          float at = p.at, o = 1.0f, eu = 0.0f, ee = 1.0f;
-          float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (ENH) {
-            r3 = S.r3[j];
-            o = enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
-            at *= o;
-          }
-          const float alpha = fminf(a.alpha_max, at);
-          if (alpha >= a.alpha_min) {
-            hit = true;
-            const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-            T = T * inv;                      // transmittance in front of this pair
-            const float wgt = alpha * T;
-            gv[8] = wgt * g0;
-            gv[9] = wgt * g1;
-            gv[10] = wgt * g2;
-            float dLda = ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) * T;
-            dLda -= Tfinal * inv * bgdot;
-            if (at <= a.alpha_max) {
-              // common = dL/dalpha d o G'; (qa, qc) = Q delta and beta from
-              // the staged base-2 constants
-              const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
-              const float common = dLda * o * p.dG;
-              const float qa = -SGS_LN2 * fmaf(2.0f * r0.z, dx, r0.w * dy);
-              const float qc = -SGS_LN2 * fmaf(r0.w, dx, 2.0f * r1.x * dy);
-              gv[0] = common * (qa * p.E - s2pi * (SGS_IKZ * r1.y));
-              gv[1] = common * (qc * p.E - s2pi * (SGS_IKZ * r1.z));
-              gv[2] = -0.5f * dx * dx * dLda * at;
-              gv[3] = -dx * dy * dLda * at;
-              gv[4] = -0.5f * dy * dy * dLda * at;
-              gv[5] = common * s2pi * dx;
-              gv[6] = common * s2pi * dy;
-              gv[7] = common * p.E * S.idv[j];
-              if (ENH) {
-                const float base = p.at;             // rho G' (1 + erf z)
-                const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
-                gv[0] -= dLda * base * dodw * r3.z;
-                gv[1] -= dLda * base * dodw * r3.w;
-                gv[11] = dLda * base * 0.5f * (1.0f + eu);
-                gv[12] = dLda * base * 0.5f * (1.0f - eu);
-                gv[13] = dLda * base * dodw * dx;
-                gv[14] = dLda * base * dodw * dy;
-              }
-            }
-            S0 = fmaf(alpha, r2.x - S0, S0);
-            S1 = fmaf(alpha, r2.y - S1, S1);
-            S2 = fmaf(alpha, r2.z - S2, S2);
-          }
-        }
+      gv[0] = common * (qa * p.E - s2pi * (SGS_IKZ * r1.y));
+      gv[1] = common * (qc * p.E - s2pi * (SGS_IKZ * r1.z));
+      gv[2] = -0.5f * dx * dx * dLda * ath;
+      gv[3] = -dx * dy * dLda * ath;
+      gv[4] = -0.5f * dy * dy * dLda * ath;
+      gv[5] = common * s2pi * dx;
+      gv[6] = common * s2pi * dy;
+      gv[7] = common * p.E * S.idv[j];
+      gv[8] = wgt * g0;
+      gv[9] = wgt * g1;
+      gv[10] = wgt * g2;
+      if constexpr (ENH) {
+        const float base = unc ? p.at : 0.0f;        // rho G' (1 + erf z)
+        const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
+        gv[0] -= dLda * base * dodw * r3.z;
+        gv[1] -= dLda * base * dodw * r3.w;
+        gv[11] = dLda * base * 0.5f * (1.0f + eu);
+        gv[12] = dLda * base * 0.5f * (1.0f - eu);
+        gv[13] = dLda * base * dodw * dx;
+        gv[14] = dLda * base * dodw * dy;
       }
-      if (__ballot(hit)) {
-        // transposing sum over each 16-lane row (DPP): lane l of a row ends
-        // with the row's sum of value l, then one LDS atomic per lane; the
-        // VALU is this kernel's bound, the LDS pipe has room
-        const float s = row_transpose_sum<NG>(gv, lane);
-        const int q = lane & 15;
-        if (q < NG && s != 0.0f) atomicAdd(&sg[q][j], s);
-      }
+      S0 = hit ? fmaf(alpha, r2.x - S0, S0) : S0;
+      S1 = hit ? fmaf(alpha, r2.y - S1, S1) : S1;
+      S2 = hit ? fmaf(alpha, r2.z - S2, S2) : S2;
+      // transposing sum over each 16-lane row (DPP): lane l of a row ends
+      // with the row's sum of value l, then one LDS atomic per lane; the
+      // VALU is this kernel's bound, the LDS pipe has room
+      const float sv = row_transpose_sum<NG>(gv, lane);
+      const int q = lane & 15;
+      if (q < NG && sv != 0.0f) atomicAdd(&sg[q][j], sv);
     }
     __syncthreads();
     flush_batch<TW, TH, B, ENH>(a, cnt, X);
