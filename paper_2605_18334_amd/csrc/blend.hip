@@ -713,47 +713,48 @@ __device__ __forceinline__ void bwd_quad(const BlendArgs& a, int tile, int quart
       SGS_QUAD_BACK(2)
       SGS_QUAD_BACK(3)
 #undef SGS_QUAD_BACK
+      // every lane computes; lanes without a contribution get zero weights
+      // through selects (no nested branches around the gradient registers)
+      const float wgt = hit ? alpha * Tm : 0.0f;
+      const bool unc = hit && at <= a.alpha_max;   // alpha not clamped: gradients reach it
+      const float dLda = unc ? ((r2.x - Sm0) * g0 + (r2.y - Sm1) * g1 + (r2.z - Sm2) * g2) * Tm -
+                                   Tfinal * __builtin_amdgcn_rcpf(1.0f - alpha) * bgdot
+                             : 0.0f;
+      const float ath = unc ? at : 0.0f;
+      const float common = unc ? dLda * o * p.dG : 0.0f;
+      const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
+      const float qa = -SGS_LN2 * fmaf(2.0f * r0.z, dx, r0.w * dy);
+      const float qc = -SGS_LN2 * fmaf(r0.w, dx, 2.0f * r1.x * dy);
       float gv[NG];
-#pragma unroll
-      for (int q = 0; q < NG; ++q) gv[q] = 0.0f;
-      if (hit) {
-        const float wgt = alpha * Tm;
-        gv[8] = wgt * g0;
-        gv[9] = wgt * g1;
-        gv[10] = wgt * g2;
-        float dLda = ((r2.x - Sm0) * g0 + (r2.y - Sm1) * g1 + (r2.z - Sm2) * g2) * Tm;
-        dLda -= Tfinal * __builtin_amdgcn_rcpf(1.0f - alpha) * bgdot;
-        if (at <= a.alpha_max) {
-          const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
-          const float common = dLda * o * p.dG;
-          const float qa = -SGS_LN2 * fmaf(2.0f * r0.z, dx, r0.w * dy);
-          const float qc = -SGS_LN2 * fmaf(r0.w, dx, 2.0f * r1.x * dy);
-          gv[0] = common * (qa * p.E - s2pi * (SGS_IKZ * r1.y));
-          gv[1] = common * (qc * p.E - s2pi * (SGS_IKZ * r1.z));
-          gv[2] = -0.5f * dx * dx * dLda * at;
-          gv[3] = -dx * dy * dLda * at;
-          gv[4] = -0.5f * dy * dy * dLda * at;
-          gv[5] = common * s2pi * dx;
-          gv[6] = common * s2pi * dy;
-          gv[7] = common * p.E * S.idv[j];
-          if (ENH) {
-            const float base = p.at;
-            const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
-            gv[0] -= dLda * base * dodw * r3.z;
-            gv[1] -= dLda * base * dodw * r3.w;
-            gv[11] = dLda * base * 0.5f * (1.0f + eu);
-            gv[12] = dLda * base * 0.5f * (1.0f - eu);
-            gv[13] = dLda * base * dodw * dx;
-            gv[14] = dLda * base * dodw * dy;
-          }
-        }
+      gv[0] = common * (qa * p.E - s2pi * (SGS_IKZ * r1.y));
+      gv[1] = common * (qc * p.E - s2pi * (SGS_IKZ * r1.z));
+      gv[2] = -0.5f * dx * dx * dLda * ath;
+      gv[3] = -dx * dy * dLda * ath;
+      gv[4] = -0.5f * dy * dy * dLda * ath;
+      gv[5] = common * s2pi * dx;
+      gv[6] = common * s2pi * dy;
+      gv[7] = common * p.E * S.idv[j];
+      gv[8] = wgt * g0;
+      gv[9] = wgt * g1;
+      gv[10] = wgt * g2;
+      if constexpr (ENH) {
+        const float base = unc ? p.at : 0.0f;
+        const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
+        gv[0] -= dLda * base * dodw * r3.z;
+        gv[1] -= dLda * base * dodw * r3.w;
+        gv[11] = dLda * base * 0.5f * (1.0f + eu);
+        gv[12] = dLda * base * 0.5f * (1.0f - eu);
+        gv[13] = dLda * base * dodw * dx;
+        gv[14] = dLda * base * dodw * dy;
       }
-      // sums over the 16 pixels of each sublane; lanes 0..3 hold sublanes 0..3
+      // sums over the 16 pixels of each sublane (lanes equal mod 4): within
+      // a row by DPP row rotations by 4 and 8, across rows by shuffles;
+      // lanes 0..3 hold sublanes 0..3
 #pragma unroll
       for (int q = 0; q < NG; ++q) {
         float v = gv[q];
-        v += __shfl_xor(v, 4);
-        v += __shfl_xor(v, 8);
+        v += dpp_src<0x124>(v);   // row_ror:4
+        v += dpp_src<0x128>(v);   // row_ror:8
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
         if (lane < 4 && has && v != 0.0f) atomicAdd(&sg[q][j], v);
