@@ -591,6 +591,7 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
   __shared__ uint32_t s_tb[256], s_tx[256];   // view's tile base and tiles per row
   __shared__ uint32_t s_rows[257];        // exclusive prefix of the chunk's records' rows
   __shared__ uint32_t s_e[256], s_k0[256], s_irec[256];   // items: output offset, first key, record
+  __shared__ uint16_t s_map[EXT];         // item of each output of a round (block-relative)
   __shared__ uint32_t hist[4][256];
   __shared__ uint32_t ws[4];
   __shared__ uint32_t s_tot, s_j0, s_w;
@@ -678,29 +679,27 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
       s_e[t] = e2;
       s_k0[t] = tk + (uint32_t)c0;
       s_irec[t] = rec;
-      __syncthreads();
-      // the items' instances are one contiguous output range: thread t
-      // writes every 256th of its part in [o0, o1) (coalesced), finding the
-      // item by a search that only moves forward
-      const uint32_t ni = min(256u, R - base);
+      // the items' instances are one contiguous output range; its part in
+      // [o0, o1) is [blo, bhi): each item marks its outputs there with its
+      // index, then thread t writes every 256th output (coalesced)
       const uint64_t blo = max(run, o0), bhi = min(run + s_tot, o1);
-      uint32_t it = 0;
-      for (uint64_t o = blo + t; o < bhi; o += 256) {
-        const uint32_t rel = (uint32_t)(o - run);
-        uint32_t lo = it, hi = ni;     // last item with s_e <= rel
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (s_e[mid] <= rel) lo = mid; else hi = mid;
-        }
-        it = lo;
-        const uint32_t key = s_k0[lo] + (rel - s_e[lo]);
-        a.keys32[o] = key;
-        a.vals[o] = s_irec[lo];
+      const uint64_t start = run + e2;
+      const uint64_t lo2 = max(start, o0), hi2 = min(start + cnt, o1);
+      if (hi2 > lo2)   // (blo <= lo2 < hi2 <= bhi, bhi - blo <= EXT)
+        for (uint32_t r = (uint32_t)(lo2 - blo), rend = (uint32_t)(hi2 - blo); r < rend; ++r)
+          s_map[r] = (uint16_t)t;
+      __syncthreads();
+      const uint32_t nout = bhi > blo ? (uint32_t)(bhi - blo) : 0u, rbase = (uint32_t)(blo - run);
+      uint32_t* __restrict__ kb = a.keys32 + blo;
+      uint32_t* __restrict__ vb = a.vals + blo;
+      for (uint32_t r = t; r < nout; r += 256) {
+        const uint32_t it = s_map[r];
+        const uint32_t key = s_k0[it] + (rbase + r - s_e[it]);
+        kb[r] = key;
+        vb[r] = s_irec[it];
         atomicAdd(&hist[0][key & dmask], 1u);
       }
       // the higher digits once per run of equal high bits of each row
-      const uint64_t start = run + e2;
-      const uint64_t lo2 = max(start, o0), hi2 = min(start + cnt, o1);
       const uint32_t tlo = tk + (uint32_t)c0 + (uint32_t)(lo2 - start);
       if (a.hpasses > 1 && hi2 > lo2) {
         const uint32_t thi = tlo + (uint32_t)(hi2 - lo2);
