@@ -40,15 +40,15 @@ constexpr int RS_T = 256;          // threads per block
 // from 0.3M to 50M keys: fewer, longer blocks keep look-back chains short
 // (4 doubled the time of a pass over 1M keys).
 constexpr int RS_IPT = 16;
-// Instances per expansion block: EX_TILE for large capacities (a pass block
-// covers RS_TILE / EX_TILE of them), EX_TILE_S up to EX_SMALL_CAP, where the
-// blocks' serial chains of dependent loads would otherwise leave most of the
-// chip idle.  A block spans at most its tile + 1 records.
-constexpr int EX_TILE = 2048;
+// Instances per expansion block: EX_TILE for large capacities (one pass
+// block's worth, measured best at 52M instances against 1024 and 2048),
+// EX_TILE_S up to EX_SMALL_CAP, where fewer, longer blocks would leave most
+// of the chip idle.  A block spans at most its tile + 1 records.
+constexpr int EX_TILE = 4096;
 constexpr int EX_TILE_S = 512;
 constexpr uint64_t EX_SMALL_CAP = (uint64_t)EX_TILE * EX_TILE;
-static inline int ex_shift_for(uint64_t cap) { return cap <= EX_SMALL_CAP ? 9 : 11; }
-static_assert((1 << 9) == EX_TILE_S && (1 << 11) == EX_TILE, "expansion tile shifts");
+static inline int ex_shift_for(uint64_t cap) { return cap <= EX_SMALL_CAP ? 9 : 12; }
+static_assert((1 << 9) == EX_TILE_S && (1 << 12) == EX_TILE, "expansion tile shifts");
 constexpr int EC = 64;             // expansion blocks per chunk of the count scan
 // pass blocks: 1024 threads for sorts of at most this many blocks (their
 // time is one block's latency), 512 for larger ones (measured: 256 threads
@@ -324,6 +324,7 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
   // look back for the prefix over the blocks before this one
   if (t < 256 && pre) {
     // offsets of this block's keys within each digit were scanned beforehand
+    static_assert(RS_TILE % EX_TILE == 0, "a pass block covers whole expansion blocks");
     const uint64_t e = (uint64_t)b * (RS_TILE / EX_TILE);
     goff[t] = ds + pre[e * 256 + t] + pre_tot[(e / EC) * 256 + t];
   } else if (t < 256 && (b == 0 || !has_digit)) {

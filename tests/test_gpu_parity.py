@@ -159,10 +159,10 @@ def test_sort_modes_agree_on_large_multiview_input():
 def test_large_capacity_sort_is_identical(views, capacity):
     """Unused capacity is a long empty tail of the sort.  One view (about 2M
     instances) runs 512-instance expansion blocks both ways; three views
-    (about 5.7M) run 2048-instance blocks, and the larger capacity (above
-    4096 radix tiles of 4096 keys) takes first-pass offsets from scanned
-    expansion counts instead of a look-back.  Keys, values, ranges and the
-    images equal the exact-capacity run."""
+    (about 5.7M) run them at the exact capacity, and at the larger capacity
+    (above 4096 radix tiles of 4096 keys) 4096-instance blocks whose scanned
+    first-digit counts replace the first pass's look-back.  Keys, values,
+    ranges and the images equal the exact-capacity run."""
     sc = S.blobs_scene(21, 60_000, 0)
     poses = S.spline_poses(3, 3)[:views]
     a = _render(sc, poses, sort_mode=1)
