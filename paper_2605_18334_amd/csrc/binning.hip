@@ -45,10 +45,10 @@ constexpr int RS_IPT = 16;
 // EX_TILE_S up to EX_SMALL_CAP, where fewer, longer blocks would leave most
 // of the chip idle.  A block spans at most its tile + 1 records.
 constexpr int EX_TILE = 4096;
-constexpr int EX_TILE_S = 512;
+constexpr int EX_TILE_S = 1024;
 constexpr uint64_t EX_SMALL_CAP = (uint64_t)EX_TILE * EX_TILE;
-static inline int ex_shift_for(uint64_t cap) { return cap <= EX_SMALL_CAP ? 9 : 12; }
-static_assert((1 << 9) == EX_TILE_S && (1 << 12) == EX_TILE, "expansion tile shifts");
+static inline int ex_shift_for(uint64_t cap) { return cap <= EX_SMALL_CAP ? 10 : 12; }
+static_assert((1 << 10) == EX_TILE_S && (1 << 12) == EX_TILE, "expansion tile shifts");
 constexpr int EC = 64;             // expansion blocks per chunk of the count scan
 // pass blocks: 1024 threads for sorts of at most this many blocks (their
 // time is one block's latency), 512 for larger ones (measured: 256 threads
@@ -1094,7 +1094,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   a.hpasses = passes;
   a.hwidth = rs_width(tb);
   if (cap > 0) {
-    if (ex_shift == 9)
+    if (ex_shift == 10)
       k_expand32<EX_TILE_S><<<(unsigned)ex_blocks, 256, 0, s>>>(a);
     else
       k_expand32<EX_TILE><<<(unsigned)ex_blocks, 256, 0, s>>>(a);

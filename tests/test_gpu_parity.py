@@ -158,7 +158,7 @@ def test_sort_modes_agree_on_large_multiview_input():
 @pytest.mark.parametrize("views,capacity", [(1, 2048 * 2048), (3, 4096 * 4096 + 12_345)])
 def test_large_capacity_sort_is_identical(views, capacity):
     """Unused capacity is a long empty tail of the sort.  One view (about 2M
-    instances) runs 512-instance expansion blocks both ways; three views
+    instances) runs 1024-instance expansion blocks both ways; three views
     (about 5.7M) run them at the exact capacity, and at the larger capacity
     (above 4096 radix tiles of 4096 keys) 4096-instance blocks whose scanned
     first-digit counts replace the first pass's look-back.  Keys, values,
