@@ -132,7 +132,8 @@ typedef struct {
                               sort; 1: stable depth presort of the records,
                               duplicate in depth order, LSD sort of 32-bit
                               tile keys.  Both give the identical order.    */
-  int32_t blend_batch;     /* [256] records staged in LDS per batch: 64, 128, 256 */
+  int32_t blend_batch;     /* [0] records staged in LDS per batch: 64, 128, 256; 0: 128 in the
+                              forward blend, 256 in the backward */
   int32_t split_tiles;     /* [-1] with 16x16 tiles and a tile order (and no
                               work counter): both blends run the first
                               split_tiles tiles of the order (the longest

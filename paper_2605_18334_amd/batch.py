@@ -120,6 +120,8 @@ DEFAULT_CANDIDATES = [
     LaunchConfig(16, 8, 128, 1, True, False, 4),
     LaunchConfig(8, 8, 64, 1, True, False, 4),
     LaunchConfig(16, 16, 256, 1, True, False, 8),
+    LaunchConfig(16, 16, 0, 1, True, False, 4),
+    LaunchConfig(16, 16, 128, 1, True, False, 4),
     LaunchConfig(16, 16, 256, 1, True, False, 4),
 ]
 

@@ -34,7 +34,8 @@ bool options_ok(const sgs_options* o) {
   if (!o) return false;
   const bool tile = (o->tile_w == 16 && o->tile_h == 16) || (o->tile_w == 16 && o->tile_h == 8) ||
                     (o->tile_w == 8 && o->tile_h == 8);
-  const bool batch = o->blend_batch == 64 || o->blend_batch == 128 || o->blend_batch == 256;
+  const bool batch = o->blend_batch == 0 || o->blend_batch == 64 || o->blend_batch == 128 ||
+                     o->blend_batch == 256;
   return tile && batch && isfinite(o->filter_s) && o->filter_s >= 0.0f && isfinite(o->guard) &&
          o->guard > 0.0f && o->alpha_min > 0.0f && o->alpha_min < o->alpha_max &&
          o->alpha_max < 1.0f && o->t_min > 0.0f && o->t_min < 1.0f &&
@@ -88,7 +89,7 @@ void sgs_default_options(sgs_options* o) {
   o->alpha_max = 0.99f;
   o->t_min = 1e-4f;
   o->sort_mode = 1;
-  o->blend_batch = 256;
+  o->blend_batch = 0;
   o->split_tiles = -1;
 }
 

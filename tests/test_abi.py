@@ -45,7 +45,7 @@ def test_struct_sizes_match_binding():
 def test_default_options_and_status_strings():
     _abi, lib = _lib()
     o = _abi.default_options()
-    assert (o.tile_w, o.tile_h, o.blend_batch, o.sort_mode, o.compensate) == (16, 16, 256, 1, 1)
+    assert (o.tile_w, o.tile_h, o.blend_batch, o.sort_mode, o.compensate) == (16, 16, 0, 1, 1)
     assert o.split_tiles == -1
     assert o.alpha_min == pytest.approx(1 / 255) and o.alpha_max == pytest.approx(0.99)
     assert o.t_min == pytest.approx(1e-4) and o.filter_s == pytest.approx(0.3)
