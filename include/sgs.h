@@ -141,7 +141,7 @@ typedef struct {
                               pixel evaluating four records at once; same
                               images (gradients up to the order of float
                               sums), more parallelism per tile.  -1:
-                              total_tiles / 32; 0: off.                     */
+                              total_tiles / 128; 0: off.                    */
 } sgs_options;
 
 /* Projected per-record data written by sgs_preprocess, record m = v*N + i for

@@ -873,7 +873,7 @@ static unsigned blend_grid(int64_t total_tiles) { return (unsigned)((total_tiles
 // n_quad tiles of the order get four workgroups each, ahead of the others.
 static void split_setup(BlendArgs& a, const sgs_options* opt, int64_t total_tiles, unsigned& grid) {
   if (a.tile_order && !a.work_counter && opt->tile_w == 16 && opt->tile_h == 16 && opt->split_tiles != 0) {
-    const int64_t q = opt->split_tiles < 0 ? total_tiles / 32 : std::min<int64_t>(opt->split_tiles, total_tiles);
+    const int64_t q = opt->split_tiles < 0 ? total_tiles / 128 : std::min<int64_t>(opt->split_tiles, total_tiles);
     a.n_quad = (int32_t)q;
     grid += 3u * (unsigned)q;
   }
