@@ -212,6 +212,8 @@ template <int DEG>
 __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
   __shared__ uint32_t s_pref[4][65];   // per wave: exclusive prefix of the records' rows
   __shared__ uint32_t s_cnt[256];
+  __shared__ float4 s_span[4][64][4];  // per wave and lane: the record's Span and tile rect
+  __shared__ uint32_t s_mark[4][64];   // per wave: owner marks of the current row window
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int v = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * 256 + t;
@@ -271,43 +273,42 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
     }
   }
   // tiles of each rect that the evaluation ellipse (cut by the skew
-  // half-plane) reaches, row by row, per wave
+  // half-plane) reaches, row by row, per wave: the wave's (record, row)
+  // items are spread over its lanes 64 at a time; each record's span and
+  // rect sit in LDS, and an item finds its record by a max-scan of marks
+  // (each record overlapping the window marks its first item there)
   const uint32_t incl = wave_incl_scan(rows);
-  s_pref[w][lane] = incl - rows;
+  const uint32_t first = incl - rows;
+  s_pref[w][lane] = first;
   if (lane == 63) s_pref[w][64] = incl;
   s_cnt[t] = 0;
+  s_span[w][lane][0] = make_float4(sp.mx, sp.my, sp.b, sp.det);
+  s_span[w][lane][1] = make_float4(sp.ia, sp.aR2, sp.ey, sp.ex);
+  s_span[w][lane][2] = make_float4(sp.yx, sp.bx, sp.by, sp.need);
+  s_span[w][lane][3] = make_float4(__uint_as_float((sp.ok ? 1u : 0u) | (sp.cut ? 2u : 0u)),
+                                   __int_as_float(tx0), __int_as_float(tx1), __int_as_float(ty0));
   __syncthreads();
   const uint32_t R = s_pref[w][64];
   for (uint32_t base = 0; base < R; base += 64) {
     const uint32_t it = base + lane;
-    int o = 0;
-    if (it < R) {   // owner: last lane whose first row is <= it
-      int lo = 0, hi = 64;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_pref[w][mid] <= it) lo = mid; else hi = mid;
-      }
-      o = lo;
-    }
-    Span so;
-    so.mx = __shfl(sp.mx, o);
-    so.my = __shfl(sp.my, o);
-    so.b = __shfl(sp.b, o);
-    so.det = __shfl(sp.det, o);
-    so.ia = __shfl(sp.ia, o);
-    so.aR2 = __shfl(sp.aR2, o);
-    so.ey = __shfl(sp.ey, o);
-    so.ex = __shfl(sp.ex, o);
-    so.yx = __shfl(sp.yx, o);
-    so.bx = __shfl(sp.bx, o);
-    so.by = __shfl(sp.by, o);
-    so.need = __shfl(sp.need, o);
-    so.ok = __shfl((int)sp.ok, o) != 0;
-    so.cut = __shfl((int)sp.cut, o) != 0;
-    const int ox0 = __shfl(tx0, o), ox1 = __shfl(tx1, o), oy0 = __shfl(ty0, o);
+    s_mark[w][lane] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (rows > 0 && first < base + 64 && incl > base)   // (positions of such records are distinct)
+      s_mark[w][(first > base ? first : base) - base] = (uint32_t)lane + 1u;
+    __builtin_amdgcn_wave_barrier();
+    const int o = (int)wave_incl_max(s_mark[w][lane]) - 1;   // last record starting at or before it
+    __builtin_amdgcn_wave_barrier();
     if (it < R) {
+      const float4 q0 = s_span[w][o][0], q1 = s_span[w][o][1], q2 = s_span[w][o][2], q3 = s_span[w][o][3];
+      Span so;
+      so.mx = q0.x; so.my = q0.y; so.b = q0.z; so.det = q0.w;
+      so.ia = q1.x; so.aR2 = q1.y; so.ey = q1.z; so.ex = q1.w;
+      so.yx = q2.x; so.bx = q2.y; so.by = q2.z; so.need = q2.w;
+      so.ok = (__float_as_uint(q3.x) & 1u) != 0u;
+      so.cut = (__float_as_uint(q3.x) & 2u) != 0u;
       int c0, c1;
-      span_row(so, oy0 + (int)(it - s_pref[w][o]), a.opt.tile_w, a.opt.tile_h, ox0, ox1, c0, c1);
+      span_row(so, __float_as_int(q3.w) + (int)(it - s_pref[w][o]), a.opt.tile_w, a.opt.tile_h,
+               __float_as_int(q3.y), __float_as_int(q3.z), c0, c1);
       if (c1 > c0) atomicAdd(&s_cnt[w * 64 + o], (uint32_t)(c1 - c0));
     }
   }
