@@ -212,7 +212,7 @@ template <int DEG>
 __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
   __shared__ uint32_t s_pref[4][65];   // per wave: exclusive prefix of the records' rows
   __shared__ uint32_t s_cnt[256];
-  __shared__ float4 s_span[4][64][4];  // per wave and lane: the record's Span and tile rect
+  __shared__ float s_span[16][4][64];  // per field, wave and lane: the record's Span and tile rect
   __shared__ uint32_t s_mark[4][64];   // per wave: owner marks of the current row window
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int v = blockIdx.y;
@@ -282,11 +282,14 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
   s_pref[w][lane] = first;
   if (lane == 63) s_pref[w][64] = incl;
   s_cnt[t] = 0;
-  s_span[w][lane][0] = make_float4(sp.mx, sp.my, sp.b, sp.det);
-  s_span[w][lane][1] = make_float4(sp.ia, sp.aR2, sp.ey, sp.ex);
-  s_span[w][lane][2] = make_float4(sp.yx, sp.bx, sp.by, sp.need);
-  s_span[w][lane][3] = make_float4(__uint_as_float((sp.ok ? 1u : 0u) | (sp.cut ? 2u : 0u)),
-                                   __int_as_float(tx0), __int_as_float(tx1), __int_as_float(ty0));
+  {
+    const float f[16] = {sp.mx, sp.my, sp.b, sp.det, sp.ia, sp.aR2, sp.ey, sp.ex,
+                         sp.yx, sp.bx, sp.by, sp.need,
+                         __uint_as_float((sp.ok ? 1u : 0u) | (sp.cut ? 2u : 0u)),
+                         __int_as_float(tx0), __int_as_float(tx1), __int_as_float(ty0)};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s_span[k][w][lane] = f[k];
+  }
   __syncthreads();
   const uint32_t R = s_pref[w][64];
   for (uint32_t base = 0; base < R; base += 64) {
@@ -299,7 +302,11 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
     const int o = (int)wave_incl_max(s_mark[w][lane]) - 1;   // last record starting at or before it
     __builtin_amdgcn_wave_barrier();
     if (it < R) {
-      const float4 q0 = s_span[w][o][0], q1 = s_span[w][o][1], q2 = s_span[w][o][2], q3 = s_span[w][o][3];
+      float g[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) g[k] = s_span[k][w][o];   // (lanes read distinct banks)
+      const float4 q0 = make_float4(g[0], g[1], g[2], g[3]), q1 = make_float4(g[4], g[5], g[6], g[7]);
+      const float4 q2 = make_float4(g[8], g[9], g[10], g[11]), q3 = make_float4(g[12], g[13], g[14], g[15]);
       Span so;
       so.mx = q0.x; so.my = q0.y; so.b = q0.z; so.det = q0.w;
       so.ia = q1.x; so.aR2 = q1.y; so.ey = q1.z; so.ex = q1.w;
