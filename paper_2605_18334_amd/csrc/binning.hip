@@ -593,6 +593,8 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
   __shared__ uint32_t s_rows[257];        // exclusive prefix of the chunk's records' rows
   __shared__ uint32_t s_e[256], s_k0[256], s_irec[256];   // items: output offset, first key, record
   __shared__ uint16_t s_map[EXT];         // item of each output of a round (block-relative)
+  __shared__ uint32_t s_mark[256];        // owner marks of the current item round
+  __shared__ uint32_t s_wmax[4];          // their per-wave maxima
   __shared__ uint32_t hist[4][256];
   __shared__ uint32_t ws[4];
   __shared__ uint32_t s_tot, s_j0, s_w;
@@ -648,18 +650,24 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
     if (t == 255) s_rows[256] = e + rows;
     __syncthreads();
     const uint32_t R = s_rows[256];
-    const uint32_t cw = min(256u, W - c);   // records of this chunk
     for (uint32_t base = 0; base < R && run < o1; base += 256) {
       const uint32_t i = base + t;
+      // record of item i: the last record of the chunk starting at or
+      // before it; each record overlapping [base, base + 256) marks its
+      // first item there (distinct positions), a block max-scan spreads them
+      s_mark[t] = 0u;
+      __syncthreads();
+      if (rows > 0 && e < base + 256 && e + rows > base) s_mark[(e > base ? e : base) - base] = (uint32_t)t + 1u;
+      __syncthreads();
+      const uint32_t wm = wave_incl_max(s_mark[t]);
+      if ((t & 63) == 63) s_wmax[t >> 6] = wm;
+      __syncthreads();
+      uint32_t own = wm;
+      for (int q = 0; q < (t >> 6); ++q) own = max(own, s_wmax[q]);
       uint32_t cnt = 0, rec = 0, tk = 0;
       int c0 = 0;
       if (i < R) {
-        // record of item i: last k with s_rows[k] <= i
-        uint32_t lo = 0, hi = cw;
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (s_rows[mid] <= i) lo = mid; else hi = mid;
-        }
+        const uint32_t lo = own - 1u;
         rec = s_rec[lo];
         Span sp;
         sp.mx = s_sp[0][lo];  sp.my = s_sp[1][lo];  sp.b = s_sp[2][lo];   sp.det = s_sp[3][lo];
