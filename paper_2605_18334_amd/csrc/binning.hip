@@ -305,8 +305,9 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
       run += cw[v];
     }
     // publish this block's count of digit t as early as possible (later
-    // blocks' look-backs wait for it); threads past the last digit idle
-    if (has_digit)
+    // blocks' look-backs wait for it); threads past the last digit idle, and
+    // a pass with precomputed offsets has no look-backs
+    if (has_digit && !pre)
       __hip_atomic_store(st, (b == 0 ? ST_INC : ST_AGG) | (uint64_t)tot, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -998,7 +999,12 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   // one fill zeroes the ranges, the instance count and every sort's state
   ZeroList z = {};
   int nz = 0;
+  bool z_overflow = false;
   auto zero = [&](uint32_t* ptr, uint64_t words, uint32_t ev = 0u) {
+    if (nz == ZL_MAX) {
+      z_overflow = true;
+      return;
+    }
     z.p[nz] = ptr;
     z.n[nz] = words;
     z.ev[nz] = ev;
@@ -1008,12 +1014,26 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   zero(ranges, 2 * T, mode == 1 ? 0xffffffffu : 0u);
   zero(n_inst, 1);
   zero(L.misc, 64);
-  if (C > 0) zero(L.rs_main, rs_words(C, L.main_passes));
+  if (C > 0) {
+    // large mode-1 sorts: the first pass takes scanned offsets and has no
+    // look-back, so its block statuses stay untouched (not cleared)
+    const bool scan0 = mode == 1 && cdiv(C, (uint64_t)RS_T * RS_IPT) > RS_WIDE_MAX_BLOCKS;
+    const uint64_t words = rs_words(C, L.main_passes);
+    const uint64_t head = 64 + (uint64_t)L.main_passes * 256 * (1 + HC);   // counters, histograms
+    const uint64_t st0 = rs_blocks(C) * 256 * 2;                             // pass 0's statuses
+    if (scan0) {
+      zero(L.rs_main, head);
+      zero(L.rs_main + head + st0, words - head - st0);
+    } else {
+      zero(L.rs_main, words);
+    }
+  }
   if (mode == 1 && m > 0) {
     zero(L.rs_depth, rs_words((uint64_t)m, 4));
     zero(L.so_status, L.so_words);
     zero(L.bstart, L.n_bstart);
   }
+  if (z_overflow) return SGS_EINVAL;   // (at most ZL_MAX regions are ever listed)
   uint64_t zmax = 0;
   for (int k = 0; k < nz; ++k) zmax = std::max(zmax, z.n[k]);
   k_zero<<<dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(cdiv(zmax, 256), 1), 2048), nz), 256, 0, s>>>(z);
