@@ -885,10 +885,11 @@ static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32
   const uint64_t hist_blocks = hist_done ? hist_blocks_done : blocks;
   const bool copies = hist_blocks > HC_MIN_BLOCKS;
   if (!hist_done) {
-    // small sorts: 4x as many blocks of 1024 keys (a block's LDS counts of
-    // the few high digits that most keys share are serialised)
+    // small sorts: twice as many blocks of 2048 keys (a block's LDS counts
+    // of the few high digits that most keys share are serialised; 1024-key
+    // blocks measured slower at 1M keys)
     if (blocks <= RS_WIDE_MAX_BLOCKS)
-      k_os_hist<K, 4><<<(unsigned)cdiv(cap, (uint64_t)RS_T * 4), RS_T, 0, s>>>(
+      k_os_hist<K, 8><<<(unsigned)cdiv(cap, (uint64_t)RS_T * 8), RS_T, 0, s>>>(
           kin, n_dev, n_host, (uint32_t)cap, passes, width, copies ? sc.hpart : sc.ghist,
           copies ? HC : 1);
     else
