@@ -411,17 +411,22 @@ class Renderer:
         statistics of this backward."""
         gs = self.gs
         if self._bwd is None:
-            g2d = torch.empty(int(self.lib.sgs_geom_rec_floats(self.m, int(gs.enhanced))),
-                              dtype=torch.float32, device=gs.mean.device)
-            grads = {f: (None if getattr(gs, f) is None else torch.empty_like(getattr(gs, f)))
-                     for f in GaussianSet.FIELDS}
-            self._bwd = (g2d, grads, _abi.GeomGrad(_ptr(g2d)))
-        g2d, grads, gg = self._bwd
+            # the 2D gradients and every parameter gradient are views of one
+            # buffer (16-byte aligned pieces), zeroed by a single fill
+            n2d = int(self.lib.sgs_geom_rec_floats(self.m, int(gs.enhanced)))
+            sizes = [(f, getattr(gs, f)) for f in GaussianSet.FIELDS if getattr(gs, f) is not None]
+            total = (n2d + 3) // 4 * 4 + sum((v.numel() + 3) // 4 * 4 for _, v in sizes)
+            flat = torch.empty(total, dtype=torch.float32, device=gs.mean.device)
+            g2d = flat[:n2d]
+            off = (n2d + 3) // 4 * 4
+            grads = {f: None for f in GaussianSet.FIELDS}
+            for f, v in sizes:
+                grads[f] = flat[off:off + v.numel()].view(v.shape)
+                off += (v.numel() + 3) // 4 * 4
+            self._bwd = (flat, g2d, grads, _abi.GeomGrad(_ptr(g2d)))
+        flat, g2d, grads, gg = self._bwd
         pg = _params_grad(grads, densify)
-        g2d.zero_()
-        for v in grads.values():
-            if v is not None:
-                v.zero_()
+        flat.zero_()
         b = self.bufs
         check("sgs_render_bwd", self.lib.sgs_render_bwd(
             C.byref(self.params), C.byref(self.geom), self.m, _ptr(b["vals"]), self.capacity,
