@@ -493,3 +493,45 @@ def test_autograd_function_matches_direct_backward():
     g = P.render_backward(fr, dL)
     for k, v in leaves.items():
         torch.testing.assert_close(v.grad, g[k], rtol=1e-5, atol=1e-7)
+
+
+def test_autograd_gradient_matches_central_differences_of_gpu_forward():
+    """Directional central differences of the FP32 GPU forward against the
+    gradient of the autograd Function, for every parameter kind.  alpha_min
+    and t_min are set near zero so that the image is continuous in the
+    parameters (the skip and stop cut-offs of compositing otherwise make it
+    jump), and the means move only across the view, which leaves every
+    depth, and with it the compositing order, bit-unchanged for this
+    axis-aligned camera.  What remains are the kinks of the alpha and colour
+    clamps, whose effect on a central difference is of order h."""
+    P = _P()
+    sc = S.blobs_scene(4, 200, 1)
+    W_, H_ = 48, 40
+    pose = S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), W_, H_)
+    o = P.default_options(alpha_min=1e-7, t_min=1e-9)
+    cams = P.CameraBatch.from_poses([pose], o)
+    gs = P.GaussianSet.from_scene(sc)
+    names = ("mean", "log_scale", "quat", "skew", "opa_logit", "sh")
+    base = {f: getattr(gs, f).clone() for f in names}
+    w = torch.from_numpy(np.random.default_rng(21).normal(size=(3, W_ * H_))).cuda()
+
+    def loss(p):
+        with torch.no_grad():
+            img = P.rasterize(*(p[f] for f in names), cams, o)
+            return float((img.double() * w).sum())
+
+    leaves = {f: v.clone().requires_grad_(True) for f, v in base.items()}
+    img = P.rasterize(*(leaves[f] for f in names), cams, o)
+    (img.double() * w).sum().backward()
+    rng = np.random.default_rng(22)
+    h = 4e-3
+    for f in names:
+        u = torch.from_numpy(rng.normal(size=tuple(base[f].shape)).astype(np.float32)).cuda()
+        if f == "mean":
+            u[2] = 0.0          # world z is the camera's depth axis here
+        xp, xm = base[f] + h * u, base[f] - h * u
+        fd = (loss({**base, f: xp}) - loss({**base, f: xm})) / (2 * h)
+        an = float((leaves[f].grad.double() * (xp - xm).double()).sum()) / (2 * h)
+        print(f"{f}: central difference {fd:.6f}, adjoint {an:.6f}", flush=True)
+        assert abs(an) > 0.1, (f, an)
+        assert abs(fd - an) <= 1e-2 * abs(an) + 1e-2, (f, fd, an)
