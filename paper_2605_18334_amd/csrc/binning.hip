@@ -811,13 +811,19 @@ __global__ void __launch_bounds__(1024) k_order_tiles(uint32_t* __restrict__ ran
   }
   if (!order) return;
   __syncthreads();
-  if (t == 0) {
-    uint32_t run = 0;
-    for (int k = OT_BUCKETS - 1; k >= 0; --k) {
-      pos[k] = run;
-      run += cnt[k];
-    }
+  // pos[k] = tiles in buckets above k (longest first): the first two waves
+  // take one bucket per lane in descending order and scan; wave 1 adds
+  // wave 0's total
+  static_assert(OT_BUCKETS == 128, "two full waves scan the buckets");
+  __shared__ uint32_t s_w0;
+  uint32_t c = 0, inc = 0;
+  if (t < OT_BUCKETS) {
+    c = cnt[OT_BUCKETS - 1 - t];
+    inc = wave_incl_scan(c);
+    if (t == 63) s_w0 = inc;
   }
+  __syncthreads();
+  if (t < OT_BUCKETS) pos[OT_BUCKETS - 1 - t] = inc - c + (t >= 64 ? s_w0 : 0u);
   __syncthreads();
   for (uint32_t i = t; i < total_tiles; i += 1024) {
     const uint32_t a = ranges[2 * i], b = ranges[2 * i + 1];
