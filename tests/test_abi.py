@@ -142,3 +142,34 @@ def test_options_are_validated_on_the_host():
                 dict(alpha_min=0.0), dict(t_min=1.0)):
         o = _abi.default_options(**bad)
         assert lib.sgs_camera_layout(cams, 1, C.byref(o), C.byref(tt), C.byref(tp)) == 1, bad
+
+
+def test_missing_library_fails_loudly():
+    """No fallback: in a fresh interpreter, loading a library that is not
+    there raises instead of handing back a substitute."""
+    import subprocess
+    import sys
+    code = ("from paper_2605_18334_amd import _abi\n"
+            "try:\n"
+            "    _abi.load('/nonexistent/libsgs.so')\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    raise SystemExit('no error for a missing library')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "raised:" in r.stdout and "missing" in r.stdout
+
+
+def test_package_never_reaches_the_oracle():
+    """The product path has no route into the CPU oracle: no source file of
+    the package imports, loads or names it."""
+    pkg = os.path.join(ROOT, "paper_2605_18334_amd")
+    found = []
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp", ".c")):
+                text = open(os.path.join(dirpath, f), errors="replace").read()
+                if re.search(r"\boracle\b", text):
+                    found.append(os.path.relpath(os.path.join(dirpath, f), ROOT))
+    assert not found, found
