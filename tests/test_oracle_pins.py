@@ -541,3 +541,204 @@ def test_power_terms_bound_the_exponent():
     t = float(O.power_terms(p, pr, idx[:1])[0, 0])
     e = float(-torch.log(O.alpha_tilde(p, pr, idx[:1], O.Options(symmetric=True)))[0, 0])
     assert abs(e - 0.5 * (120 / 50) ** 2) < 1e-9 and abs(t / e - 1e4) < 1e-3 * 1e4
+
+
+# ------------------------------------------------------------------ projection chain
+def _hamilton(p, q):
+    """Quaternion product p q, (w, x, y, z) order."""
+    pw, px, py, pz = p
+    qw, qx, qy, qz = q
+    return np.array([pw * qw - px * qx - py * qy - pz * qz,
+                     pw * qx + px * qw + py * qz - pz * qy,
+                     pw * qy - px * qz + py * qw + pz * qx,
+                     pw * qz + px * qy - py * qx + pz * qw])
+
+
+def test_rotation_matrix_equals_quaternion_sandwich():
+    """Sec. "Preliminary of 3D Gaussian Splatting": R is the rotation of the
+    (normalised) quaternion q, i.e. R v is the vector part of q (0, v) q*,
+    computed here by Hamilton products; also equal to scipy's rotation of
+    the same quaternion (scalar-last order there)."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(41)
+    q = rng.normal(size=(24, 4)) * rng.uniform(0.3, 3.0, (24, 1))      # not unit length
+    R = O.quat_to_rotmat(torch.from_numpy(q)).numpy()
+    for i in range(len(q)):
+        qn = q[i] / np.linalg.norm(q[i])
+        qc = qn * np.array([1.0, -1.0, -1.0, -1.0])
+        for v in [*np.eye(3), rng.normal(size=3)]:
+            rv = _hamilton(_hamilton(qn, np.concatenate([[0.0], v])), qc)
+            assert abs(rv[0]) < 1e-13
+            np.testing.assert_allclose(R[i] @ v, rv[1:], atol=1e-13)
+    np.testing.assert_allclose(R, Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix(), atol=1e-13)
+
+
+def _perspective_jacobian_fd(cam, t):
+    """Central differences of the pinhole map pi(t) = (fx tx/tz + cx,
+    fy ty/tz + cy) at camera-space point t: a 2x3 matrix."""
+    fx, fy, cx, cy = cam.K[0, 0], cam.K[1, 1], cam.K[0, 2], cam.K[1, 2]
+    pi = lambda u: np.array([fx * u[0] / u[2] + cx, fy * u[1] / u[2] + cy])
+    J = np.zeros((2, 3))
+    for k in range(3):
+        h = 1e-5 * max(1.0, abs(t[k]))
+        e = np.zeros(3)
+        e[k] = h
+        J[:, k] = (pi(t + e) - pi(t - e)) / (2 * h)
+    return J, pi(t)
+
+
+def test_ewa_projection_matches_perspective_map_off_axis():
+    """Sec. "Preliminary of 3D Gaussian Splatting" (affine approximation of
+    the viewing transform) and the appendix "Forward Pass": Sigma' = A Sigma
+    A^T with A the Jacobian of the pinhole map at the camera-space centre
+    times the world-to-camera rotation; the Jacobian is taken at the centre
+    with x/z and y/z clamped to +-1.3 tan(FoV/2) (reading R15).  Sigma comes
+    from scipy's rotation of the quaternion and the scales; A from central
+    differences of the pinhole map at the clamped point.  Means lie off the
+    axis inside and beyond the clamp, under a general camera pose; the conic
+    (Sigma' + sI)^-1, rho and the 2D mean are compared."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(43)
+    pose = S.Pose(S.look_at_gl((2.0, -3.0, 7.0), (0.3, 0.1, -0.2)), 160, 96, 60.0, 0.2)
+    cam = O.camera_from_pose(pose)
+    c2w = np.linalg.inv(cam.w2c)
+    fx, fy = cam.K[0, 0], cam.K[1, 1]
+    limx, limy = 1.3 * (cam.W / 2) / fx, 1.3 * (cam.H / 2) / fy
+    # camera-space targets: ratios x/z, y/z inside and beyond the clamp
+    ratios = [(0.2, -0.1), (-0.6, 0.3), (0.9 * limx, -0.8 * limy), (1.4 * limx, 0.2),
+              (-1.7 * limx, 1.5 * limy), (0.1, -2.0 * limy), (-0.5, 0.95 * limy)]
+    n = len(ratios)
+    tcam = np.array([[rx * z, ry * z, z] for (rx, ry), z in zip(ratios, rng.uniform(3.0, 9.0, n))])
+    mean = (c2w[:3, :3] @ tcam.T).T + c2w[:3, 3]
+    q = rng.normal(size=(n, 4))
+    ls = rng.uniform(-3.0, -0.5, (n, 3))
+    sc = S.Scene(mean.T.astype(np.float32), ls.T.astype(np.float32), q.T.astype(np.float32),
+                 np.zeros((3, n), np.float32), np.zeros(n, np.float32),
+                 np.zeros((1, 3, n), np.float32), 0)
+    s_f = 0.3
+    pr = O.project_numpy(sc, pose, O.Options(filter_s=s_f))
+    beyond = 0
+    for i in range(n):
+        m64 = sc.mean[:, i].astype(np.float64)
+        t = cam.w2c[:3, :3] @ m64 + cam.w2c[:3, 3]
+        rx, ry = t[0] / t[2], t[1] / t[2]
+        tc = np.array([np.clip(rx, -limx, limx) * t[2], np.clip(ry, -limy, limy) * t[2], t[2]])
+        beyond += (abs(rx) > limx) or (abs(ry) > limy)
+        J, _ = _perspective_jacobian_fd(cam, tc)
+        _, mu = _perspective_jacobian_fd(cam, t)
+        A = J @ cam.w2c[:3, :3]
+        Rq = Rotation.from_quat(sc.quat[[1, 2, 3, 0], i].astype(np.float64)).as_matrix()
+        s = np.exp(sc.log_scale[:, i].astype(np.float64))
+        sig3 = Rq @ np.diag(s * s) @ Rq.T
+        sig2 = A @ sig3 @ A.T
+        Q = np.linalg.inv(sig2 + s_f * np.eye(2))
+        rho = math.sqrt(np.linalg.det(sig2) / np.linalg.det(sig2 + s_f * np.eye(2)))
+        np.testing.assert_allclose(pr["conic"][i], [Q[0, 0], Q[0, 1], Q[1, 1]], rtol=1e-7,
+                                   atol=1e-9 * np.abs(Q).max(), err_msg=f"conic {i}")
+        assert pr["rho"][i] == pytest.approx(rho, rel=1e-7), i
+        np.testing.assert_allclose(pr["mu2d"][i], mu, rtol=1e-12, atol=1e-9)
+    assert beyond >= 3
+
+
+def test_filter_and_compensation_closed_form():
+    """Appendix "Forward Pass": d = o sqrt(det Sigma' / det(Sigma' + sI)).
+    For an isotropic Gaussian of scale sigma at (0, 0, Z) in front of the
+    camera Sigma' = sigma_p^2 I with sigma_p = f sigma / Z, so by hand
+    rho = sigma_p^2 / (sigma_p^2 + s) and, without skew, C(p) = rgb min(0.99,
+    o rho exp(-|delta|^2 / (2 (sigma_p^2 + s)))) with s = 0.3."""
+    Z, sig, s_f = 6.0, 0.07, 0.3
+    pose = _identity_pose()
+    sc = _one_gaussian([0.0, 0.0, Z], sig, [0.0, 0.0, 0.0], opa_logit=3.0)
+    opt = O.Options(filter_s=s_f, compensate=True)
+    f = 64 / (2 * math.tan(math.radians(30)))
+    Zf = float(np.float32(Z))
+    sf = math.exp(float(np.float32(math.log(sig))))
+    sp2 = (f * sf / Zf) ** 2
+    rho = sp2 / (sp2 + s_f)
+    assert 0.3 < rho < 0.9                         # the filter matters here
+    pr = O.project_numpy(sc, pose, opt)
+    assert pr["rho"][0] == pytest.approx(rho, rel=1e-12)
+    o = 1 / (1 + math.exp(-3.0))
+    rgb = 0.5 + np.array([0.3, -0.1, 0.2], np.float32).astype(np.float64) / (2 * math.sqrt(math.pi))
+    px = (np.arange(64 * 64) % 64) + 0.5 - 32
+    py = (np.arange(64 * 64) // 64) + 0.5 - 32
+    a = np.minimum(o * rho * np.exp(-(px ** 2 + py ** 2) / (2 * (sp2 + s_f))), 0.99)
+    a = np.where(a >= 1 / 255, a, 0.0)
+    r = O.render(sc, pose, opt=opt)
+    np.testing.assert_allclose(r.color, a[:, None] * rgb[None, :], atol=1e-12)
+
+
+def _needle_scene(seed=7, n=60):
+    sc = S.blobs_scene(seed, n, 0)
+    rng = np.random.default_rng(seed + 100)
+    sc.log_scale[:] = np.log(0.004)
+    sc.log_scale[0] = np.log(rng.uniform(0.8, 2.5, n)).astype(np.float32)
+    sc.opa_logit[:] = rng.uniform(1.0, 5.0, n).astype(np.float32)
+    sc.skew[:] *= np.float32(0.02)
+    # a mid-grey background gives derivatives of both signs along a pixel
+    return sc, S.Pose(S.look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 96, 72, 60.0, 0.2, (0.5, 0.5, 0.5))
+
+
+def _composite_by_hand(alpha_t, rgb, bg, amax):
+    """Front-to-back compositing of one pixel's included pairs (in order),
+    written out: returns colour [3] and T."""
+    T, C = 1.0, np.zeros(3)
+    for at, c in zip(alpha_t, rgb):
+        a = min(amax, at)
+        C += c * a * T
+        T *= 1.0 - a
+    return C + T * bg, T
+
+
+def test_float32_error_bound_covers_rounding_and_is_first_order_tight():
+    """float32_error_bound sizes the tolerance on ill-conditioned inputs: it
+    must (1) cover the change of the FP64 image when every conic is rounded
+    to float32 (exponent terms off by at most 2^-24 of power_terms, a
+    quarter of the u = 2^-22 the bound assumes), with the decisions held,
+    and (2) equal, pixel by pixel, the first-order effect of the worst-case
+    perturbation alpha~ -> alpha~ (1 +- u power_terms), here obtained by
+    central differences of compositing written out by hand."""
+    sc, pose = _needle_scene()
+    opt = O.Options()
+    bC, bT = O.float32_error_bound(sc, pose)
+    cam = O.camera_from_pose(pose)
+    with torch.no_grad():
+        pr = O.project(O.to_tensors(sc), 0, cam, opt)
+        order = O.depth_order(pr)
+        pix, pc = O.pixel_centres(cam, None)
+        at = O.alpha_tilde(pc, pr, order, opt)
+        inc = O.inclusion(at, opt)
+        bg = torch.from_numpy(cam.bg)
+        C0, T0 = O.composite(at, pr.rgb[order], bg, inc, opt)
+        pr.conic = pr.conic.float().double()
+        at32 = O.alpha_tilde(pc, pr, order, opt)
+        C1, T1 = O.composite(at32, pr.rgb[order], bg, inc, opt)
+        pt = O.power_terms(pc, pr, order).numpy()
+    dC = (C1 - C0).abs().numpy()
+    dT = (T1 - T0).abs().numpy()
+    assert bC.max() > 1e-7                         # the needles make the bound matter
+    assert (dC <= bC * (1 + 1e-6) + 1e-15).all() and (dT <= bT * (1 + 1e-6) + 1e-15).all()
+    assert dC.max() > 0.05 * bC.max()              # and the rounding is of its order
+    # first-order tightness on the pixels with the largest bounds and on
+    # those where most pairs overlap (derivatives of mixed sign)
+    u = 2.0 ** -22
+    atn, incn, rgb = at.numpy(), inc.numpy(), pr.rgb[order].numpy()
+    many = np.argsort(-(incn.sum(1) + 1e-3 * (bC.max(1) > 1e-9)))[:12]
+    assert incn.sum(1)[many].min() >= 3
+    for p in np.concatenate([np.argsort(-bC.max(1))[:12], many]):
+        ks = np.nonzero(incn[p])[0]
+        a_p, c_p = atn[p, ks], rgb[ks]
+        tight = np.zeros(4)
+        for j, k in enumerate(ks):
+            if a_p[j] >= opt.alpha_max:
+                continue                              # clamped: no derivative
+            h = 1e-7 * a_p[j]
+            up, dn = a_p.copy(), a_p.copy()
+            up[j] += h
+            dn[j] -= h
+            Cu, Tu = _composite_by_hand(up, c_p, cam.bg, opt.alpha_max)
+            Cd, Td = _composite_by_hand(dn, c_p, cam.bg, opt.alpha_max)
+            d = np.concatenate([(Cu - Cd), [Tu - Td]]) / (2 * h)
+            tight += np.abs(d) * a_p[j] * u * pt[p, k]
+        np.testing.assert_allclose(np.concatenate([bC[p], [bT[p]]]), tight, rtol=1e-5,
+                                   atol=1e-9 * tight.max())
