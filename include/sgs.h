@@ -23,7 +23,9 @@
  *    component j of element i at index j*n + i.
  *  - The caller allocates and owns all memory, including scratch; the library
  *    allocates nothing, keeps no global state and may be called concurrently
- *    on distinct streams with distinct buffers.
+ *    on distinct streams with distinct buffers.  The one exception is
+ *    sgs_bin_sort_noalloc, which uses a fixed scratch array held by the
+ *    library on each device (see there).
  *  - `stream` is a hipStream_t (NULL = default stream).  Calls only enqueue
  *    work and return; no call synchronises.  Kernel launch errors are reported
  *    as SGS_EHIP by the call that launched them.
@@ -255,6 +257,29 @@ sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_hos
                         uint64_t* keys, uint32_t* vals, uint32_t* tile_ranges,
                         uint32_t* n_inst_dev, const sgs_schedule* sched, void* scratch,
                         size_t scratch_bytes, void* stream);
+
+/* sgs_bin_sort for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, checks, results and errors as sgs_bin_sort, minus the
+ * scratch pair: the scratch is a fixed array of SGS_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) per device, part of the library's code object, allocated when the
+ * library is loaded on that device and held until the process ends.  The
+ * call itself allocates nothing (no hipMalloc, no allocating library
+ * routine); its first call on a device looks up the array's address there.
+ *  - ECAPACITY when sgs_bin_sort_scratch_bytes(m, inst_capacity, tiles, opt)
+ *    exceeds SGS_NOALLOC_SCRATCH_BYTES (about 2M records and 4M instances
+ *    fit; the 300k-Gaussian 1280x720 frame needs 13 MiB), checked before any
+ *    work is enqueued.
+ *  - Every call on one device shares that device's array and clears what it
+ *    needs at its start (on the stream, with a fill kernel).  Calls that
+ *    overlap in time on one device race on it: serialise them (one stream, or
+ *    events between streams). */
+#define SGS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sgs_status sgs_bin_sort_noalloc(const sgs_geom* g, int64_t m, const sgs_camera* cams_host,
+                                const sgs_camera* cams_dev, int32_t n_views,
+                                const sgs_options* opt, int64_t inst_capacity, uint64_t* keys,
+                                uint32_t* vals, uint32_t* tile_ranges, uint32_t* n_inst_dev,
+                                const sgs_schedule* sched, void* stream);
 
 /* Alg. 1 per pixel: alpha = min(alpha_max, d G'(x) (1 + erf(beta.delta/sqrt2)))
  * (times the enhanced-opacity factor), pairs below alpha_min skipped, stop

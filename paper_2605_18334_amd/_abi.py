@@ -55,6 +55,9 @@ class Schedule(C.Structure):
 
 STRUCTS = [Params, ParamsGrad, Camera, Options, Geom, GeomGrad, Schedule]
 
+# bytes of the fixed per-device scratch of sgs_bin_sort_noalloc (SGS_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
 STATUS = {0: "SGS_OK", 1: "SGS_EINVAL", 2: "SGS_ECAPACITY", 3: "SGS_EHIP", 4: "SGS_EUNSUPPORTED"}
 
 # name -> (restype, argtypes)
@@ -74,6 +77,8 @@ SIGNATURES = {
     "sgs_bin_sort": (C.c_int, [C.POINTER(Geom), C.c_int64, C.POINTER(Camera), P, C.c_int32,
                                C.POINTER(Options), C.c_int64, P, P, P, P, C.POINTER(Schedule), P,
                                C.c_size_t, P]),
+    "sgs_bin_sort_noalloc": (C.c_int, [C.POINTER(Geom), C.c_int64, C.POINTER(Camera), P, C.c_int32,
+                                       C.POINTER(Options), C.c_int64, P, P, P, P, C.POINTER(Schedule), P]),
     "sgs_render_fwd": (C.c_int, [C.POINTER(Geom), C.c_int64, P, C.c_int64, P, C.POINTER(Schedule),
                                  C.POINTER(Camera), P, C.c_int32, C.c_int32, C.POINTER(Options), P, P, P,
                                  P, C.c_int64, P]),

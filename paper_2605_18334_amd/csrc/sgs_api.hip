@@ -1,9 +1,12 @@
 // extern "C" entry points of libsgs: argument checks and dispatch to the
-// kernel launchers.  No allocation, no global state, no synchronisation.
+// kernel launchers.  No allocation and no synchronisation.  The only global
+// state is the fixed scratch array of sgs_bin_sort_noalloc and its per-device
+// addresses (below).
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "sgs_dev.h"
 
@@ -72,6 +75,31 @@ int64_t tiles_total(const sgs_camera* c, int32_t n_views) {
 int64_t pixels_total(const sgs_camera* c, int32_t n_views) {
   const sgs_camera& k = c[n_views - 1];
   return k.pix_base + (int64_t)k.width * k.height;
+}
+
+// Scratch of sgs_bin_sort_noalloc: one array per device, allocated when the
+// code object is loaded and held until the process ends.  In host code the
+// name below only stands for the symbol; its device address comes from
+// hipGetSymbolAddress, once per device (with that device current), and is
+// the only handle host code ever passes on.
+static __device__ __align__(256) unsigned char scratch[SGS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[MAX_DEVICES];   // device address of `scratch` on each device
+
+sgs_status noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SGS_EHIP;
+  if (dev < 0 || dev >= MAX_DEVICES) return SGS_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SGS_EHIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return SGS_OK;
 }
 
 }  // namespace
@@ -232,6 +260,26 @@ sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_hos
   return sgs::launch_bin_sort(g, m, m / n_views, cams_dev, n_views, tt, opt, inst_capacity, keys,
                               vals, tile_ranges, n_inst_dev, sched ? sched->tile_order : nullptr,
                               scratch, (hipStream_t)stream);
+}
+
+sgs_status sgs_bin_sort_noalloc(const sgs_geom* g, int64_t m, const sgs_camera* cams_host,
+                                const sgs_camera* cams_dev, int32_t n_views,
+                                const sgs_options* opt, int64_t inst_capacity, uint64_t* keys,
+                                uint32_t* vals, uint32_t* tile_ranges, uint32_t* n_inst_dev,
+                                const sgs_schedule* sched, void* stream) {
+  // the same checks as sgs_bin_sort, then the size check against the fixed
+  // array, before any HIP call that touches it
+  if (!g || m < 0 || !cams_ok(cams_host, n_views) || !cams_dev || !options_ok(opt) ||
+      inst_capacity < 0 || inst_capacity >= ((int64_t)1 << 32))
+    return SGS_EINVAL;
+  const size_t need = sgs::bin_sort_scratch_bytes(m, inst_capacity, tiles_total(cams_host, n_views),
+                                                  opt->sort_mode);
+  if (need > (size_t)SGS_NOALLOC_SCRATCH_BYTES) return SGS_ECAPACITY;
+  void* ws = nullptr;
+  const sgs_status st = noalloc_scratch(&ws);
+  if (st != SGS_OK) return st;
+  return sgs_bin_sort(g, m, cams_host, cams_dev, n_views, opt, inst_capacity, keys, vals,
+                      tile_ranges, n_inst_dev, sched, ws, (size_t)SGS_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 sgs_status sgs_render_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals,
