@@ -228,17 +228,40 @@ size_t sgs_bin_sort_scratch_bytes(int64_t m, int64_t inst_capacity, int64_t tota
 
 /* Projects every Gaussian into every view (see sgs_geom) and computes
  * block_off (scan of the tile counts), so that *block_off[last] is the
- * number of instances.  cams_host / cams_dev: the same n_views laid-out
- * cameras.  EINVAL: null pointers, n < 0, sh_degree > 3, bad options. */
+ * number of instances.  Per (view, Gaussian), in the paper's terms:
+ *  - Sigma = R S S^T R^T from the normalised quaternion and exp(log_scale),
+ *    opacity sigmoid(logit), colour from the SH coefficients in the view
+ *    direction (Sec. "Preliminary of 3D Gaussian Splatting");
+ *  - world-to-camera with the view's w2c (M_cv of Alg. 3), cull at
+ *    z <= near_z, depth = camera z;
+ *  - Sigma' = J W Sigma W^T J^T (the affine EWA approximation of the same
+ *    section), conic (Sigma' + s I)^-1 and opacity compensation
+ *    sqrt(det Sigma' / det(Sigma' + s I)) (appendix "Forward Pass", Alg. 1);
+ *  - the 2D skew (beta_x, beta_y) of Alg. 1 from the 3D skew vector of
+ *    Sec. "3D Skew Gaussian Kernel", as the skew-normal marginal under the
+ *    same affine map and filter;
+ *  - the extent where alpha can reach alpha_min (the Gaussian's ellipse,
+ *    cut by the half-plane where 1 + erf(z) is large enough) as a tile rect
+ *    and an exact per-row tile count.
+ * cams_host / cams_dev: the same n_views laid-out cameras.  Outputs in g
+ * (caller-allocated, sizes from sgs_geom_rec_floats and
+ * sgs_geom_block_entries); every entry is overwritten.  The instance count
+ * in block_off saturates at 0xffffffff (more than one sort launch can
+ * take).  EINVAL: null pointers, n < 0, sh_degree > 3, bad options or
+ * cameras; EUNSUPPORTED: n * n_views >= 2^32 records. */
 sgs_status sgs_preprocess(const sgs_params* p, const sgs_camera* cams_host,
                           const sgs_camera* cams_dev, int32_t n_views,
                           const sgs_options* opt, const sgs_geom* g, void* stream);
 
-/* Writes, for each record with tiles > 0 and each tile its extent reaches
+/* The tile pipeline's duplication and sort (Sec. "Preliminary of 3D
+ * Gaussian Splatting": a tile-based pipeline blends each pixel's Gaussians
+ * in near-to-far order; Alg. 1 walks each tile's list front to back).  Writes,
+ * for each record with tiles > 0 and each tile its extent reaches
  * (row-major inside its rect: per tile row, the columns whose pixel centres
  * the evaluation ellipse reaches, cut by the skew half-plane), one instance,
  * sorts them stably by (global tile, depth) (ties keep record order) and
- * extracts tile_ranges[t] = [start, end).
+ * extracts tile_ranges[t] = [start, end).  One call sorts at most
+ * 2^32 - 2 instances (32-bit positions and counts).
  *  keys          [inst_capacity] u64 (tile<<32 | float bits of depth), sorted;
  *                may be NULL (then not written) in sort_mode 1.
  *  vals          [inst_capacity] u32 record index m, sorted.
