@@ -390,13 +390,14 @@ def _margins(at, order_depth, opt, rel, cond=None):
     stopped = ta < opt.t_min
     upto = torch.cumsum(stopped.to(torch.int64), 1) <= 1     # up to the stop point
     amb |= (((ta - opt.t_min).abs() <= rel["T"] * opt.t_min) & (a > 0) & upto).any(1)
-    # depth ties: runs of consecutive ordered Gaussians with nearly equal z
+    # depth ties: two Gaussians that reach the pixel, consecutive among those
+    # that do, with nearly equal z may be composited in either order
     z = order_depth
     if z.numel() > 1:
-        tie = (z[1:] - z[:-1]).abs() <= rel["depth"] * z[1:].abs()
         reach = (at >= opt.alpha_min * (1 - rel["alpha"])) & upto
-        for k in torch.nonzero(tie).flatten().tolist():
-            amb |= reach[:, k] & reach[:, k + 1]
+        for p in torch.nonzero(reach.sum(1) > 1).flatten().tolist():
+            zp = z[reach[p]]
+            amb[p] |= bool(((zp[1:] - zp[:-1]).abs() <= rel["depth"] * zp[1:].abs()).any())
     return amb
 
 
@@ -571,3 +572,92 @@ def densify_stats(scene, pose_or_cam, dL_dC: np.ndarray, pixels: np.ndarray | No
             reach[idx[hit].numpy()] = True
     return {"uv": np.sqrt((ndc * ndc).sum(1)), "z": z, "reach": reach,
             "valid": pr0.valid.numpy().copy(), "dL_dmu2d": g_shift.detach().numpy()}
+
+
+# ------------------------------------------------------------ densification
+@dataclass
+class DensifyOptions:
+    tau_uv: float = 0.001        # the appendix's threshold of the 2D gradient statistic
+    tau_z: float = 0.001         # reading: the same threshold for the depth gradient g_z
+    dense_scale: float = 0.01    # 3DGS: Gaussians larger than this are split, smaller cloned
+    split_shrink: float = 1.6    # 3DGS: child scale = parent scale / 1.6
+
+
+def densify_decisions(log_scale: np.ndarray, uv_sum, view_count, z_max,
+                      opt: DensifyOptions = DensifyOptions()) -> np.ndarray:
+    """Clone / split selection of Sec. "Depth-Aware Densification Strategy":
+    a Gaussian is densified when its mean screen-space gradient norm (the
+    accumulated g_uv over the views that saw it, divided by their number)
+    reaches tau_uv, or when its depth gradient g_z (Eq. depth_grad) reaches
+    tau_z; it is split when its largest scale exceeds dense_scale, else
+    cloned.  The comparisons are float decisions that pick an integer, so
+    they are taken in float32 (the kernel's precision).  log_scale [3][N];
+    returns int8 [N]: 0 keep, 1 clone, 2 split."""
+    n = log_scale.shape[1]
+    f32 = np.float32
+    sel = np.zeros(n, bool)
+    if uv_sum is not None:
+        cnt = np.asarray(view_count).astype(f32)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            avg = np.where(cnt > 0, np.asarray(uv_sum, f32) / np.where(cnt > 0, cnt, f32(1)), f32(0))
+        sel |= avg >= f32(opt.tau_uv)
+    if z_max is not None:
+        sel |= np.asarray(z_max, f32) >= f32(opt.tau_z)
+    big = np.asarray(log_scale, f32).max(0) > f32(math.log(opt.dense_scale))
+    return np.where(sel, np.where(big, 2, 1), 0).astype(np.int8)
+
+
+def skew_normal_moments(sigma3: np.ndarray, beta: np.ndarray):
+    """Mean offset and covariance of the normalised 3D skew-normal density
+    2 phi(x; 0, Sigma) Phi(beta^T x) (the paper's kernel, normalised):
+    delta = Sigma beta / sqrt(1 + beta^T Sigma beta), mean sqrt(2/pi) delta,
+    covariance Sigma - (2/pi) delta delta^T (Azzalini & Dalla Valle 1996)."""
+    sb = sigma3 @ beta
+    delta = sb / math.sqrt(1.0 + float(beta @ sb))
+    return math.sqrt(2.0 / math.pi) * delta, sigma3 - (2.0 / math.pi) * np.outer(delta, delta), delta
+
+
+def densify(scene, decisions: np.ndarray, opt: DensifyOptions = DensifyOptions()) -> dict:
+    """The new Gaussian set of a densification step (float64): in input order,
+    kept Gaussians once, cloned ones twice, split ones as two children.
+    Reading of the split (the paper's split figure: along the largest axis,
+    children's scales adjusted to the skew): child scale along the largest
+    axis e is s_max / split_shrink, every other attribute the parent's; the
+    two children are placed on e so that, as equal-weight skew-normal
+    densities, they have the parent's mean and the parent's variance along
+    e.  Returns SoA arrays like the scene's plus the parent index."""
+    n = scene.n
+    ls = scene.log_scale.astype(np.float64)
+    R = quat_to_rotmat(torch.from_numpy(scene.quat.T.astype(np.float64))).numpy()
+    outs = {k: [] for k in ("mean", "log_scale", "parent")}
+    for i in range(n):
+        d = int(decisions[i])
+        mu = scene.mean[:, i].astype(np.float64)
+        if d != 2:
+            for _ in range(2 if d == 1 else 1):
+                outs["mean"].append(mu)
+                outs["log_scale"].append(ls[:, i])
+                outs["parent"].append(i)
+            continue
+        s = np.exp(ls[:, i])
+        k = int(np.argmax(ls[:, i]))           # first largest
+        e = R[i][:, k]
+        sc = s.copy()
+        sc[k] = s[k] / opt.split_shrink
+        beta = np.zeros(3) if scene.skew is None else scene.skew[:, i].astype(np.float64)
+        m_p, cov_p, _ = skew_normal_moments(R[i] @ np.diag(s * s) @ R[i].T, beta)
+        m_c, cov_c, _ = skew_normal_moments(R[i] @ np.diag(sc * sc) @ R[i].T, beta)
+        a = math.sqrt(max(float(e @ cov_p @ e) - float(e @ cov_c @ e), 0.0))
+        lc = ls[:, i].copy()
+        lc[k] = math.log(sc[k])
+        for sign in (1.0, -1.0):
+            outs["mean"].append(mu + m_p - m_c + sign * a * e)
+            outs["log_scale"].append(lc)
+            outs["parent"].append(i)
+    parent = np.array(outs["parent"], np.int64)
+    res = {"mean": np.array(outs["mean"]).T.reshape(3, -1), "log_scale": np.array(outs["log_scale"]).T.reshape(3, -1),
+           "parent": parent}
+    for f in ("quat", "skew", "opa_logit", "opa2_logit", "opa_dir", "sh"):
+        v = getattr(scene, f)
+        res[f] = None if v is None else v[..., parent].astype(np.float64)
+    return res

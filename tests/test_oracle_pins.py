@@ -742,3 +742,87 @@ def test_float32_error_bound_covers_rounding_and_is_first_order_tight():
             tight += np.abs(d) * a_p[j] * u * pt[p, k]
         np.testing.assert_allclose(np.concatenate([bC[p], [bT[p]]]), tight, rtol=1e-5,
                                    atol=1e-9 * tight.max())
+
+
+# ------------------------------------------------------------ densification
+def test_densify_decisions_by_hand():
+    """Thresholds of the selection (mean uv statistic, depth gradient) and the
+    clone / split choice by the largest scale, on hand-made statistics."""
+    ls = np.log(np.array([[0.005, 0.02, 0.005, 0.02, 0.005, 0.02],
+                          [0.001, 0.001, 0.009, 0.001, 0.001, 0.001],
+                          [0.002, 0.003, 0.001, 0.004, 0.001, 0.001]], np.float32))
+    uv = np.array([0.003, 0.003, 0.0, 0.0019, 0.0, 0.0], np.float32)
+    cnt = np.array([2, 3, 0, 2, 0, 5], np.uint32)
+    z = np.array([0.0, 0.0, 0.0, 0.0, 0.002, 0.0005], np.float32)
+    d = O.densify_decisions(ls, uv, cnt, z)
+    # 0: mean 0.0015 >= 1e-3, small -> clone; 1: mean 1e-3 (float32) >= 1e-3, large -> split;
+    # 2: unseen -> keep; 3: mean 0.00095 -> keep; 4: g_z -> clone; 5: below both -> keep
+    np.testing.assert_array_equal(d, [1, 2, 0, 0, 1, 0])
+    np.testing.assert_array_equal(O.densify_decisions(ls, None, None, z), [0, 0, 0, 0, 1, 0])
+
+
+@pytest.mark.parametrize("b", [-3.0, 0.7, 5.0])
+def test_skew_normal_moments_match_scipy_on_an_axis(b):
+    """Diagonal Sigma and skew along one axis: the marginal is the 1D skew
+    normal 2 phi(x; s) Phi(b x), whose mean and variance scipy gives."""
+    from scipy.stats import skewnorm
+    s = np.array([0.3, 0.8, 0.5])
+    beta = np.array([0.0, b, 0.0])
+    mean, cov, _ = O.skew_normal_moments(np.diag(s * s), beta)
+    ref = skewnorm(b * s[1], scale=s[1])
+    assert mean[1] == pytest.approx(ref.mean(), rel=1e-12)
+    assert cov[1, 1] == pytest.approx(ref.var(), rel=1e-12)
+    assert mean[0] == 0.0 and mean[2] == 0.0 and cov[0, 0] == pytest.approx(s[0] ** 2)
+
+
+def _sample_skew_normal(rng, mu, sigma3, beta, n):
+    """Azzalini's stochastic representation of 2 phi(x - mu; Sigma) Phi(beta.(x - mu)):
+    x = mu + delta |u0| + v, v ~ N(0, Sigma - delta delta^T)."""
+    _, _, delta = O.skew_normal_moments(sigma3, beta)
+    L = np.linalg.cholesky(sigma3 - np.outer(delta, delta) + 1e-15 * np.eye(3))
+    return mu + np.abs(rng.normal(size=(n, 1))) * delta + rng.normal(size=(n, 3)) @ L.T
+
+
+def test_split_children_keep_the_parents_mean_and_axis_variance():
+    """Samples of the two children (equal weights) against samples of the
+    parent: same 3D mean, same variance along the split axis, the split axis
+    being the parent's largest; with zero skew the children sit at
+    +- s sqrt(1 - 1/1.6^2) on that axis with scale s / 1.6."""
+    rng = np.random.default_rng(7)
+    sc = S.blobs_scene(3, 4, 0)
+    sc.log_scale[:] = np.log(np.array([[0.4, 0.1, 0.2, 0.3], [0.1, 0.5, 0.2, 0.1], [0.2, 0.1, 0.6, 0.1]], np.float32))
+    sc.skew[:, 3] = 0.0
+    d = np.full(4, 2, np.int8)
+    out = O.densify(sc, d)
+    assert out["mean"].shape == (3, 8) and (out["parent"] == np.repeat(np.arange(4), 2)).all()
+    R = O.quat_to_rotmat(torch.from_numpy(sc.quat.T.astype(np.float64))).numpy()
+    n = 400_000
+    for i in range(4):
+        s = np.exp(sc.log_scale[:, i].astype(np.float64))
+        k = int(np.argmax(s))
+        e = R[i][:, k]
+        beta = sc.skew[:, i].astype(np.float64)
+        par = _sample_skew_normal(rng, sc.mean[:, i].astype(np.float64), R[i] @ np.diag(s * s) @ R[i].T, beta, n)
+        kids = []
+        for c in (2 * i, 2 * i + 1):
+            sk = np.exp(out["log_scale"][:, c])
+            assert sk[k] == pytest.approx(s[k] / 1.6) and np.delete(sk, k) == pytest.approx(np.delete(s, k))
+            kids.append(_sample_skew_normal(rng, out["mean"][:, c], R[i] @ np.diag(sk * sk) @ R[i].T, beta, n // 2))
+        kids = np.concatenate(kids)
+        se = np.sqrt(np.diag(np.cov(par.T)) / n).max()
+        np.testing.assert_allclose(kids.mean(0), par.mean(0), atol=6 * se)
+        vp, vk = (par @ e).var(), (kids @ e).var()
+        assert vk == pytest.approx(vp, rel=0.02)
+        if i == 3:   # zero skew: the textbook symmetric split
+            a = s[k] * math.sqrt(1 - 1 / 1.6 ** 2)
+            np.testing.assert_allclose(out["mean"][:, 6] - sc.mean[:, 3], a * e, atol=1e-6)
+            np.testing.assert_allclose(out["mean"][:, 7] - sc.mean[:, 3], -a * e, atol=1e-6)
+
+
+def test_densify_keeps_and_clones_copy_the_attributes():
+    sc = S.blobs_scene(5, 6, 1)
+    d = np.array([0, 1, 0, 1, 0, 0], np.int8)
+    out = O.densify(sc, d)
+    assert (out["parent"] == [0, 1, 1, 2, 3, 3, 4, 5]).all()
+    np.testing.assert_array_equal(out["mean"], sc.mean[:, out["parent"]].astype(np.float64))
+    np.testing.assert_array_equal(out["sh"], sc.sh[..., out["parent"]].astype(np.float64))
