@@ -154,6 +154,45 @@ def sh_basis(deg: int, d: torch.Tensor) -> torch.Tensor:
     return torch.stack(out, 1)
 
 
+# ------------------------------------------------------------ depth key
+def fma_f32(a, b, c) -> np.ndarray:
+    """Correctly rounded float32 fused multiply-add a * b + c of float32
+    arrays (IEEE 754 fusedMultiplyAdd, round to nearest even): the product
+    of two float32 values is exact in float64; TwoSum (Knuth) gives the sum
+    s + e exactly; rounding s to float32 is then correct except when s is a
+    float32 midpoint, where the sign of e (or evenness, when e = 0) decides."""
+    a = np.asarray(a, np.float32).astype(np.float64)
+    b = np.asarray(b, np.float32).astype(np.float64)
+    c = np.asarray(c, np.float32).astype(np.float64)
+    p = a * b                                   # exact (48-bit significand)
+    s = p + c
+    bb = s - p
+    e = (p - (s - bb)) + (c - bb)               # s + e == p + c exactly
+    r = s.astype(np.float32)
+    d = s - r.astype(np.float64)
+    up = np.nextafter(r, np.float32(np.inf))
+    dn = np.nextafter(r, np.float32(-np.inf))
+    half_up = (up.astype(np.float64) - r.astype(np.float64)) / 2
+    half_dn = (r.astype(np.float64) - dn.astype(np.float64)) / 2
+    # s on a midpoint: r is the even neighbour; move if e points the other way
+    mid_up = (d == half_up) & (half_up > 0)     # s = r + half ulp: tie broken downwards to r
+    mid_dn = (d == -half_dn) & (half_dn > 0)    # s = r - half ulp: tie broken upwards to r
+    r = np.where(mid_up & (e > 0), up, r)
+    r = np.where(mid_dn & (e < 0), dn, r)
+    return r.astype(np.float32)
+
+
+def depth_key(mean_f32: np.ndarray, cam: Camera) -> np.ndarray:
+    """Camera-space depth as the float32 key of ordering and near culling:
+    z = fma(r20, x, fma(r21, y, fma(r22, z, t2))) in float32 from the float32
+    means and the float32-rounded third row of w2c, every fma correctly
+    rounded, so that any implementation of this expression gets the same bits
+    (reading R17: order by camera z, ties by index)."""
+    W = cam.w2c[2, :4].astype(np.float32)
+    x, y, z = (np.asarray(mean_f32[k], np.float32) for k in range(3))
+    return fma_f32(W[0], x, fma_f32(W[1], y, fma_f32(W[2], z, W[3])))
+
+
 # ----------------------------------------------------------- per Gaussian
 def quat_to_rotmat(q: torch.Tensor) -> torch.Tensor:
     """Unit-quaternion rotation matrix, q = (w, x, y, z) normalised first."""
@@ -190,14 +229,17 @@ class Projected:
     rgb: torch.Tensor       # [N,3]
     depth: torch.Tensor     # [N] camera-space z
     valid: torch.Tensor     # [N] bool (not culled)
+    z32: torch.Tensor | None = None   # [N] float32 depth key (ordering and near cull)
 
 
-def to_tensors(scene, requires_grad=False) -> dict:
-    """Scene arrays (float32 SoA) -> float64 [N, ...] leaf tensors."""
+def to_tensors(scene, requires_grad=False, dtype=F64) -> dict:
+    """Scene arrays (float32 SoA) -> float64 [N, ...] leaf tensors (float32
+    with dtype=torch.float32: used only to size the decision margins)."""
+    npt = np.float64 if dtype == F64 else np.float32
     def t(a, shape_fn):
         if a is None:
             return None
-        x = torch.from_numpy(np.ascontiguousarray(shape_fn(np.asarray(a, np.float64))))
+        x = torch.from_numpy(np.ascontiguousarray(shape_fn(np.asarray(a, npt))))
         return x.requires_grad_(requires_grad)
     return {
         "mean": t(scene.mean, lambda a: a.T),
@@ -219,17 +261,21 @@ def project(P: dict, sh_degree: int, cam: Camera, opt: Options = Options(),
     for the gradient with respect to the 2D means, zero in every render."""
     mean = P["mean"]
     n = mean.shape[0]
+    dt = mean.dtype
     # Sigma = R S S^T R^T
     s = torch.exp(P["log_scale"])
     R = quat_to_rotmat(P["quat"])
     M = R * s[:, None, :]
     sigma3 = M @ M.transpose(1, 2)
     # world -> camera (OpenCV)
-    Wr = torch.from_numpy(cam.w2c[:3, :3].copy())
-    tv = torch.from_numpy(cam.w2c[:3, 3].copy())
+    Wr = torch.from_numpy(cam.w2c[:3, :3].copy()).to(dt)
+    tv = torch.from_numpy(cam.w2c[:3, 3].copy()).to(dt)
     t = mean @ Wr.T + tv
     tx, ty, tz = t.unbind(1)
-    valid = tz > cam.near
+    # order and near cull by the float32 depth key (the projection itself
+    # uses the full-precision tz)
+    z32 = torch.from_numpy(depth_key(mean.detach().numpy().T.astype(np.float32), cam).astype(np.float64))
+    valid = (z32 > float(np.float32(cam.near))) & torch.isfinite(z32)
     fx, fy, cx, cy = cam.K[0, 0], cam.K[1, 1], cam.K[0, 2], cam.K[1, 2]
     tzs = torch.where(valid, tz, torch.ones_like(tz))      # culled rows: harmless values
     limx = opt.guard * (cam.W / (2.0 * fx))
@@ -243,7 +289,7 @@ def project(P: dict, sh_degree: int, cam: Camera, opt: Options = Options(),
     ], 1)
     A = J @ Wr
     sig2 = A @ sigma3 @ A.transpose(1, 2)
-    eye = torch.eye(2, dtype=F64)
+    eye = torch.eye(2, dtype=dt)
     sigf = sig2 + opt.filter_s * eye
     det2 = sig2[:, 0, 0] * sig2[:, 1, 1] - sig2[:, 0, 1] * sig2[:, 1, 0]
     detf = sigf[:, 0, 0] * sigf[:, 1, 1] - sigf[:, 0, 1] * sigf[:, 1, 0]
@@ -263,20 +309,20 @@ def project(P: dict, sh_degree: int, cam: Camera, opt: Options = Options(),
     if P.get("skew") is not None and not opt.symmetric:
         beta2d = skew_to_2d(P["skew"], sigma3, A, Q)
     else:
-        beta2d = torch.zeros((n, 2), dtype=F64)
+        beta2d = torch.zeros((n, 2), dtype=dt)
     w2d = None
     if P.get("opa2_logit") is not None:
-        g = P["opa_dir"] if P.get("opa_dir") is not None else torch.zeros((n, 3), dtype=F64)
+        g = P["opa_dir"] if P.get("opa_dir") is not None else torch.zeros((n, 3), dtype=dt)
         if P.get("skew") is not None:
             g = g + P["skew"]
         w2d = skew_to_2d(g, sigma3, A, Q)
     # view-dependent colour from SH
-    campos = torch.from_numpy(cam.position.copy())
+    campos = torch.from_numpy(cam.position.copy()).to(dt)
     dvec = mean - campos
     dirs = dvec / torch.linalg.norm(dvec, dim=1, keepdim=True)
     Y = sh_basis(sh_degree, dirs)                           # [N, K]
     rgb = torch.clamp((Y[:, :, None] * P["sh"]).sum(1) + 0.5, min=0.0)
-    return Projected(mu2d, conic, rho, o1, o2, beta2d, w2d, rgb, tz, valid)
+    return Projected(mu2d, conic, rho, o1, o2, beta2d, w2d, rgb, tz, valid, z32)
 
 
 # ------------------------------------------------------------ per pixel
@@ -292,6 +338,7 @@ def alpha_tilde(pc: torch.Tensor, pr: Projected, idx: torch.Tensor, opt: Options
     """Unclamped 2D opacity of Gaussians ``idx`` at pixel centres pc [P,2]:
     alpha~ = rho o(delta) G'(delta) (1 + erf(beta . delta / sqrt 2)), with
     G' = exp(-(a dx^2 + c dy^2)/2 - b dx dy) (Alg. 1).  Returns [P, len(idx)]."""
+    pc = pc.to(pr.mu2d.dtype)
     mu = pr.mu2d[idx]
     dx = pc[:, None, 0] - mu[None, :, 0]
     dy = pc[:, None, 1] - mu[None, :, 1]
@@ -326,11 +373,42 @@ def power_terms(pc: torch.Tensor, pr: Projected, idx: torch.Tensor) -> torch.Ten
 
 
 def depth_order(pr: Projected) -> torch.Tensor:
-    """Valid Gaussians sorted near to far by camera z, ties by index."""
+    """Valid Gaussians sorted near to far by the float32 depth key, ties by
+    index."""
     idx = torch.nonzero(pr.valid).flatten()
-    key = pr.depth.detach()[idx].numpy()
+    key = (pr.z32 if pr.z32 is not None else pr.depth.detach())[idx].numpy()
     order = np.argsort(key, kind="stable")
     return idx[torch.from_numpy(order)]
+
+
+def inclusion_with(at: torch.Tensor, opt: Options, keep: torch.Tensor) -> torch.Tensor:
+    """The inclusion rule with the alpha_min decisions given (keep [P,K]):
+    the pixel still stops before the first kept pair whose T_{k+1} would fall
+    below t_min."""
+    alpha = torch.clamp(at, max=opt.alpha_max)
+    a = torch.where(keep, alpha, torch.zeros_like(alpha))
+    live = torch.cumprod(1.0 - a, dim=1) >= opt.t_min
+    return keep & live
+
+
+def composite_pixel(at: np.ndarray, rgb: np.ndarray, bg: np.ndarray, opt: Options,
+                    flip_keep=(), flip_stop=()) -> np.ndarray:
+    """One pixel's front-to-back compositing written as the Alg. 1 loop (at
+    [K] unclamped alpha in depth order, rgb [K,3]), with the alpha_min
+    decision of the pairs in flip_keep and the stop decision of the pairs in
+    flip_stop taken the other way.  Returns (C, T) as [4]."""
+    T = 1.0
+    C = np.zeros(3)
+    for k in range(len(at)):
+        a = min(opt.alpha_max, float(at[k]))
+        if (a >= opt.alpha_min) == (k in flip_keep):
+            continue
+        Tn = T * (1.0 - a)
+        if (Tn < opt.t_min) != (k in flip_stop):
+            break
+        C = C + rgb[k] * (a * T)
+        T = Tn
+    return np.concatenate([C + T * np.asarray(bg, np.float64), [T]])
 
 
 def inclusion(at: torch.Tensor, opt: Options) -> torch.Tensor:
@@ -369,40 +447,95 @@ class RenderResult:
     T: np.ndarray            # [P]
     last: np.ndarray         # [P] index of the last contributing Gaussian (-1 if none)
     n_contrib: np.ndarray    # [P]
-    ambiguous: np.ndarray    # [P] bool: a decision within the margins below
+    ambiguous: np.ndarray    # [P] bool: a decision of the image within the margins below
+    # ambiguous pixels whose only uncertain decisions are alpha >= alpha_min
+    # (at most MAX_FLIPS of them): (C, T) of every combination of those
+    # decisions, as rows [n_alt, 4] of alt_rows[alt_start[p]:alt_start[p+1]];
+    # an empty range for pixels without alternatives
+    alt_start: np.ndarray | None = None   # [P+1]
+    alt_rows: np.ndarray | None = None    # [*, 4]
+    # ambiguous for a gradient: also alpha~ within the margins of the 0.99
+    # clamp, where the derivative of alpha jumps
+    ambiguous_grad: np.ndarray | None = None
 
 
-def _margins(at, order_depth, opt, rel, cond=None):
+MAX_FLIPS = 4
+
+
+def skew_factor(pc: torch.Tensor, pr: Projected, idx: torch.Tensor, opt: Options) -> torch.Tensor:
+    """1 + erf(beta . delta / sqrt 2) of Gaussians ``idx`` at pixel centres
+    pc [P,2] (1 in the symmetric mode).  Returns [P, len(idx)]."""
+    pc = pc.to(pr.mu2d.dtype)
+    mu = pr.mu2d[idx]
+    dx = pc[:, None, 0] - mu[None, :, 0]
+    dy = pc[:, None, 1] - mu[None, :, 1]
+    if opt.symmetric:
+        return torch.ones_like(dx)
+    bx, by = pr.beta2d[idx].unbind(1)
+    return 1.0 + torch.erf((bx * dx + by * dy) / SQRT2)
+
+
+def _margins(at, order_depth, opt, rel, cond=None, pair_extra=None, detail=False):
     """Per-pixel flag: some decision of the definition lies within a relative
     margin of its threshold, where float32 evaluation may legitimately
     decide the other way (alpha vs 1/255 or vs the 0.99 clamp, T(1-alpha) vs
     the stop level, two reaching Gaussians at equal depth).  Alpha margins
     are on the log scale, |ln(alpha~ / threshold)| <= margin, and a pair's
     grows by rel["cond"] times its power_terms (cond): rounding the stored
-    exponent's terms scales alpha~ by exp(+-rel["cond"] * power_terms)."""
+    exponent's terms scales alpha~ by exp(+-rel["cond"] * power_terms).
+    pair_extra [P,K]: a further per-pair margin on the same log scale.
+    detail: also return the per-pair alpha_min flags [P,K] (pairs up to the
+    stop point) and the per-pixel flag of the other kinds of ambiguity."""
     ra = rel["alpha"] if cond is None else rel["alpha"] + rel.get("cond", 0.0) * cond
+    if pair_extra is not None:
+        ra = ra + pair_extra
     la = torch.log(at.clamp_min(1e-300))
-    amb = ((la - math.log(opt.alpha_min)).abs() <= ra).any(1)
-    amb |= ((la - math.log(opt.alpha_max)).abs() <= ra).any(1)
     alpha = torch.clamp(at, max=opt.alpha_max)
     a = torch.where(alpha >= opt.alpha_min, alpha, torch.zeros_like(alpha))
     ta = torch.cumprod(1.0 - a, 1)
     stopped = ta < opt.t_min
     upto = torch.cumsum(stopped.to(torch.int64), 1) <= 1     # up to the stop point
-    amb |= (((ta - opt.t_min).abs() <= rel["T"] * opt.t_min) & (a > 0) & upto).any(1)
-    # depth ties: two Gaussians that reach the pixel, consecutive among those
-    # that do, with nearly equal z may be composited in either order
+    flip = ((la - math.log(opt.alpha_min)).abs() <= ra) & upto
+    tflip = ((ta - opt.t_min).abs() <= rel["T"] * opt.t_min) & (a > 0) & upto
+    amb = flip.any(1) | tflip.any(1)
+    other = torch.zeros_like(amb)
+    # alpha near the 0.99 clamp changes no decision of the image (both sides'
+    # alpha differ by the same rounding either way) but the derivative there
+    # jumps: flagged for gradients only
+    clamp = ((la - math.log(opt.alpha_max)).abs() <= ra).any(1)
+    # depth keys: both sides order by the same float32 key and break equal
+    # keys by index; two Gaussians that reach the pixel, consecutive among
+    # those that do, whose keys differ by a few float32 ulps at most could
+    # only swap if a key's bits differed between implementations (from w2c
+    # rounded differently): flagged
     z = order_depth
-    if z.numel() > 1:
+    if z.numel() > 1 and rel.get("depth", 0.0) > 0:
         reach = (at >= opt.alpha_min * (1 - rel["alpha"])) & upto
         for p in torch.nonzero(reach.sum(1) > 1).flatten().tolist():
             zp = z[reach[p]]
-            amb[p] |= bool(((zp[1:] - zp[:-1]).abs() <= rel["depth"] * zp[1:].abs()).any())
-    return amb
+            dz = (zp[1:] - zp[:-1]).abs()
+            if bool(((dz > 0) & (dz <= rel["depth"] * zp[1:].abs())).any()):
+                amb[p] = True
+                other[p] = True
+    return (amb, flip, tflip, other, amb | clamp) if detail else amb | clamp
 
 
-# relative margins; "cond": 2^-23 (two float32 half-ulps) per unit of power_terms
-DEFAULT_MARGINS = {"alpha": 2e-4, "T": 2e-3, "depth": 1e-6, "cond": 2.0 ** -23}
+# Margins where a float32 pipeline may decide a threshold the other way, on
+# the log scale of alpha~ (reading R18):
+#   "alpha": a floor (the blend's own rounding: exp2, products, the stored
+#            log of the opacity factor: a few float32 ulps of an exponent <= 8)
+#   "cond":  2^-23 (two float32 half-ulps) per unit of power_terms (rounding
+#            of the stored mean and conic)
+#   "fp32":  times |ln alpha~_f32 - ln alpha~|, the change when the same
+#            projection and alpha are evaluated in float32 from the float32
+#            inputs (the size of the projection's float32 error for this pair)
+#   "erf":   an absolute error of 1 + erf(z) (a float32 erfc approximation with
+#            |error| <= 1.5e-7 plus its own rounding), divided by 1 + erf(z)
+# T: relative margin of T(1 - alpha) against t_min; depth: relative
+# difference of two float32 depth keys (2 ulps) below which their order is
+# flagged (see _margins).
+DEFAULT_MARGINS = {"alpha": 1e-5, "cond": 2.0 ** -22, "fp32": 8.0, "erf": 3e-7,
+                   "T": 2e-3, "depth": 0.0}
 
 
 def render(scene, pose_or_cam, pixels: np.ndarray | None = None, opt: Options = Options(),
@@ -416,11 +549,18 @@ def render(scene, pose_or_cam, pixels: np.ndarray | None = None, opt: Options = 
         pixels, pc = pixel_centres(cam, pixels)
         bg = torch.from_numpy(cam.bg.astype(np.float64))
         rgb = pr.rgb[order]
-        od = pr.depth[order]
+        od = pr.z32[order]
         n_pix = pc.shape[0]
+        # the same projection in float32 (margins only: it sizes how far a
+        # float32 pipeline's alpha~ may sit from the FP64 value)
+        pr32 = project(to_tensors(scene, dtype=torch.float32), scene.sh_degree, cam, opt) \
+            if margins.get("fp32", 0.0) > 0 else None
+        bad32 = None if pr32 is None else ~pr32.valid[order]
         col = np.zeros((n_pix, 3)); Tf = np.ones(n_pix)
         last = np.full(n_pix, -1, np.int64); ncon = np.zeros(n_pix, np.int64)
         amb = np.zeros(n_pix, bool)
+        amb_grad = np.zeros(n_pix, bool)
+        alts = {}
         step = max(1, chunk_elems // max(1, order.numel()))
         for s in range(0, n_pix, step):
             pcs = pc[s:s + step]
@@ -434,8 +574,43 @@ def render(scene, pose_or_cam, pixels: np.ndarray | None = None, opt: Options = 
             lastpos = torch.where(inc, torch.arange(k).expand_as(inc), torch.full_like(inc, -1, dtype=torch.int64)).max(1).values if k else torch.full((pcs.shape[0],), -1)
             last[s:s + step] = np.where(lastpos.numpy() >= 0, order.numpy()[np.maximum(lastpos.numpy(), 0)], -1)
             cond = power_terms(pcs, pr, order) if margins.get("cond", 0.0) > 0 else None
-            amb[s:s + step] = _margins(at, od, opt, margins, cond).numpy()
-    return RenderResult(pixels, col, Tf, last, ncon, amb)
+            # per-pair margins, on the pairs near a threshold only (far below
+            # it neither term can move a decision, and float32 underflows)
+            la = torch.log(at.clamp_min(1e-300))
+            near = ((la - math.log(opt.alpha_min)).abs() < 0.5) | ((la - math.log(opt.alpha_max)).abs() < 0.5)
+            extra = torch.zeros_like(la)
+            if pr32 is not None:
+                la32 = torch.log(alpha_tilde(pcs, pr32, order, opt).double().clamp_min(1e-300))
+                dl = (la32 - la).abs().clamp_max(1e-2)
+                # a Gaussian the float32 projection culls gets a wide margin
+                dl = torch.where(bad32[None, :] | ~torch.isfinite(dl), torch.full_like(dl, 1e-2), dl)
+                extra = extra + margins["fp32"] * dl
+            if margins.get("erf", 0.0) > 0:
+                extra = extra + (margins["erf"] / skew_factor(pcs, pr, order, opt).clamp_min(1e-300)).clamp_max(1e-2)
+            extra = torch.where(near, extra, torch.zeros_like(extra))
+            a_, flip, tflip, other, ag = _margins(at, od, opt, margins, cond, extra, detail=True)
+            amb[s:s + step] = a_.numpy()
+            amb_grad[s:s + step] = ag.numpy()
+            # every outcome of the uncertain decisions of a pixel: each
+            # alpha_min decision and each stop decision near its threshold
+            # taken either way
+            for q in torch.nonzero(a_ & ~other).flatten().tolist():
+                fa = torch.nonzero(flip[q]).flatten().tolist()
+                ft = torch.nonzero(tflip[q]).flatten().tolist()
+                if len(fa) + len(ft) > MAX_FLIPS:
+                    continue
+                atq = at[q].numpy()
+                rows = []
+                for bits in range(1 << (len(fa) + len(ft))):
+                    fa_set = {k for j, k in enumerate(fa) if (bits >> j) & 1}
+                    ft_set = {k for j, k in enumerate(ft) if (bits >> (len(fa) + j)) & 1}
+                    rows.append(composite_pixel(atq, rgb.numpy(), cam.bg, opt, fa_set, ft_set))
+                alts[s + q] = np.array(rows)
+    starts = np.zeros(n_pix + 1, np.int64)
+    for q in range(n_pix):
+        starts[q + 1] = starts[q] + (len(alts[q]) if q in alts else 0)
+    rows = np.concatenate([alts[q] for q in sorted(alts)]) if alts else np.zeros((0, 4))
+    return RenderResult(pixels, col, Tf, last, ncon, amb, starts, rows, amb_grad)
 
 
 def float32_error_bound(scene, pose_or_cam, pixels: np.ndarray | None = None, opt: Options = Options(),

@@ -826,3 +826,87 @@ def test_densify_keeps_and_clones_copy_the_attributes():
     assert (out["parent"] == [0, 1, 1, 2, 3, 3, 4, 5]).all()
     np.testing.assert_array_equal(out["mean"], sc.mean[:, out["parent"]].astype(np.float64))
     np.testing.assert_array_equal(out["sh"], sc.sh[..., out["parent"]].astype(np.float64))
+
+
+# ------------------------------------------------------------ depth key and margins
+def _round_f32_exact(fr):
+    """Correct round-to-nearest-even of a Fraction to float32 (by comparing
+    the three float32 neighbours of the double nearest to it)."""
+    from fractions import Fraction
+    if fr == 0:
+        return np.float32(0)
+    f = np.float32(float(fr))
+    best = None
+    for cand in (np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))):
+        d = abs(Fraction(float(cand)) - fr)
+        even = (int(np.float32(cand).view(np.uint32)) & 1) == 0
+        if best is None or d < best[0] or (d == best[0] and even):
+            best = (d, cand)
+    return best[1]
+
+
+def test_fma_f32_is_correctly_rounded():
+    """Against exact rational arithmetic, on random triples and on triples
+    whose exact result is a rounding error (c = -fl(a b)) or sits on a
+    float32 midpoint."""
+    from fractions import Fraction
+    rng = np.random.default_rng(0)
+    n = 3000
+    a = rng.normal(size=n).astype(np.float32)
+    b = rng.normal(size=n).astype(np.float32)
+    c = rng.normal(size=n).astype(np.float32) * np.float32(4.0)
+    c[::3] = -(a[::3].astype(np.float64) * b[::3]).astype(np.float32)
+    # midpoints: a = 1 + 2^-12, b = 1 + 2^-12: a b = 1 + 2^-11 + 2^-24, c = 0 ties-to-even on the 2^-24 bit
+    a[1::7] = np.float32(1 + 2 ** -12)
+    b[1::7] = np.float32(1 + 2 ** -12)
+    c[1::7] = np.float32(0.0)
+    got = O.fma_f32(a, b, c)
+    for i in range(n):
+        ref = _round_f32_exact(Fraction(float(a[i])) * Fraction(float(b[i])) + Fraction(float(c[i])))
+        assert got[i] == ref, (i, a[i], b[i], c[i], got[i], ref)
+
+
+def test_depth_key_is_the_camera_depth_in_float32():
+    sc, pose = S.tiny_config()
+    cam = O.camera_from_pose(pose)
+    z32 = O.depth_key(sc.mean, cam)
+    z64 = (cam.w2c[2, :3] @ sc.mean.astype(np.float64)) + cam.w2c[2, 3]
+    assert z32.dtype == np.float32
+    np.testing.assert_allclose(z32, z64, rtol=4 * 2.0 ** -24, atol=1e-6)
+
+
+def test_composite_pixel_equals_vectorised_compositing_and_flips_one_decision():
+    """The per-pixel loop (used for the outcomes of uncertain decisions)
+    against the vectorised compositing, and a flipped alpha_min decision
+    against compositing with that pair's decision negated."""
+    rng = np.random.default_rng(3)
+    opt = O.Options()
+    for _ in range(30):
+        K = 12
+        at = rng.uniform(0, 1.2, K) * (rng.uniform(size=K) > 0.3)
+        at[rng.integers(0, K)] = 1 / 255 * (1 + 1e-9)
+        rgb = rng.uniform(0, 1, (K, 3))
+        bg = rng.uniform(0, 1, 3)
+        att = torch.from_numpy(at[None, :])
+        inc = O.inclusion(att, opt)
+        C, T = O.composite(att, torch.from_numpy(rgb), torch.from_numpy(bg), inc, opt)
+        got = O.composite_pixel(at, rgb, bg, opt)
+        np.testing.assert_allclose(got, np.concatenate([C.numpy()[0], T.numpy()]), rtol=1e-12, atol=1e-15)
+        k = int(rng.integers(0, K))
+        keep = torch.clamp(att, max=opt.alpha_max) >= opt.alpha_min
+        keep[0, k] = ~keep[0, k]
+        C2, T2 = O.composite(att, torch.from_numpy(rgb), torch.from_numpy(bg), O.inclusion_with(att, opt, keep), opt)
+        np.testing.assert_allclose(O.composite_pixel(at, rgb, bg, opt, flip_keep={k}),
+                                   np.concatenate([C2.numpy()[0], T2.numpy()]), rtol=1e-12, atol=1e-15)
+
+
+def test_ambiguous_pixels_list_their_outcomes():
+    """On the tiny scene every ambiguous pixel lists the outcomes of its
+    uncertain decisions, the first being the oracle's own colour."""
+    sc, pose = S.tiny_config()
+    r = O.render(sc, pose)
+    assert r.ambiguous.mean() < 1e-3
+    for q in np.nonzero(r.ambiguous)[0]:
+        rows = r.alt_rows[r.alt_start[q]:r.alt_start[q + 1]]
+        assert len(rows) >= 2
+        np.testing.assert_allclose(rows[0, :3], r.color[q], atol=1e-12)
