@@ -144,6 +144,12 @@ typedef struct {
                               images (gradients up to the order of float
                               sums), more parallelism per tile.  -1:
                               total_tiles / 128; 0: off.                    */
+  int32_t depth_digit_bits;/* [0] radix digits of the depth presort (sort
+                              mode 1): 8 (4 passes over the 32-bit keys),
+                              10 (3 passes over keys shifted to 30 bits; needs
+                              every near_z > 0 and at most 16.7M records,
+                              else 8 is used), 0: 10 when possible.  Same
+                              order either way.                             */
 } sgs_options;
 
 /* Projected per-record data written by sgs_preprocess, record m = v*N + i for
@@ -154,7 +160,11 @@ typedef struct {
  *   slot 0: (mu_x, mu_y, a, b)   2D mean in pixels, conic (Sigma'+sI)^-1 = [[a,b],[b,c]]
  *   slot 1: (c, beta_x, beta_y, d)  2D skew; d = rho*alpha_1 (rho with enhanced opacity)
  *   slot 2: (r, g, b, log_thr)   colour; log_thr: below this exponent a pair is skipped
- *   slot 3: (alpha_1, alpha_2, w_x, w_y)  with enhanced opacity; unspecified otherwise
+ *   slot 3: (alpha_1, alpha_2, w_x, w_y)  with enhanced opacity; otherwise the
+ *           two words of the record's tile rect (as in `rect`) in .x and .y,
+ *           so that binning gathers one 64-byte line per record
+ * `enhanced` says which: it must equal (p->opa2_logit != NULL) of the
+ * parameters passed to sgs_preprocess (EINVAL otherwise).
  */
 typedef struct {
   float* rec;              /* [M][4][4]                                     */
@@ -165,6 +175,8 @@ typedef struct {
   uint32_t* block_off;     /* [sgs_geom_block_entries(N, V)] exclusive prefix of the
                               tile counts per block of 256 records of one view
                               (view-major); the last entry is the total      */
+  int32_t enhanced;        /* 1: records carry enhanced opacity (slot 3)   */
+  int32_t _pad;
 } sgs_geom;
 
 /* Optional tile scheduling for the blend kernels (device pointers).
@@ -196,7 +208,8 @@ void sgs_default_options(sgs_options* opt);
 
 /* sizeof of the ABI structs, for bindings to check their mirrors:
  * 0 sgs_params, 1 sgs_params_grad, 2 sgs_camera, 3 sgs_options, 4 sgs_geom,
- * 5 sgs_geom_grad, 6 sgs_schedule; 0 for any other value. */
+ * 5 sgs_geom_grad, 6 sgs_schedule, 7 sgs_adam_group, 8 sgs_densify_options,
+ * 9 sgs_densify_out; 0 for any other value. */
 size_t sgs_struct_size(int32_t which);
 const char* sgs_status_string(sgs_status s);
 
@@ -310,15 +323,18 @@ sgs_status sgs_bin_sort_noalloc(const sgs_geom* g, int64_t m, const sgs_camera* 
  * by sgs_bin_sort with the same inst_capacity (ranges are clamped to it).  Outputs (device, per view at
  * its pix_base): out_rgb planes [3][P] (colour + T_final*bg), out_T [P]
  * (final transmittance), out_last [P] (number of range entries up to and
- * including the last contributor, 0 if none), out_count [P] (optional, NULL to
- * skip: number of pairs composited into the pixel). */
+ * including the last contributor, 0 if none), and two optional work
+ * counters (NULL to skip; with both NULL the blend runs without counting):
+ * out_count [P] pairs composited into the pixel, out_eval [P] pairs
+ * evaluated for it (alpha computed: past the exponent test of the skip
+ * rule, before the comparison with alpha_min). */
 sgs_status sgs_render_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals,
                           int64_t inst_capacity, const uint32_t* tile_ranges,
                           const sgs_schedule* sched, const sgs_camera* cams_host,
                           const sgs_camera* cams_dev, int32_t n_views, int32_t enhanced,
                           const sgs_options* opt, float* out_rgb, float* out_T,
-                          uint32_t* out_last, uint32_t* out_count, int64_t total_pixels,
-                          void* stream);
+                          uint32_t* out_last, uint32_t* out_count, uint32_t* out_eval,
+                          int64_t total_pixels, void* stream);
 
 /* Alg. 2 and the chain rule.  Re-walks each pixel's list from its last
  * contributor to the front, rebuilding T from out_T (nothing per pair is
@@ -334,6 +350,105 @@ sgs_status sgs_render_bwd(const sgs_params* p, const sgs_geom* g, int64_t m,
                           const uint32_t* out_last, const float* dL_drgb,
                           int64_t total_pixels, const sgs_geom_grad* g2d,
                           const sgs_params_grad* grad, void* stream);
+
+/* ------------------------------------------------------- densification */
+
+/* Options of sgs_densify; sgs_default_densify_options fills the values in
+ * brackets. */
+typedef struct {
+  float tau_uv;            /* [0.001] threshold of the mean screen-space
+                              gradient norm (the appendix's tau_uv)        */
+  float tau_z;             /* [0.001] threshold of the depth gradient g_z
+                              (not given by the paper: a reading)          */
+  float dense_scale;       /* [0.01] selected Gaussians whose largest scale
+                              exceeds it are split, the others cloned
+                              (3DGS: 0.01 x the scene extent)              */
+  float split_shrink;      /* [1.6] child scale along the split axis is the
+                              parent's divided by this (3DGS's factor)     */
+} sgs_densify_options;
+
+/* Output Gaussian set of sgs_densify: SoA arrays of `capacity` entries
+ * (component j of entry o at j * capacity + o), same fields as sgs_params
+ * (skew / opa2_logit / opa_dir may be NULL when the input has none), plus
+ * the input index each output came from (NULL: not written). */
+typedef struct {
+  int64_t capacity;
+  float* mean;
+  float* log_scale;
+  float* quat;
+  float* skew;
+  float* opa_logit;
+  float* opa2_logit;
+  float* opa_dir;
+  float* sh;
+  uint32_t* parent;
+} sgs_densify_out;
+
+void sgs_default_densify_options(sgs_densify_options* o);
+
+/* Scratch words (u32) of sgs_densify for n Gaussians. */
+int64_t sgs_densify_scratch_words(int64_t n);
+
+/* The densification step of the training loop (Sec. "Depth-Aware
+ * Densification Strategy", Eq. depth_grad; the appendix's tau_uv), from the
+ * statistics the backward accumulates in sgs_params_grad.densify_*.
+ * Decision per Gaussian i, in float32 (decision[i]: 0 keep, 1 clone,
+ * 2 split):
+ *   selected = uv_sum[i] / view_count[i] >= tau_uv (0 when the count is 0)
+ *              or z_max[i] >= tau_z;
+ *   split when selected and its largest log-scale > log(dense_scale),
+ *   clone when selected otherwise.
+ * The new set, in input order: a kept Gaussian once, a cloned one twice,
+ * a split one as two children.  The split is along the largest scale axis
+ * e and adjusts the children to the skew (the paper's split figure): each
+ * child has scale s_max / split_shrink along e and the parent's other
+ * scales, rotation, skew, opacities and SH; with delta = Sigma beta /
+ * sqrt(1 + beta^T Sigma beta) of the parent and delta_c of a child, they sit
+ * at mu + sqrt(2/pi) (delta - delta_c) +- a e with
+ * a^2 = max(0, v - v_c), v = s_max^2 - (2/pi) (e.delta)^2 and
+ * v_c = s_c^2 - (2/pi) (e.delta_c)^2: the pair's mean is the parent's and
+ * its variance along e the parent's.
+ *  uv_sum, view_count, z_max  [N] device (uv_sum and view_count together, or
+ *                both NULL; z_max may be NULL: that criterion is off).
+ *  decision      [N] u8 device, written.
+ *  out           outputs past out->capacity are dropped; capacity 0 computes
+ *                the decisions and the count only.
+ *  n_out_dev     [1] u32 device: number of outputs (N + clones + splits).
+ *  scratch       device, sgs_densify_scratch_words(N) u32 words.
+ * EINVAL: null required pointers, n < 0, bad options. */
+sgs_status sgs_densify(const sgs_params* p, const float* uv_sum, const uint32_t* view_count,
+                       const float* z_max, const sgs_densify_options* opt, uint8_t* decision,
+                       const sgs_densify_out* out, uint32_t* n_out_dev, uint32_t* scratch,
+                       void* stream);
+
+/* ---------------------------------------------------------- optimiser */
+
+/* One parameter array of an Adam step (device pointers, n floats each). */
+typedef struct {
+  float* param;            /* updated in place                              */
+  const float* grad;       /* gradient of the loss                          */
+  float* m1;               /* first-moment estimate (zeroed before step 1)  */
+  float* m2;               /* second-moment estimate (zeroed before step 1) */
+  int64_t n;
+  float lr;                /* learning rate of this array                   */
+  int32_t _pad;
+} sgs_adam_group;
+
+#define SGS_ADAM_MAX_GROUPS 16
+
+/* One Adam step (Kingma & Ba, ICLR 2015) over n_groups <= 16 arrays: the
+ * optimiser of the training loop, which fits the Gaussian attributes by
+ * gradient descent on the photometric loss (Sec. "Preliminary of 3D
+ * Gaussian Splatting"; the appendix sets the skew's learning rate).  Per
+ * element, with t the step count after this call:
+ *   m1 = b1 m1 + (1 - b1) g;  m2 = b2 m2 + (1 - b2) g^2;
+ *   param -= lr (m1 / (1 - b1^t)) / (sqrt(m2 / (1 - b2^t)) + eps).
+ * state: 4 floats of device memory, zeroed before the first step; the call
+ * advances state[0] = t and keeps the bias corrections in state[1..2] on the
+ * device, so a captured graph of a training step replays correctly.
+ * groups is a host array.  EINVAL: bad counts, null pointers, n < 0. */
+sgs_status sgs_adam_step(const sgs_adam_group* groups, int32_t n_groups, float* state,
+                         float beta1, float beta2, float eps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -6,9 +6,9 @@ does not load the library; the first call does, and fails loudly if it is
 missing (no CPU fallback exists).
 """
 from ._abi import SgsError, default_options, load
-from .raster import (CameraBatch, Frame, GaussianSet, Renderer, SkewGaussianRasterizer, bin_sort,
+from .raster import (CameraBatch, Frame, GaussianSet, Renderer, SkewGaussianRasterizer, bin_sort, densify,
                      densify_stats, preprocess, rasterize, render, render_backward)
 
 __all__ = ["SgsError", "default_options", "load", "CameraBatch", "Frame", "GaussianSet", "Renderer",
-           "SkewGaussianRasterizer", "bin_sort", "densify_stats", "preprocess", "rasterize", "render",
+           "SkewGaussianRasterizer", "bin_sort", "densify", "densify_stats", "preprocess", "rasterize", "render",
            "render_backward"]

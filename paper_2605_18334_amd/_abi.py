@@ -38,11 +38,12 @@ class Options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("filter_s", C.c_float),
                 ("compensate", C.c_int32), ("guard", C.c_float), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("t_min", C.c_float), ("sort_mode", C.c_int32),
-                ("blend_batch", C.c_int32), ("split_tiles", C.c_int32)]
+                ("blend_batch", C.c_int32), ("split_tiles", C.c_int32), ("depth_digit_bits", C.c_int32)]
 
 
 class Geom(C.Structure):
-    _fields_ = [("rec", P), ("depth", P), ("rect", P), ("tiles", P), ("block_off", P)]
+    _fields_ = [("rec", P), ("depth", P), ("rect", P), ("tiles", P), ("block_off", P),
+                ("enhanced", C.c_int32), ("_pad", C.c_int32)]
 
 
 class GeomGrad(C.Structure):
@@ -53,7 +54,25 @@ class Schedule(C.Structure):
     _fields_ = [("tile_order", P), ("work_counter", P)]
 
 
-STRUCTS = [Params, ParamsGrad, Camera, Options, Geom, GeomGrad, Schedule]
+class DensifyOptions(C.Structure):
+    _fields_ = [("tau_uv", C.c_float), ("tau_z", C.c_float), ("dense_scale", C.c_float),
+                ("split_shrink", C.c_float)]
+
+
+class DensifyOut(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("mean", P), ("log_scale", P), ("quat", P), ("skew", P),
+                ("opa_logit", P), ("opa2_logit", P), ("opa_dir", P), ("sh", P), ("parent", P)]
+
+
+class AdamGroup(C.Structure):
+    _fields_ = [("param", P), ("grad", P), ("m1", P), ("m2", P), ("n", C.c_int64), ("lr", C.c_float),
+                ("_pad", C.c_int32)]
+
+
+ADAM_MAX_GROUPS = 16
+
+STRUCTS = [Params, ParamsGrad, Camera, Options, Geom, GeomGrad, Schedule, AdamGroup, DensifyOptions,
+           DensifyOut]
 
 # bytes of the fixed per-device scratch of sgs_bin_sort_noalloc (SGS_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -81,7 +100,12 @@ SIGNATURES = {
                                        C.POINTER(Options), C.c_int64, P, P, P, P, C.POINTER(Schedule), P]),
     "sgs_render_fwd": (C.c_int, [C.POINTER(Geom), C.c_int64, P, C.c_int64, P, C.POINTER(Schedule),
                                  C.POINTER(Camera), P, C.c_int32, C.c_int32, C.POINTER(Options), P, P, P,
-                                 P, C.c_int64, P]),
+                                 P, P, C.c_int64, P]),
+    "sgs_default_densify_options": (None, [C.POINTER(DensifyOptions)]),
+    "sgs_densify_scratch_words": (C.c_int64, [C.c_int64]),
+    "sgs_densify": (C.c_int, [C.POINTER(Params), P, P, P, C.POINTER(DensifyOptions), P, C.POINTER(DensifyOut), P,
+                              P, P]),
+    "sgs_adam_step": (C.c_int, [C.POINTER(AdamGroup), C.c_int32, P, C.c_float, C.c_float, C.c_float, P]),
     "sgs_render_bwd": (C.c_int, [C.POINTER(Params), C.POINTER(Geom), C.c_int64, P, C.c_int64, P,
                                  C.POINTER(Schedule), C.POINTER(Camera), P, C.c_int32, C.POINTER(Options),
                                  P, P, P, C.c_int64, C.POINTER(GeomGrad), C.POINTER(ParamsGrad), P]),

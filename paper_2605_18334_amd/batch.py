@@ -35,10 +35,12 @@ class LaunchConfig:
     tile_order: bool = True
     persistent: bool = False
     views_per_launch: int = 16
+    depth_digit_bits: int = 0      # radix digits of the depth presort: 8, 10 (0: the library's choice)
 
     def options(self) -> _abi.Options:
         return _abi.default_options(tile_w=self.tile_w, tile_h=self.tile_h,
-                                    blend_batch=self.blend_batch, sort_mode=self.sort_mode)
+                                    blend_batch=self.blend_batch, sort_mode=self.sort_mode,
+                                    depth_digit_bits=self.depth_digit_bits)
 
 
 class BatchRenderer:
@@ -123,6 +125,11 @@ DEFAULT_CANDIDATES = [
     LaunchConfig(16, 16, 0, 1, True, False, 4),
     LaunchConfig(16, 16, 128, 1, True, False, 4),
     LaunchConfig(16, 16, 256, 1, True, False, 4),
+    # radix digit width of the depth presort: 8-bit (4 passes) and 10-bit (3)
+    LaunchConfig(16, 16, 0, 1, True, False, 4, 8),
+    LaunchConfig(16, 16, 0, 1, True, False, 4, 10),
+    LaunchConfig(16, 16, 0, 1, True, False, 16, 8),
+    LaunchConfig(16, 16, 0, 1, True, False, 16, 10),
 ]
 
 

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsgs.so")
 
-SOURCES = ["preprocess.hip", "binning.hip", "blend.hip", "sgs_api.hip"]
+SOURCES = ["preprocess.hip", "binning.hip", "blend.hip", "optim.hip", "densify.hip", "sgs_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -30,6 +30,8 @@
 //           sorted over the tile bits only.  Stability keeps depth order and
 //           index order inside a tile.  Far fewer bytes move.
 #include <algorithm>
+#include <cmath>
+#include <cstring>
 
 #include "sgs_dev.h"
 
@@ -98,19 +100,45 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* ws4
   return e;
 }
 
+// Optional transform of the 32-bit keys the first pass (and the histogram)
+// read, for depth keys: the depth buffer's bits of a positive float (a
+// record with tiles, depth > near > 0) become key - base (base = the bits of
+// the nearest near plane), clamped below lim; all-ones bits (records without
+// tiles) become lim, so they still sort last.  The order of the keys is kept
+// (the clamp only ties depths more than 2^127 times the nearest near plane
+// distance, which do not occur), and they fit in 30 bits.  on = false: the
+// identity.
+struct KeyXf {
+  uint32_t base, lim;
+  bool on;
+};
+
+template <typename K>
+__device__ __forceinline__ K xf_key(K k, const KeyXf& x) {
+  if constexpr (sizeof(K) == 4) {
+    if (x.on) {
+      const uint32_t u = (uint32_t)k;
+      return (K)(u == 0xffffffffu ? x.lim : min(u - x.base, x.lim - 1u));
+    }
+  }
+  return k;
+}
+
 // Digit histograms of every pass in one read of the keys, added into copy
-// (block % ncopies) of the partial histograms [ncopies][passes][256]: many
-// blocks adding into one set of 256 words serialise on those addresses
-// (ncopies = 1 adds straight into the final histograms).
-template <typename K, int RS_IPT>
+// (block % ncopies) of the partial histograms [ncopies][passes][DB]: many
+// blocks adding into one set of DB words serialise on those addresses
+// (ncopies = 1 adds straight into the final histograms).  DB: bins per
+// digit (256, or 1024 for the wide digits of small depth sorts).
+template <typename K, int RS_IPT, int DB = 256>
 __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, const uint32_t* n_dev,
                                                   uint32_t n_host, uint32_t cap, int passes,
                                                   int width, uint32_t* __restrict__ hpart,
-                                                  int ncopies) {
-  __shared__ uint32_t h[RS_MAX_PASSES][256];
+                                                  int ncopies, KeyXf xf) {
+  constexpr int MP = DB == 256 ? RS_MAX_PASSES : 4;
+  __shared__ uint32_t h[MP][DB];
   const int t = threadIdx.x;
   const uint32_t dmask = (1u << width) - 1u;
-  for (int k = t; k < RS_MAX_PASSES * 256; k += RS_T) (&h[0][0])[k] = 0;
+  for (int k = t; k < MP * DB; k += RS_T) (&h[0][0])[k] = 0;
   __syncthreads();
   const uint32_t n = count_of(n_dev, n_host, cap);
   constexpr int RS_TILE = RS_T * RS_IPT;
@@ -120,7 +148,7 @@ __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, co
 #pragma unroll
   for (int i = 0; i < RS_IPT; ++i) {
     const uint64_t idx = base + (uint64_t)i * RS_T + t;
-    key[i] = idx < n ? keys[idx] : (K)0;
+    key[i] = idx < n ? xf_key<K>(keys[idx], xf) : (K)0;
   }
 #pragma unroll
   for (int i = 0; i < RS_IPT; ++i) {
@@ -128,9 +156,10 @@ __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, co
       for (int p = 0; p < passes; ++p) atomicAdd(&h[p][digit_of<K>(key[i], width * p, dmask)], 1u);
   }
   __syncthreads();
-  uint32_t* dst = hpart + (size_t)(blockIdx.x % (unsigned)ncopies) * passes * 256;
+  uint32_t* dst = hpart + (size_t)(blockIdx.x % (unsigned)ncopies) * passes * DB;
   for (int p = 0; p < passes; ++p)
-    if (h[p][t]) atomicAdd(&dst[p * 256 + t], h[p][t]);
+    for (int d = t; d < DB; d += RS_T)
+      if (h[p][d]) atomicAdd(&dst[p * DB + d], h[p][d]);
 }
 
 // Per-block digit counts cnt[e][256] of the expansion blocks, scanned in two
@@ -183,13 +212,14 @@ __global__ void __launch_bounds__(256) k_chunk_totals(uint32_t* __restrict__ tot
   }
 }
 
-// Sums the HC partial copies of the digit histograms: ghist[p][d].
+// Sums the HC partial copies of the digit histograms: ghist[p][d], DB bins
+// per pass (blockIdx.x = pass, blockIdx.y = group of 256 bins).
 __global__ void __launch_bounds__(256) k_hist_final(const uint32_t* __restrict__ hpart, int passes,
-                                                    uint32_t* __restrict__ ghist) {
-  const int p = blockIdx.x, t = threadIdx.x;
+                                                    int db, uint32_t* __restrict__ ghist) {
+  const int p = blockIdx.x, d = blockIdx.y * 256 + threadIdx.x;
   uint32_t sum = 0;
-  for (int c = 0; c < HC; ++c) sum += hpart[((size_t)c * passes + p) * 256 + t];
-  ghist[p * 256 + t] = sum;
+  for (int c = 0; c < HC; ++c) sum += hpart[((size_t)c * passes + p) * db + d];
+  ghist[p * db + d] = sum;
 }
 
 // vin == nullptr: the values are the input positions (0, 1, 2, ...).
@@ -205,7 +235,9 @@ __global__ void __launch_bounds__(256) k_hist_final(const uint32_t* __restrict__
 // ranking RS_TILE / NT keys per lane): 512 threads for large sorts, 1024 for
 // small ones, where a block's latency (mostly the per-wave ranking rounds)
 // is the pass time.
-template <typename K, int NT, int LB_W>
+// DB: bins per digit; thread t < DB handles digit t (DB <= NT).  xf: the key
+// transform applied where the first pass reads its keys (see KeyXf).
+template <typename K, int NT, int LB_W, int DB = 256>
 __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
                                                 const uint32_t* __restrict__ vin,
                                                 K* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -216,21 +248,22 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
                                                 uint32_t* err, uint32_t* n_fold,
                                                 uint32_t* ranges, uint32_t n_tiles,
                                                 const uint32_t* __restrict__ pre,
-                                                const uint32_t* __restrict__ pre_tot) {
+                                                const uint32_t* __restrict__ pre_tot, KeyXf xf) {
+  static_assert(DB <= NT && DB % 64 == 0, "one thread per digit bin");
   constexpr int NW = NT / 64;
   constexpr int RS_TILE = RS_T * RS_IPT;
   constexpr int IPT = RS_TILE / NT;
-  __shared__ uint32_t wc[NW][256];
-  __shared__ uint32_t lstart[256];
-  __shared__ uint32_t lend[256];
-  __shared__ uint32_t goff[256];
-  __shared__ uint32_t ws[8];
+  __shared__ uint32_t wc[NW][DB];
+  __shared__ uint32_t lstart[DB];
+  __shared__ uint32_t lend[DB];
+  __shared__ uint32_t goff[DB];
+  __shared__ uint32_t ws[2 * (DB / 64)];
   __shared__ uint32_t s_bid;
   __shared__ K skey[RS_TILE];
   __shared__ uint32_t sval[RS_TILE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   if (t == 0) s_bid = atomicAdd(counter, 1u);
-  for (int k = t; k < NW * 256; k += NT) (&wc[0][0])[k] = 0;
+  for (int k = t; k < NW * DB; k += NT) (&wc[0][0])[k] = 0;
   __syncthreads();
   const uint32_t b = s_bid;
   const uint32_t n = count_of(n_dev, n_host, cap);
@@ -241,14 +274,14 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
   const uint64_t lt = lanemask_lt();
   // this lane's keys are base + 64 i for i < nv (the valid ones)
   const int nv = base < n ? (int)min((uint64_t)IPT, (n - base + 63) / 64) : 0;
-  const uint32_t gh = t < 256 ? ghist[t] : 0u;   // keys of digit t in the whole input
+  const uint32_t gh = t < DB ? ghist[t] : 0u;   // keys of digit t in the whole input
   K key[IPT];
   uint32_t val[IPT];
   uint32_t rank[IPT];
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const uint64_t idx = base + (uint64_t)i * 64;
-    key[i] = i < nv ? kin[idx] : (K)0;
+    key[i] = i < nv ? xf_key<K>(kin[idx], xf) : (K)0;
     val[i] = i < nv ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
   }
   // rank inside the wave: the lowest lane of each digit's peers reserves
@@ -270,11 +303,12 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
 #pragma unroll
   for (int i = 0; i < IPT; ++i) rank[i] = (rank[i] & 255u) + __shfl(lead_base[i], (int)(rank[i] >> 8));
   __syncthreads();
-  // digit t (threads 0..255, the first four waves): block total, start in
+  // digit t (threads 0..DB-1, the first DB/64 waves): block total, start in
   // the block, per-wave starts, and start in the output (scan of ghist)
+  constexpr int DW = DB / 64;
   uint32_t cw[NW];
   uint32_t tot = 0, ls = 0, ds = 0;
-  if (t < 256) {
+  if (t < DB) {
 #pragma unroll
     for (int v = 0; v < NW; ++v) {
       cw[v] = wc[v][t];
@@ -283,18 +317,18 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
     const uint32_t il = wave_incl_scan(tot), ig = wave_incl_scan(gh);
     if (lane == 63) {
       ws[w] = il;
-      ws[4 + w] = ig;
+      ws[DW + w] = ig;
     }
     ls = il - tot;
     ds = ig - gh;
   }
   __syncthreads();
-  const bool has_digit = t < (1 << nbits);   // (nbits <= 8: implies t < 256)
-  uint64_t* st = status + (uint64_t)b * 256 + t;
-  if (t < 256) {
+  const bool has_digit = t < (1 << nbits);   // (nbits <= log2 DB: implies t < DB)
+  uint64_t* st = status + (uint64_t)b * DB + t;
+  if (t < DB) {
     for (int k = 0; k < w; ++k) {
       ls += ws[k];
-      ds += ws[4 + k];
+      ds += ws[DW + k];
     }
     lstart[t] = ls;
     lend[t] = ls + tot;
@@ -323,14 +357,15 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
     }
   }
   // look back for the prefix over the blocks before this one
-  if (t < 256 && pre) {
+  if (t < DB && pre) {
     // offsets of this block's keys within each digit were scanned beforehand
+    // (256-bin digits only)
     static_assert(RS_TILE % EX_TILE == 0, "a pass block covers whole expansion blocks");
     const uint64_t e = (uint64_t)b * (RS_TILE / EX_TILE);
     goff[t] = ds + pre[e * 256 + t] + pre_tot[(e / EC) * 256 + t];
-  } else if (t < 256 && (b == 0 || !has_digit)) {
+  } else if (t < DB && (b == 0 || !has_digit)) {
     goff[t] = ds;
-  } else if (t < 256) {
+  } else if (t < DB) {
     // walk back LB_W predecessors at a time (their loads are in flight
     // together), summing published counts until an inclusive prefix
     uint32_t excl = 0, spins = 0;
@@ -341,7 +376,7 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
 #pragma unroll
       for (int k = 0; k < LB_W; ++k) {
         const int64_t q = q0 - k;
-        sw[k] = q >= 0 ? __hip_atomic_load(status + (uint64_t)q * 256 + t, __ATOMIC_RELAXED,
+        sw[k] = q >= 0 ? __hip_atomic_load(status + (uint64_t)q * DB + t, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT)
                        : ST_INC;   // block 0 publishes an inclusive prefix: never reached
       }
@@ -417,6 +452,7 @@ struct DupArgs {
   int32_t hpasses;       //         digits of hwidth bits, hcopies copies
   int32_t hwidth;
   int32_t hcopies;
+  int32_t enhanced;      // 0: each record's rect is in its slot 3 (one line per record)
   int64_t m;
 };
 
@@ -621,20 +657,35 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
   uint64_t run = a.offs[j0];    // instance offset of the next item
   // records in chunks of 256: each thread sets up one record's span (its
   // loads are the chunk's only dependent gathers), then the chunk's (record,
-  // tile row) items are enumerated from LDS, 256 at a time
+  // tile row) items are enumerated from LDS, 256 at a time.  A record has
+  // tiles when the next offset in depth order is larger than its own (the
+  // last record's count is read directly), and its rect sits in its own
+  // 64-byte line unless the records carry enhanced opacity: one gathered
+  // line per record.
   for (uint32_t c = 0; c < W && run < o1; c += 256) {
     const uint32_t k = c + t;
     uint32_t rows = 0;
     if (k < W) {
-      const uint32_t rec = a.order[j0 + k];
+      const uint64_t j = (uint64_t)j0 + k;
+      const uint32_t rec = a.order[j];
       s_rec[t] = rec;
-      if ((k == 0 || a.offs[j0 + k] < o1) && rec < (uint64_t)a.m && a.tiles[rec] > 0) {
-        const uint2 r = reinterpret_cast<const uint2*>(a.rect)[rec];
+      const uint32_t off = a.offs[j];
+      bool has = false;
+      if ((k == 0 || off < o1) && rec < (uint64_t)a.m)
+        has = j + 1 < (uint64_t)a.m ? a.offs[j + 1] > off : a.tiles[rec] > 0;
+      if (has) {
+        const float4* rp = a.rec + 4 * (uint64_t)rec;
+        const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2];
+        uint2 r;
+        if (a.enhanced) {
+          r = reinterpret_cast<const uint2*>(a.rect)[rec];
+        } else {
+          const float4 q3 = rp[3];
+          r = make_uint2(__float_as_uint(q3.x), __float_as_uint(q3.y));
+        }
         rows = (r.y >> 16) - min(r.x >> 16, r.y >> 16);
         s_r0[t] = r.x;
         s_r1[t] = r.y;
-        const float4* rp = a.rec + 4 * (uint64_t)rec;
-        const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2];
         Span sp;
         span_setup(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, record_zcut(a, q1), sp);
         s_sp[0][t] = sp.mx;  s_sp[1][t] = sp.my;  s_sp[2][t] = sp.b;   s_sp[3][t] = sp.det;
@@ -835,18 +886,21 @@ __global__ void __launch_bounds__(1024) k_order_tiles(uint32_t* __restrict__ ran
 // ------------------------------------------------------------------ host side
 static inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
-// Passes of at most 8 bits; the digit width spreads the bits evenly over
-// them (13 bits: 7 + 6, not 8 + 5): fewer digits per block, longer runs.
-static int rs_passes(int bits) { return (bits + 7) / 8; }
-static int rs_width(int bits) { return (bits + rs_passes(bits) - 1) / rs_passes(bits); }
+// Passes of at most 8 bits (dbits = 10: 10 bits, for the wide digits of
+// small depth sorts); the digit width spreads the bits evenly over them (13
+// bits: 7 + 6, not 8 + 5): fewer digits per block, longer runs.
+static int rs_passes(int bits, int dbits = 8) { return (bits + dbits - 1) / dbits; }
+static int rs_width(int bits, int dbits = 8) {
+  return (bits + rs_passes(bits, dbits) - 1) / rs_passes(bits, dbits);
+}
 static uint64_t rs_blocks(uint64_t cap) { return std::max<uint64_t>(1, cdiv(cap, (uint64_t)RS_T * RS_IPT)); }
 
-// Scratch of one sort of up to `cap` keys in `passes` passes, contiguous so
-// that it is zeroed as one region: block counters [64] (one per pass), digit
-// histograms [passes][256] u32, their partial copies [HC][passes][256] u32,
-// look-back status [passes][blocks][256] u64.
-static size_t rs_words(uint64_t cap, int passes) {
-  return 64 + (size_t)passes * 256 * (1 + HC) + (size_t)passes * rs_blocks(cap) * 256 * 2;
+// Scratch of one sort of up to `cap` keys in `passes` passes of db-bin
+// digits, contiguous so that it is zeroed as one region: block counters [64]
+// (one per pass), digit histograms [passes][db] u32, their partial copies
+// [HC][passes][db] u32, look-back status [passes][blocks][db] u64.
+static size_t rs_words(uint64_t cap, int passes, int db = 256) {
+  return 64 + (size_t)passes * db * (1 + HC) + (size_t)passes * rs_blocks(cap) * db * 2;
 }
 
 struct RsScratch {
@@ -858,12 +912,12 @@ struct RsScratch {
   uint32_t* n_fold;     // instance count to mark N_INVALID on failure, or null
 };
 
-static RsScratch rs_carve(uint32_t* p, int passes, uint32_t* err, uint32_t* n_fold) {
+static RsScratch rs_carve(uint32_t* p, int passes, uint32_t* err, uint32_t* n_fold, int db = 256) {
   RsScratch s;
   s.counters = p;
   s.ghist = p + 64;
-  s.hpart = s.ghist + (size_t)passes * 256;
-  s.status = reinterpret_cast<uint64_t*>(p + 64 + (size_t)passes * 256 * (1 + HC));
+  s.hpart = s.ghist + (size_t)passes * db;
+  s.status = reinterpret_cast<uint64_t*>(p + 64 + (size_t)passes * db * (1 + HC));
   s.err = err;
   s.n_fold = n_fold;
   return s;
@@ -878,51 +932,61 @@ static RsScratch rs_carve(uint32_t* p, int passes, uint32_t* err, uint32_t* n_fo
 // the hist_blocks_done blocks that counted them exceed HC_MIN_BLOCKS, else in
 // the final histograms.  With ranges, the last
 // pass also writes the tile ranges of the sorted keys (see k_os_pass).
-template <typename K>
+// DB = 1024 (10-bit digits) only for small sorts (at most RS_WIDE_MAX_BLOCKS
+// blocks, 1024-thread pass blocks) without precomputed first-pass offsets;
+// xf (32-bit keys) transforms the keys as the first pass and the histogram
+// read them.
+template <typename K, int DB = 256>
 static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32_t* vb[2],
                              const uint32_t* n_dev, uint32_t n_host, uint64_t cap, int bits,
                              RsScratch sc, hipStream_t s, bool hist_done = false,
                              uint64_t hist_blocks_done = 0, uint32_t* ranges = nullptr,
                              uint32_t n_tiles = 0, const uint32_t* pre0 = nullptr,
-                             const uint32_t* pre0_tot = nullptr) {
+                             const uint32_t* pre0_tot = nullptr, KeyXf xf = KeyXf{0u, 0u, false}) {
+  constexpr int DBITS = DB == 1024 ? 10 : 8;
   const uint64_t blocks = rs_blocks(cap);
-  const int passes = rs_passes(bits);
-  const int width = rs_width(bits);
+  const int passes = rs_passes(bits, DBITS);
+  const int width = rs_width(bits, DBITS);
   const uint64_t hist_blocks = hist_done ? hist_blocks_done : blocks;
   const bool copies = hist_blocks > HC_MIN_BLOCKS;
+  if (DB != 256 && (blocks > RS_WIDE_MAX_BLOCKS || pre0 || hist_done)) return SGS_EINVAL;
   if (!hist_done) {
     // small sorts: twice as many blocks of 2048 keys (a block's LDS counts
     // of the few high digits that most keys share are serialised; 1024-key
     // blocks measured slower at 1M keys)
     if (blocks <= RS_WIDE_MAX_BLOCKS)
-      k_os_hist<K, 8><<<(unsigned)cdiv(cap, (uint64_t)RS_T * 8), RS_T, 0, s>>>(
+      k_os_hist<K, 8, DB><<<(unsigned)cdiv(cap, (uint64_t)RS_T * 8), RS_T, 0, s>>>(
           kin, n_dev, n_host, (uint32_t)cap, passes, width, copies ? sc.hpart : sc.ghist,
-          copies ? HC : 1);
+          copies ? HC : 1, xf);
     else
-      k_os_hist<K, RS_IPT><<<(unsigned)blocks, RS_T, 0, s>>>(kin, n_dev, n_host, (uint32_t)cap, passes,
-                                                              width, copies ? sc.hpart : sc.ghist,
-                                                              copies ? HC : 1);
+      k_os_hist<K, RS_IPT, DB><<<(unsigned)blocks, RS_T, 0, s>>>(kin, n_dev, n_host, (uint32_t)cap,
+                                                                  passes, width,
+                                                                  copies ? sc.hpart : sc.ghist,
+                                                                  copies ? HC : 1, xf);
     SGS_LAUNCH_CHECK();
   }
   if (copies) {
-    k_hist_final<<<passes, 256, 0, s>>>(sc.hpart, passes, sc.ghist);
+    k_hist_final<<<dim3(passes, DB / 256), 256, 0, s>>>(sc.hpart, passes, DB, sc.ghist);
     SGS_LAUNCH_CHECK();
   }
+  const KeyXf none = {0u, 0u, false};
   for (int p = 0; p < passes; ++p) {
     const int nb = std::min(width, bits - width * p);
     const int dst = (passes - 1 - p) & 1;
     const K* ki = p == 0 ? kin : kb[dst ^ 1];
     const uint32_t* vi = p == 0 ? vin : vb[dst ^ 1];
     if (blocks <= RS_WIDE_MAX_BLOCKS)
-      k_os_pass<K, 1024, LB_W><<<(unsigned)blocks, 1024, 0, s>>>(
-        ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
-        sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
-        p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot);
-    else
+      k_os_pass<K, 1024, LB_W, DB><<<(unsigned)blocks, 1024, 0, s>>>(
+        ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * DB,
+        sc.status + (size_t)p * blocks * DB, sc.counters + p, sc.err, sc.n_fold,
+        p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot,
+        p == 0 ? xf : none);
+    else if constexpr (DB == 256)
       k_os_pass<K, 512, LB_W><<<(unsigned)blocks, 512, 0, s>>>(
         ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
         sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
-        p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot);
+        p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot,
+        p == 0 ? xf : none);
     SGS_LAUNCH_CHECK();
   }
   return SGS_OK;
@@ -970,7 +1034,8 @@ static BinLayout bin_layout(uintptr_t base, int64_t m, int64_t cap, int64_t tota
     L.kalt = reinterpret_cast<uint64_t*>(take(C * 8));
     L.valt = reinterpret_cast<uint32_t*>(take(C * 4));
   } else {
-    L.rs_depth = reinterpret_cast<uint32_t*>(take(rs_words(M, 4) * 4));
+    // depth presort: 4 passes of 8-bit digits, or 3 of 10 bits (room for either)
+    L.rs_depth = reinterpret_cast<uint32_t*>(take(std::max(rs_words(M, 4), rs_words(M, 3, 1024)) * 4));
     L.so_words = 64 + 2 * (size_t)cdiv(std::max<uint64_t>(M, 1), SO_TILE);
     L.so_status = reinterpret_cast<uint32_t*>(take(L.so_words * 4));
     for (int k = 0; k < 2; ++k) {
@@ -995,11 +1060,22 @@ size_t bin_sort_scratch_bytes(int64_t m, int64_t cap, int64_t total_tiles, int m
   return bin_layout(0, m, cap, total_tiles, mode).bytes;
 }
 
+// Wide (10-bit) depth digits: for depth sorts of at most RS_WIDE_MAX_BLOCKS
+// blocks, when every view's near plane is positive.  The keys, transformed
+// by KeyXf with base = the bits of the nearest near plane, take 30 bits: 3
+// passes instead of 4.
+static bool wide_depth(uint64_t m, float near_min) {
+  return m > 0 && rs_blocks(m) <= RS_WIDE_MAX_BLOCKS && near_min > 0.0f && std::isfinite(near_min);
+}
+constexpr int DEPTH_BITS_WIDE = 30;
+
 sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_camera* cams_dev,
                            int32_t n_views, int64_t total_tiles, const sgs_options* opt,
                            int64_t cap, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
-                           uint32_t* n_inst, uint32_t* tile_order, void* scratch, hipStream_t s) {
+                           uint32_t* n_inst, uint32_t* tile_order, void* scratch, float near_min,
+                           hipStream_t s) {
   const int mode = opt->sort_mode;
+  const bool wide = mode == 1 && opt->depth_digit_bits != 8 && wide_depth((uint64_t)m, near_min);
   const BinLayout L = bin_layout(reinterpret_cast<uintptr_t>(scratch), m, cap, total_tiles, mode);
   const uint64_t T = (uint64_t)total_tiles, C = (uint64_t)cap;
   uint32_t* err = L.misc;
@@ -1036,7 +1112,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
     }
   }
   if (mode == 1 && m > 0) {
-    zero(L.rs_depth, rs_words((uint64_t)m, 4));
+    zero(L.rs_depth, wide ? rs_words((uint64_t)m, 3, 1024) : rs_words((uint64_t)m, 4));
     zero(L.so_status, L.so_words);
     zero(L.bstart, L.n_bstart);
   }
@@ -1068,6 +1144,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   a.cap = (uint32_t)cap;
   a.vals = vals;
   a.n_inst = n_inst;
+  a.enhanced = g->enhanced;
   a.m = m;
   const RsScratch sc_main = rs_carve(L.rs_main, L.main_passes, err, n_inst);
   if (mode == 0) {
@@ -1099,8 +1176,22 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   uint32_t* dk[2] = {L.dk[0], L.dk[1]};
   uint32_t* dv[2] = {L.dv[0], L.dv[1]};
   // depth presort straight from the depth buffer (all-ones for tile-less records)
-  sgs_status st = radix_sort<uint32_t>(reinterpret_cast<const uint32_t*>(g->depth), nullptr, dk, dv,
-                                       nullptr, (uint32_t)m, mm, 32, rs_carve(L.rs_depth, 4, err, nullptr), s);
+  sgs_status st;
+  if (wide) {
+    KeyXf xf;
+    uint32_t nb;
+    memcpy(&nb, &near_min, 4);
+    xf.base = nb;
+    xf.lim = (1u << DEPTH_BITS_WIDE) - 1u;
+    xf.on = true;
+    st = radix_sort<uint32_t, 1024>(reinterpret_cast<const uint32_t*>(g->depth), nullptr, dk, dv, nullptr,
+                                    (uint32_t)m, mm, DEPTH_BITS_WIDE,
+                                    rs_carve(L.rs_depth, 3, err, nullptr, 1024), s, false, 0, nullptr, 0,
+                                    nullptr, nullptr, xf);
+  } else {
+    st = radix_sort<uint32_t>(reinterpret_cast<const uint32_t*>(g->depth), nullptr, dk, dv, nullptr,
+                              (uint32_t)m, mm, 32, rs_carve(L.rs_depth, 4, err, nullptr), s);
+  }
   if (st != SGS_OK) return st;
   const uint32_t* order = dv[0];
   k_sorted_offsets<<<(unsigned)cdiv(mm, SO_TILE), 256, 0, s>>>(

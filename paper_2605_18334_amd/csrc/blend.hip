@@ -42,6 +42,7 @@ struct BlendArgs {
   float* out_T;
   uint32_t* out_last;
   uint32_t* out_count;     // optional: contributing pairs per pixel
+  uint32_t* out_eval;      // optional: evaluated pairs per pixel (past the exponent test)
   const uint32_t* tile_order;  // optional: tiles in this order (longest lists first)
   uint32_t* work_counter;      // optional: persistent workgroups take tiles from it
   int32_t n_quad;              // forward: the first n_quad tiles of tile_order run split
@@ -252,7 +253,7 @@ __device__ __forceinline__ int next_tile(const BlendArgs& a, uint32_t* s_next) {
   return a.tile_order ? (int)a.tile_order[idx] : (int)idx;
 }
 
-template <int TW, int TH, int B, bool ENH>
+template <int TW, int TH, int B, bool ENH, bool CNT>
 __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW, TH, B, ENH>& S) {
   TileSetup ts;
   if (!setup_tile<TW, TH>(a, tile, ts)) return;
@@ -262,7 +263,7 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
   rg.y = min(rg.y, a.n_vals);
   rg.x = min(rg.x, rg.y);
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  uint32_t last = 0, count = 0;
+  uint32_t last = 0, count = 0, evals = 0;
   bool done = !ts.inside;
   for (uint32_t base = rg.x; base < rg.y; base += B) {
     if (__syncthreads_and(done)) break;
@@ -282,7 +283,8 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
       const float dx = fx - r0.x, dy = fy - r0.y;
       const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
       const bool in = !done && l2 >= r2.w;
-      if (!__any(in)) continue;
+      if (!wave_any(in)) continue;
+      if (CNT && in) ++evals;
       Pair2 p;
       pair_eval2(l2, r1.y, r1.z, dx, dy, (e & LIST_SKEW) != 0u, p);
       float at = p.at;
@@ -304,10 +306,10 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
         C2 = fmaf(r2.z, wgt, C2);
         T = Tn;
         last = base - rg.x + (uint32_t)j + 1u;
-        ++count;
+        if (CNT) ++count;
       }
       done = done || stop;
-      if (__any(stop) && __all(done)) break;
+      if (wave_any(stop) && wave_all(done)) break;
     }
   }
   if (ts.inside) {
@@ -317,7 +319,10 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
     a.out_rgb[2 * a.P + pix] = fmaf(T, ts.cam->bg[2], C2);
     a.out_T[pix] = T;
     a.out_last[pix] = last;
-    if (a.out_count) a.out_count[pix] = count;
+    if (CNT) {
+      if (a.out_count) a.out_count[pix] = count;
+      if (a.out_eval) a.out_eval[pix] = evals;
+    }
   }
 }
 
@@ -336,7 +341,7 @@ __device__ __forceinline__ int quad_bcast(int v) {
 // consecutive records of the wave's list (one each), then every lane of the
 // quad composites the four in list order.  Same decisions and the same
 // floating-point operations in the same order as fwd_tile: identical results.
-template <int B, bool ENH>
+template <int B, bool ENH, bool CNT>
 __device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quarter,
                                          Stage<16, 16, B, ENH>& S) {
   TileSetup ts;
@@ -352,7 +357,7 @@ __device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quart
   rg.y = min(rg.y, a.n_vals);
   rg.x = min(rg.x, rg.y);
   float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  uint32_t last = 0, count = 0;
+  uint32_t last = 0, count = 0, evals = 0;
   bool done = !ts.inside;
   for (uint32_t base = rg.x; base < rg.y; base += B) {
     if (__syncthreads_and(done)) break;
@@ -371,7 +376,8 @@ __device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quart
       const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
       const bool in = has && !done && l2 >= r2.w;
       float alpha = 0.0f;
-      if (__any(in)) {
+      if (CNT && in) ++evals;
+      if (wave_any(in)) {
         Pair2 p;
         pair_eval2(l2, r1.y, r1.z, dx, dy, (e & LIST_SKEW) != 0u, p);
         float at = p.at;
@@ -399,7 +405,7 @@ __device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quart
             C2 = fmaf(quad_bcast<Q>(cb), wgt, C2);                           \
             T = Tn;                                                          \
             last = base - rg.x + (uint32_t)quad_bcast<Q>(jj) + 1u;           \
-            ++count;                                                         \
+            if (CNT) ++count;                                                \
           }                                                                  \
         }                                                                    \
       }
@@ -408,9 +414,12 @@ __device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quart
       SGS_QUAD_STEP(2)
       SGS_QUAD_STEP(3)
 #undef SGS_QUAD_STEP
-      if (__all(done)) break;
+      if (wave_all(done)) break;
     }
   }
+  if (CNT)   // the quad's four lanes evaluated disjoint records of the pixel
+    evals = (uint32_t)(quad_bcast<0>((int)evals) + quad_bcast<1>((int)evals) + quad_bcast<2>((int)evals) +
+                       quad_bcast<3>((int)evals));
   if (ts.inside && sub == 0) {
     const int64_t pix = ts.cam->pix_base + (int64_t)ts.py * ts.cam->width + ts.px;
     a.out_rgb[pix] = fmaf(T, ts.cam->bg[0], C0);
@@ -418,26 +427,31 @@ __device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quart
     a.out_rgb[2 * a.P + pix] = fmaf(T, ts.cam->bg[2], C2);
     a.out_T[pix] = T;
     a.out_last[pix] = last;
-    if (a.out_count) a.out_count[pix] = count;
+    if (CNT) {
+      if (a.out_count) a.out_count[pix] = count;
+      if (a.out_eval) a.out_eval[pix] = evals;
+    }
   }
 }
 
-template <int TW, int TH, int B, bool ENH>
+// CNT: also count evaluated and composited pairs per pixel (out_eval,
+// out_count); the variant without them skips the counting instructions.
+template <int TW, int TH, int B, bool ENH, bool CNT>
 __global__ void __launch_bounds__(TW * TH) k_blend_fwd(BlendArgs a) {
   __shared__ Stage<TW, TH, B, ENH> S;
   __shared__ uint32_t s_next;
   if (!a.work_counter) {
     if constexpr (TW == 16 && TH == 16) {
       if (blockIdx.x < 4u * (uint32_t)a.n_quad) {
-        fwd_quad<B, ENH>(a, (int)a.tile_order[blockIdx.x >> 2], (int)(blockIdx.x & 3u), S);
+        fwd_quad<B, ENH, CNT>(a, (int)a.tile_order[blockIdx.x >> 2], (int)(blockIdx.x & 3u), S);
         return;
       }
     }
-    fwd_tile<TW, TH, B, ENH>(a, launch_tile(a), S);
+    fwd_tile<TW, TH, B, ENH, CNT>(a, launch_tile(a), S);
     return;
   }
   for (int tile = next_tile(a, &s_next); tile >= 0; tile = next_tile(a, &s_next))
-    fwd_tile<TW, TH, B, ENH>(a, tile, S);
+    fwd_tile<TW, TH, B, ENH, CNT>(a, tile, S);
 }
 
 template <int TW, int TH, int B, bool ENH>
@@ -540,7 +554,7 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
       const float dx = fx - r0.x, dy = fy - r0.y;
       const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
       const bool in = (uint32_t)(start + j) < last && l2 >= r2.w;
-      if (!__any(in)) continue;
+      if (!wave_any(in)) continue;
       // from here on every lane computes; lanes without a contribution get
       // zero weights through selects (nested branches made the compiler
       // re-zero all gradient registers on every path)
@@ -555,7 +569,7 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
       }
       const float alpha = fminf(a.alpha_max, at);
       const bool hit = in && alpha >= a.alpha_min;
-      if (!__any(hit)) continue;
+      if (!wave_any(hit)) continue;
       const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
       const float Tn = T * inv;                 // transmittance in front of this pair
       T = hit ? Tn : T;
@@ -677,7 +691,7 @@ __device__ __forceinline__ void bwd_quad(const BlendArgs& a, int tile, int quart
       p.at = 0.0f;
       float at = 0.0f, o = 1.0f, eu = 0.0f, ee = 1.0f, alpha = 0.0f;
       float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (__any(in)) {
+      if (wave_any(in)) {
         pair_eval2(l2, r1.y, r1.z, dx, dy, (e & LIST_SKEW) != 0u, p);
         at = p.at;
         if (ENH) {
@@ -688,7 +702,7 @@ __device__ __forceinline__ void bwd_quad(const BlendArgs& a, int tile, int quart
         alpha = fminf(a.alpha_max, at);
       }
       const bool hit = in && alpha >= a.alpha_min;
-      if (!__any(hit)) continue;
+      if (!wave_any(hit)) continue;
       // transmittance and colour-behind recursion, records in list order
       // (latest first), replicated on the quad
       const int hi = hit ? 1 : 0;
@@ -800,7 +814,7 @@ static unsigned resident_grid(F kernel, int threads) {
 
 template <int TW, int TH, int B, bool ENH>
 static void launch_fwd_t(const BlendArgs& a, unsigned grid, hipStream_t s) {
-  auto k = k_blend_fwd<TW, TH, B, ENH>;
+  auto k = (a.out_count || a.out_eval) ? k_blend_fwd<TW, TH, B, ENH, true> : k_blend_fwd<TW, TH, B, ENH, false>;
   if (a.work_counter) {
     const unsigned g = resident_grid(k, TW * TH);
     grid = g ? std::min(g, grid) : grid;
@@ -884,12 +898,13 @@ sgs_status launch_blend_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals, 
                             const sgs_camera* cams_dev, int32_t n_views,
                             int64_t total_tiles, int enhanced, const sgs_options* opt,
                             float* out_rgb, float* out_T, uint32_t* out_last,
-                            uint32_t* out_count, int64_t P, hipStream_t s) {
+                            uint32_t* out_count, uint32_t* out_eval, int64_t P, hipStream_t s) {
   BlendArgs a = make_args(g, m, vals, cap, ranges, sched, cams_dev, n_views, total_tiles, opt, P);
   a.out_rgb = out_rgb;
   a.out_T = out_T;
   a.out_last = out_last;
   a.out_count = out_count;
+  a.out_eval = out_eval;
   unsigned grid = blend_grid(total_tiles);
   split_setup(a, opt, total_tiles, grid);
   return enhanced ? dispatch_tile<false, true>(a, opt, grid, s)

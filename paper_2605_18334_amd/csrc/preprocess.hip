@@ -266,7 +266,10 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
             rec[0] = make_float4(P.mux, P.muy, P.a, P.b);
             rec[1] = make_float4(P.c, P.b2x, P.b2y, d);
             rec[2] = make_float4(P.rgb[0], P.rgb[1], P.rgb[2], thr);
-            if (a.enhanced) rec[3] = make_float4(P.o1, P.o2, P.w2x, P.w2y);
+            // slot 3: enhanced opacity, or else the rect (binning then
+            // gathers this one line per record)
+            rec[3] = a.enhanced ? make_float4(P.o1, P.o2, P.w2x, P.w2y)
+                                : make_float4(__uint_as_float(rx), __uint_as_float(ry), 0.0f, 0.0f);
           }
         }
       }

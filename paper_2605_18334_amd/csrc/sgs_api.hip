@@ -20,15 +20,19 @@ size_t bin_sort_scratch_bytes(int64_t m, int64_t cap, int64_t total_tiles, int m
 sgs_status launch_bin_sort(const sgs_geom*, int64_t m, int64_t n, const sgs_camera*, int32_t,
                            int64_t total_tiles, const sgs_options*, int64_t cap, uint64_t*,
                            uint32_t*, uint32_t*, uint32_t*, uint32_t* tile_order, void*,
-                           hipStream_t);
+                           float near_min, hipStream_t);
 sgs_status launch_blend_fwd(const sgs_geom*, int64_t, const uint32_t*, int64_t, const uint32_t*,
                             const sgs_schedule*, const sgs_camera*, int32_t, int64_t, int,
-                            const sgs_options*, float*, float*, uint32_t*, uint32_t*, int64_t,
-                            hipStream_t);
+                            const sgs_options*, float*, float*, uint32_t*, uint32_t*, uint32_t*,
+                            int64_t, hipStream_t);
 sgs_status launch_blend_bwd(const sgs_geom*, int64_t, const uint32_t*, int64_t, const uint32_t*,
                             const sgs_schedule*, const sgs_camera*, int32_t, int64_t, int,
                             const sgs_options*, const float*, const uint32_t*, const float*,
                             int64_t, float*, hipStream_t);
+sgs_status launch_adam(const sgs_adam_group*, int32_t, float*, float, float, float, hipStream_t);
+sgs_status launch_densify(const sgs_params*, const float*, const uint32_t*, const float*,
+                          const sgs_densify_options*, uint8_t*, uint32_t*, const sgs_densify_out*,
+                          uint32_t*, hipStream_t);
 }  // namespace sgs
 
 namespace {
@@ -42,7 +46,8 @@ bool options_ok(const sgs_options* o) {
   return tile && batch && isfinite(o->filter_s) && o->filter_s >= 0.0f && isfinite(o->guard) &&
          o->guard > 0.0f && o->alpha_min > 0.0f && o->alpha_min < o->alpha_max &&
          o->alpha_max < 1.0f && o->t_min > 0.0f && o->t_min < 1.0f &&
-         (o->sort_mode == 0 || o->sort_mode == 1) && o->split_tiles >= -1;
+         (o->sort_mode == 0 || o->sort_mode == 1) && o->split_tiles >= -1 &&
+         (o->depth_digit_bits == 0 || o->depth_digit_bits == 8 || o->depth_digit_bits == 10);
 }
 
 bool params_ok(const sgs_params* p) {
@@ -119,6 +124,7 @@ void sgs_default_options(sgs_options* o) {
   o->sort_mode = 1;
   o->blend_batch = 0;
   o->split_tiles = -1;
+  o->depth_digit_bits = 0;
 }
 
 size_t sgs_struct_size(int32_t which) {
@@ -130,6 +136,9 @@ size_t sgs_struct_size(int32_t which) {
     case 4: return sizeof(sgs_geom);
     case 5: return sizeof(sgs_geom_grad);
     case 6: return sizeof(sgs_schedule);
+    case 7: return sizeof(sgs_adam_group);
+    case 8: return sizeof(sgs_densify_options);
+    case 9: return sizeof(sgs_densify_out);
   }
   return 0;
 }
@@ -238,6 +247,7 @@ sgs_status sgs_preprocess(const sgs_params* p, const sgs_camera* cams_host,
     return SGS_EINVAL;
   if (p->n > 0 && (!g->rec || !g->depth || !g->rect || !g->tiles)) return SGS_EINVAL;
   if (!g->block_off) return SGS_EINVAL;
+  if (g->enhanced != (p->opa2_logit != nullptr ? 1 : 0)) return SGS_EINVAL;
   if (p->n * (int64_t)n_views >= ((int64_t)1 << 32)) return SGS_EUNSUPPORTED;
   return sgs::launch_preprocess(p, cams_dev, n_views, opt, g, (hipStream_t)stream);
 }
@@ -254,12 +264,15 @@ sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_hos
   if (inst_capacity > 0 && !vals) return SGS_EINVAL;
   if (opt->sort_mode == 0 && inst_capacity > 0 && !keys) return SGS_EINVAL;
   if (m > 0 && (!g->rec || !g->depth || !g->rect || !g->tiles || !g->block_off)) return SGS_EINVAL;
+  if (g->enhanced != 0 && g->enhanced != 1) return SGS_EINVAL;
   const int64_t tt = tiles_total(cams_host, n_views);
   if (!scratch || scratch_bytes < sgs::bin_sort_scratch_bytes(m, inst_capacity, tt, opt->sort_mode))
     return SGS_ECAPACITY;
+  float near_min = cams_host[0].near_z;
+  for (int v = 1; v < n_views; ++v) near_min = std::min(near_min, cams_host[v].near_z);
   return sgs::launch_bin_sort(g, m, m / n_views, cams_dev, n_views, tt, opt, inst_capacity, keys,
                               vals, tile_ranges, n_inst_dev, sched ? sched->tile_order : nullptr,
-                              scratch, (hipStream_t)stream);
+                              scratch, near_min, (hipStream_t)stream);
 }
 
 sgs_status sgs_bin_sort_noalloc(const sgs_geom* g, int64_t m, const sgs_camera* cams_host,
@@ -287,17 +300,18 @@ sgs_status sgs_render_fwd(const sgs_geom* g, int64_t m, const uint32_t* vals,
                           const sgs_schedule* sched, const sgs_camera* cams_host,
                           const sgs_camera* cams_dev, int32_t n_views, int32_t enhanced,
                           const sgs_options* opt, float* out_rgb, float* out_T,
-                          uint32_t* out_last, uint32_t* out_count, int64_t total_pixels,
-                          void* stream) {
+                          uint32_t* out_last, uint32_t* out_count, uint32_t* out_eval,
+                          int64_t total_pixels, void* stream) {
   if (!g || (m > 0 && !g->rec) || m < 0 || !tile_ranges || !cams_ok(cams_host, n_views) ||
       !cams_dev || !options_ok(opt) || !out_rgb || !out_T || !out_last)
     return SGS_EINVAL;
   if (total_pixels != pixels_total(cams_host, n_views)) return SGS_EINVAL;
   if (inst_capacity < 0 || inst_capacity >= ((int64_t)1 << 32) || (!vals && inst_capacity > 0))
     return SGS_EINVAL;
+  if ((enhanced ? 1 : 0) != g->enhanced) return SGS_EINVAL;
   return sgs::launch_blend_fwd(g, m, vals, inst_capacity, tile_ranges, sched, cams_dev, n_views,
                                tiles_total(cams_host, n_views), enhanced ? 1 : 0, opt, out_rgb,
-                               out_T, out_last, out_count, total_pixels, (hipStream_t)stream);
+                               out_T, out_last, out_count, out_eval, total_pixels, (hipStream_t)stream);
 }
 
 sgs_status sgs_render_bwd(const sgs_params* p, const sgs_geom* g, int64_t m,
@@ -317,6 +331,7 @@ sgs_status sgs_render_bwd(const sgs_params* p, const sgs_geom* g, int64_t m,
   if (inst_capacity < 0 || inst_capacity >= ((int64_t)1 << 32) || (!vals && inst_capacity > 0))
     return SGS_EINVAL;
   const int enhanced = p->opa2_logit != nullptr;
+  if (enhanced != g->enhanced) return SGS_EINVAL;
   sgs_status st = sgs::launch_blend_bwd(g, m, vals, inst_capacity, tile_ranges, sched, cams_dev,
                                         n_views,
                                         tiles_total(cams_host, n_views), enhanced, opt, out_T,
@@ -325,6 +340,52 @@ sgs_status sgs_render_bwd(const sgs_params* p, const sgs_geom* g, int64_t m,
   if (st != SGS_OK) return st;
   return sgs::launch_preprocess_bwd(p, cams_dev, n_views, opt, g, g2d->rec, grad,
                                     (hipStream_t)stream);
+}
+
+void sgs_default_densify_options(sgs_densify_options* o) {
+  if (!o) return;
+  o->tau_uv = 0.001f;
+  o->tau_z = 0.001f;
+  o->dense_scale = 0.01f;
+  o->split_shrink = 1.6f;
+}
+
+int64_t sgs_densify_scratch_words(int64_t n) {
+  return n < 0 ? 0 : (n + 255) / 256 + 1;
+}
+
+sgs_status sgs_densify(const sgs_params* p, const float* uv_sum, const uint32_t* view_count,
+                       const float* z_max, const sgs_densify_options* opt, uint8_t* decision,
+                       const sgs_densify_out* out, uint32_t* n_out_dev, uint32_t* scratch,
+                       void* stream) {
+  if (!params_ok(p) || !opt || !out || !n_out_dev || !scratch) return SGS_EINVAL;
+  if ((uv_sum == nullptr) != (view_count == nullptr)) return SGS_EINVAL;
+  if (p->n > 0 && !decision) return SGS_EINVAL;
+  if (!(isfinite(opt->tau_uv) && isfinite(opt->tau_z) && opt->dense_scale > 0.0f &&
+        isfinite(opt->dense_scale) && opt->split_shrink > 1.0f && isfinite(opt->split_shrink)))
+    return SGS_EINVAL;
+  if (out->capacity < 0) return SGS_EINVAL;
+  if (out->capacity > 0 &&
+      (!out->mean || !out->log_scale || !out->quat || !out->opa_logit || !out->sh ||
+       (p->skew && !out->skew) || (p->opa2_logit && !out->opa2_logit) ||
+       (p->opa_dir && !out->opa_dir)))
+    return SGS_EINVAL;
+  if (2 * p->n >= ((int64_t)1 << 32)) return SGS_EUNSUPPORTED;
+  return sgs::launch_densify(p, uv_sum, view_count, z_max, opt, decision, scratch, out, n_out_dev,
+                             (hipStream_t)stream);
+}
+
+sgs_status sgs_adam_step(const sgs_adam_group* groups, int32_t n_groups, float* state,
+                         float beta1, float beta2, float eps, void* stream) {
+  if (!groups || !state || n_groups <= 0 || n_groups > SGS_ADAM_MAX_GROUPS) return SGS_EINVAL;
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f))
+    return SGS_EINVAL;
+  for (int k = 0; k < n_groups; ++k) {
+    const sgs_adam_group& g = groups[k];
+    if (g.n < 0 || !isfinite(g.lr)) return SGS_EINVAL;
+    if (g.n > 0 && (!g.param || !g.grad || !g.m1 || !g.m2)) return SGS_EINVAL;
+  }
+  return sgs::launch_adam(groups, n_groups, state, beta1, beta2, eps, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -215,6 +215,13 @@ __device__ __forceinline__ void span_row(const Span& s, int row, int tw, int th,
 }
 
 // ---------------------------------------------------------------- wave ops
+// Wave vote on a condition held as a lane mask: the ballot of the bool
+// itself (the HIP __any / __all take an int, which costs a select and a
+// compare per call to turn the mask into an int and back).  Lanes that are
+// not active count as false for wave_any and as true for wave_all.
+__device__ __forceinline__ bool wave_any(bool b) { return __builtin_amdgcn_ballot_w64(b) != 0ull; }
+__device__ __forceinline__ bool wave_all(bool b) { return __builtin_amdgcn_ballot_w64(!b) == 0ull; }
+
 // v of the lane that the DPP control CTRL selects (0 where none).
 template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
 __device__ __forceinline__ float dpp_src(float v) {

@@ -155,7 +155,8 @@ def alloc_geom(m: int, n: int, n_views: int, enhanced: bool, device=DEV) -> tupl
         "tiles": torch.empty(max(m, 1), dtype=torch.int32, device=device),
         "block_off": torch.empty(int(lib.sgs_geom_block_entries(n, n_views)), dtype=torch.int32, device=device),
     }
-    g = _abi.Geom(_ptr(b["rec"]), _ptr(b["depth"]), _ptr(b["rect"]), _ptr(b["tiles"]), _ptr(b["block_off"]))
+    g = _abi.Geom(_ptr(b["rec"]), _ptr(b["depth"]), _ptr(b["rect"]), _ptr(b["tiles"]), _ptr(b["block_off"]),
+                  int(enhanced), 0)
     return g, b
 
 
@@ -188,12 +189,27 @@ def bin_sort(geom, bufs, m: int, cams: CameraBatch, opt: _abi.Options, capacity:
     return out
 
 
+N_INVALID = 0xFFFFFFFF     # instance count after a sort look-back that did not complete
+
+
+def check_instance_count(n: int, capacity: int, fn: str = "sgs_bin_sort") -> None:
+    """Raises SgsError when the device instance count reports a failed sort
+    (0xffffffff) or more instances than the buffers hold."""
+    n &= 0xFFFFFFFF
+    if n == N_INVALID:
+        raise _abi.SgsError(f"{fn}: a sort look-back did not complete; outputs invalid", 3)
+    if n > capacity:
+        raise _abi.SgsError(f"{fn}: {n} instances exceed the capacity {capacity}", 2)
+
+
 def render(gs: GaussianSet, cams: CameraBatch, opt: _abi.Options | None = None,
            keep_keys: bool = False, capacity: int | None = None, stream=None,
-           count: bool = False) -> Frame:
+           count: bool = False, check_count: bool = True) -> Frame:
     """Forward render of all views.  Without ``capacity`` the instance count
     is read back after the preprocess (one 4-byte device-to-host copy) and
-    buffers are sized exactly."""
+    buffers are sized exactly.  With ``check_count`` the sort's instance
+    count is read back after the blend (a second host sync) and a failed or
+    overflowed sort raises instead of returning its image."""
     lib = load()
     opt = opt if opt is not None else _abi.default_options()
     m = gs.n * cams.n_views
@@ -210,10 +226,13 @@ def render(gs: GaussianSet, cams: CameraBatch, opt: _abi.Options | None = None,
     out_T = torch.empty(P, dtype=torch.float32, device=dev)
     out_last = torch.empty(P, dtype=torch.int32, device=dev)
     bufs["count"] = torch.empty(P, dtype=torch.int32, device=dev) if count else None
+    bufs["eval"] = torch.empty(P, dtype=torch.int32, device=dev) if count else None
     check("sgs_render_fwd", lib.sgs_render_fwd(
         C.byref(geom), m, _ptr(bufs["vals"]), capacity, _ptr(bufs["ranges"]), None, cams.host, _ptr(cams.dev),
         cams.n_views, int(gs.enhanced), C.byref(opt), _ptr(out_rgb), _ptr(out_T), _ptr(out_last),
-        _ptr(bufs["count"]), P, _stream(stream)))
+        _ptr(bufs["count"]), _ptr(bufs["eval"]), P, _stream(stream)))
+    if check_count:
+        check_instance_count(int(bufs["n_inst"].item()), capacity)
     return Frame(gs, cams, opt, geom, bufs, capacity, out_rgb, out_T, out_last)
 
 
@@ -294,6 +313,36 @@ def rasterize(mean, log_scale, quat, skew, opa_logit, sh, cams: CameraBatch, opt
                                         opa_dir, cams, opt, sh_degree)
 
 
+def layout_totals(poses, opt: _abi.Options | None = None) -> tuple[int, int]:
+    """(total tiles, total pixels) of a batch of poses laid out in one tile
+    space, computed on the host (no device memory)."""
+    lib = load()
+    opt = opt if opt is not None else _abi.default_options()
+    arr = (_abi.Camera * len(poses))(*[CameraBatch.camera_from_pose(p) for p in poses])
+    tt, tp = C.c_int64(), C.c_int64()
+    check("sgs_camera_layout", lib.sgs_camera_layout(arr, len(poses), C.byref(opt), C.byref(tt), C.byref(tp)))
+    return int(tt.value), int(tp.value)
+
+
+def renderer_device_bytes(n: int, n_views: int, enhanced: bool, total_tiles: int, total_pixels: int,
+                          capacity: int, opt: _abi.Options | None = None, keep_keys: bool = False,
+                          count: bool = False, tile_order: bool = True, persistent: bool = False) -> int:
+    """Device bytes a Renderer with these sizes allocates for its forward
+    buffers, from the library's own size helpers (the same expressions as
+    Renderer.__init__ and alloc_geom)."""
+    lib = load()
+    opt = opt if opt is not None else _abi.default_options()
+    m = n * n_views
+    cap = max(int(capacity), 1)
+    geom = (4 * int(lib.sgs_geom_rec_floats(m, int(enhanced))) + 4 * max(m, 1) + 4 * max(2 * m, 2)
+            + 4 * max(m, 1) + 4 * int(lib.sgs_geom_block_entries(n, n_views)))
+    sort = (4 * cap + 8 * total_tiles + 4 + (8 * cap if (keep_keys or opt.sort_mode == 0) else 0)
+            + int(lib.sgs_bin_sort_scratch_bytes(m, int(capacity), total_tiles, C.byref(opt))))
+    out = 20 * total_pixels + (8 * total_pixels if count else 0)
+    sched = (4 * total_tiles if tile_order else 0) + (4 if persistent else 0)
+    return geom + sort + out + sched
+
+
 class Renderer:
     """Fixed-buffer renderer for one Gaussian set and one camera batch.
 
@@ -312,7 +361,7 @@ class Renderer:
         self.opt = opt if opt is not None else _abi.default_options()
         self.m = gs.n * cams.n_views
         self.geom, self.bufs = alloc_geom(self.m, gs.n, cams.n_views, gs.enhanced, gs.mean.device)
-        self.params = gs.struct()
+        self._params = None
         dev = gs.mean.device
         if capacity is None:
             self.preprocess()
@@ -335,11 +384,27 @@ class Renderer:
         self.out_T = torch.empty(P, dtype=torch.float32, device=dev)
         self.out_last = torch.empty(P, dtype=torch.int32, device=dev)
         b["count"] = torch.empty(P, dtype=torch.int32, device=dev) if count else None
+        b["eval"] = torch.empty(P, dtype=torch.int32, device=dev) if count else None
         b["tile_order"] = torch.empty(cams.total_tiles, dtype=torch.int32, device=dev) if tile_order else None
         b["work_counter"] = torch.zeros(1, dtype=torch.int32, device=dev) if persistent else None
         self.sched = _abi.Schedule(_ptr(b["tile_order"]), _ptr(b["work_counter"]))
         self._bwd = None
         self.graph = None
+
+    @property
+    def params(self) -> _abi.Params:
+        if self._params is None:
+            self._params = self.gs.struct()
+        return self._params
+
+    def device_bytes(self) -> int:
+        """Bytes of every buffer this renderer holds (forward buffers; the
+        backward's gradient buffer is added once backward() has run)."""
+        ts = [v for v in self.bufs.values() if isinstance(v, torch.Tensor)]
+        ts += [self.out_rgb, self.out_T, self.out_last]
+        if self._bwd is not None:
+            ts.append(self._bwd[0])
+        return sum(t.numel() * t.element_size() for t in ts)
 
     # ---- forward stages
     def preprocess(self, stream=None):
@@ -355,19 +420,25 @@ class Renderer:
             _ptr(b["n_inst"]), C.byref(self.sched), _ptr(b["scratch"]), self.scratch_bytes,
             _stream(stream)))
 
-    def blend(self, stream=None):
+    def blend(self, stream=None, count: bool | None = None):
+        """The forward blend; ``count`` (default: as constructed) also writes
+        the per-pixel composited and evaluated pair counts."""
         b = self.bufs
+        cnt = (b["count"] is not None) if count is None else count
+        if cnt and b["count"] is None:
+            raise ValueError("this Renderer was built without count buffers")
         check("sgs_render_fwd", self.lib.sgs_render_fwd(
             C.byref(self.geom), self.m, _ptr(b["vals"]), self.capacity, _ptr(b["ranges"]),
             C.byref(self.sched), self.cams.host, _ptr(self.cams.dev), self.cams.n_views,
             int(self.gs.enhanced),
             C.byref(self.opt), _ptr(self.out_rgb), _ptr(self.out_T), _ptr(self.out_last),
-            _ptr(b["count"]), self.cams.total_pixels, _stream(stream)))
+            _ptr(b["count"]) if cnt else None, _ptr(b["eval"]) if cnt else None,
+            self.cams.total_pixels, _stream(stream)))
 
-    def forward(self, stream=None) -> torch.Tensor:
+    def forward(self, stream=None, count: bool | None = None) -> torch.Tensor:
         self.preprocess(stream)
         self.bin_sort(stream)
-        self.blend(stream)
+        self.blend(stream, count)
         return self.out_rgb
 
     def capture(self):
@@ -396,7 +467,7 @@ class Renderer:
 
     def overflowed(self) -> bool:
         n = self.n_inst()
-        if n == 0xFFFFFFFF:
+        if n == N_INVALID:
             raise _abi.SgsError("sgs_bin_sort: a sort look-back did not complete; outputs invalid", 3)
         return n > self.capacity
 
@@ -434,3 +505,42 @@ class Renderer:
             _ptr(self.out_T), _ptr(self.out_last), _ptr(dL_drgb), self.cams.total_pixels,
             C.byref(gg), C.byref(pg), _stream(stream)))
         return grads
+
+
+def densify(gs: GaussianSet, stats: dict | None, opt: "_abi.DensifyOptions | None" = None,
+            capacity: int | None = None, stream=None):
+    """Densification step (sgs_densify): decisions (0 keep, 1 clone, 2 split)
+    from the statistics of densify_stats() accumulated by backward passes,
+    and the new GaussianSet with the cloned and split Gaussians.  Without
+    ``capacity`` the number of outputs is read back first (one host sync)
+    and the new set is sized exactly.  Returns (new set, decisions, parent
+    index of each new Gaussian)."""
+    lib = load()
+    if opt is None:
+        opt = _abi.DensifyOptions()
+        lib.sgs_default_densify_options(C.byref(opt))
+    dev = gs.mean.device
+    n = gs.n
+    st = stats or {}
+    decision = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int32, device=dev)
+    scratch = torch.empty(int(lib.sgs_densify_scratch_words(n)), dtype=torch.int32, device=dev)
+    p = gs.struct()
+
+    def call(out):
+        check("sgs_densify", lib.sgs_densify(C.byref(p), _ptr(st.get("uv")), _ptr(st.get("count")),
+                                             _ptr(st.get("z")), C.byref(opt), _ptr(decision), C.byref(out),
+                                             _ptr(n_out), _ptr(scratch), _stream(stream)))
+
+    if capacity is None:
+        call(_abi.DensifyOut())
+        capacity = int(n_out.item())
+    new = {f: (None if getattr(gs, f) is None else
+               torch.empty((*getattr(gs, f).shape[:-1], capacity), dtype=torch.float32, device=dev))
+           for f in GaussianSet.FIELDS}
+    parent = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    out = _abi.DensifyOut(capacity, *[_ptr(new[f]) for f in GaussianSet.FIELDS], _ptr(parent))
+    call(out)
+    ns = GaussianSet(new["mean"], new["log_scale"], new["quat"], new["skew"], new["opa_logit"], new["sh"],
+                     gs.sh_degree, new["opa2_logit"], new["opa_dir"])
+    return ns, decision[:n], parent[:capacity]

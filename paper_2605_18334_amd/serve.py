@@ -89,6 +89,7 @@ class RenderServer:
         self.results: list[Result] = []
         self.batches = 0
         self.failed = 0
+        self.concurrency = []     # requests admitted and not yet done, after each launch
         self._next_id = 0
         self._thread = None
         self._stop = threading.Event()
@@ -128,6 +129,7 @@ class RenderServer:
             self.inflight.append(b)
             self.batches += 1
             launched += 1
+            self.concurrency.append(sum(len(x.reqs) for x in self.inflight))
         return launched
 
     def _retire(self):
@@ -220,16 +222,29 @@ class RenderServer:
         return {"completed": len(lat), "failed": self.failed, "batches": self.batches,
                 "mean_batch": float(np.mean([r.batch_size for r in self.results])),
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                "mean_ms": float(lat.mean() * 1e3), "span_s": float(t1 - t0)}
+                "mean_ms": float(lat.mean() * 1e3), "span_s": float(t1 - t0),
+                "admitted_concurrency_mean": float(np.mean(self.concurrency)) if self.concurrency else 0.0,
+                "admitted_concurrency_max": int(max(self.concurrency, default=0)),
+                "reruns": int(getattr(self.backend, "reruns", 0))}
 
 
 # ------------------------------------------------------------------ GPU backend
 class GpuBackend:
     """Scenes resident on the GPU; each batch renders on a stream of its own
     (streams of default priority), with a completion event polled by the
-    scheduler.  Images are copied to pinned host memory on the same stream."""
+    scheduler.  Nothing here waits for the device: a batch's instance
+    capacity comes from the instances per pixel learnt from earlier batches
+    of its scene (with headroom), and its instance count and image are
+    copied to pinned host memory on its stream.  When the batch's event has
+    completed, done() reads the count: a batch that overflowed its capacity
+    is rendered again alone on the same stream with exactly the count it
+    reported (the library drops instances past the capacity and still
+    reports the true count), and is done only when that finishes; a failed
+    sort (0xffffffff) makes results() raise, and such a batch teaches the
+    capacity model nothing."""
 
-    def __init__(self, scenes: dict, opt=None, n_streams: int = 4, inst_per_pixel: float = 8.0):
+    def __init__(self, scenes: dict, opt=None, n_streams: int = 4, inst_per_pixel: float = 8.0,
+                 headroom: float = 1.3):
         import torch
         from . import _abi
         from .raster import GaussianSet
@@ -241,52 +256,73 @@ class GpuBackend:
         self.free_streams = list(range(n_streams))
         # instances per pixel, per scene: starts pessimistic, learnt from batches
         self.ipp = {k: inst_per_pixel for k in self.scenes}
+        self.headroom = float(headroom)
+        self.reruns = 0
+
+    def capacity_for(self, scene, total_pixels: int) -> int:
+        return int(self.ipp[scene] * total_pixels * self.headroom) + 4096
 
     def bytes_for(self, scene, poses) -> int:
+        """Device bytes of the batch's renderer, from the library's size
+        helpers at the capacity the batch will get."""
+        from .raster import layout_totals, renderer_device_bytes
         gs = self.scenes[scene]
-        P = sum(p.width * p.height for p in poses)
-        m = gs.n * len(poses)
-        rec = m * (48 + (16 if gs.enhanced else 0) + 16 + 12)       # records, depth, rect, tiles, sort
-        inst = int(self.ipp[scene] * P * 1.3) + 1024
-        return rec + inst * 20 + P * 24
+        tiles, pixels = layout_totals(poses, self.opt)
+        return renderer_device_bytes(gs.n, len(poses), gs.enhanced, tiles, pixels,
+                                     self.capacity_for(scene, pixels), self.opt)
 
-    def launch(self, scene, poses, want_images):
+    def _enqueue(self, scene, poses, want_images, capacity, si):
         torch = self.torch
         from .raster import CameraBatch, Renderer
+        s = self.streams[si]
+        with torch.cuda.stream(s):
+            cams = CameraBatch.from_poses(poses, self.opt)
+            if capacity is None:
+                capacity = self.capacity_for(scene, cams.total_pixels)
+            R = Renderer(self.scenes[scene], cams, self.opt, capacity=capacity)
+            R.forward()
+            n_host = torch.empty(1, dtype=torch.int32, pin_memory=True)
+            n_host.copy_(R.bufs["n_inst"], non_blocking=True)
+            host = None
+            if want_images:
+                host = torch.empty(R.out_rgb.shape, dtype=torch.float32, pin_memory=True)
+                host.copy_(R.out_rgb, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return {"R": R, "ev": ev, "host": host, "n_host": n_host}
+
+    def launch(self, scene, poses, want_images):
         if not self.free_streams:
             raise ServerError("no free stream")
         si = self.free_streams.pop()
-        s = self.streams[si]
         try:
-            with torch.cuda.stream(s):
-                cams = CameraBatch.from_poses(poses, self.opt)
-                # the constructor runs the preprocess and reads the instance
-                # count back (waits for this stream only); then bin and blend
-                R = Renderer(self.scenes[scene], cams, self.opt, headroom=1.0)
-                R.bin_sort()
-                R.blend()
-                imgs = []
-                host = None
-                if want_images:
-                    host = torch.empty(R.out_rgb.shape, dtype=torch.float32, pin_memory=True)
-                    host.copy_(R.out_rgb, non_blocking=True)
-                ev = torch.cuda.Event()
-                ev.record(s)
+            h = self._enqueue(scene, poses, want_images, None, si)
         except Exception:
             self.free_streams.append(si)
             raise
-        return {"R": R, "ev": ev, "host": host, "si": si, "poses": poses, "scene": scene}
+        h.update(si=si, poses=poses, scene=scene, want=want_images, rerun=False)
+        return h
 
     def done(self, h) -> bool:
-        return h["ev"].query()
+        if not h["ev"].query():
+            return False
+        n = int(h["n_host"][0]) & 0xFFFFFFFF
+        if n != 0xFFFFFFFF and n > h["R"].capacity and not h["rerun"]:
+            # overflow: render the batch again, sized exactly, on its stream
+            self.reruns += 1
+            h.update(self._enqueue(h["scene"], h["poses"], h["want"], n, h["si"]), rerun=True)
+            return False
+        return True
 
     def results(self, h):
+        from .raster import check_instance_count
         R, host = h["R"], h["host"]
-        P = sum(p.width * p.height for p in h["poses"])
-        n = R.n_inst()
+        n = int(h["n_host"][0]) & 0xFFFFFFFF
+        check_instance_count(n, R.capacity)
+        P = R.cams.total_pixels
         self.ipp[h["scene"]] = max(0.5 * self.ipp[h["scene"]], n / max(P, 1))
         out = []
-        for v, p in enumerate(h["poses"]):
+        for v in range(len(h["poses"])):
             c = R.cams.view(v)
             if host is not None:      # pinned host tensor, kept alive by the result
                 out.append(host[:, c.pix_base:c.pix_base + c.width * c.height].reshape(3, c.height, c.width))

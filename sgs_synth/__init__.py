@@ -305,11 +305,30 @@ def clustered_config(seed: int = 1):
     return sc, orbit_pose(15.0, az, math.radians(20.0), 1280, 720)
 
 
+def small_batch_config(seed: int = 1, n_views: int = 16):
+    """The clustered 300k SH3 scene seen from n_views 640x480 cameras on the
+    radius-15 orbit (elevation 20 deg, azimuths evenly spaced from the seed's):
+    many small views, where one launch per view leaves the GPU mostly idle."""
+    sc = clusters_scene(seed, 300_000, 3)
+    az0 = float(np.random.default_rng(seed + 1000).uniform(0, 2 * np.pi))
+    return sc, [orbit_pose(15.0, az0 + 2 * np.pi * k / n_views, math.radians(20.0), 640, 480)
+                for k in range(n_views)]
+
+
 def diff_config(seed: int = 2, target_seed: int = 3, n: int = 1_000_000):
     """1M skew Gaussians (blobs generator, SH0) at one 1600x1064 view from
     distance 8; the target image comes from a separately seeded 1M set."""
     pose = Pose(look_at_gl((0.0, 0.0, 8.0), up=(0, 1, 0)), 1600, 1064)
     return blobs_scene(seed, n, 0), blobs_scene(target_seed, n, 0), pose
+
+
+def train_config(seed: int = 2, target_seed: int = 3, n: int = 1_000_000, n_views: int = 4,
+                 pose_seed: int = 9):
+    """Multi-view training: the 1M-Gaussian differentiation scene and its
+    separately seeded target set, seen from n_views spline poses at
+    1600x1064 (distance 8 +- 1, looking at the origin)."""
+    poses = spline_poses(pose_seed, n_views, resolutions=[(1600, 1064)])
+    return blobs_scene(seed, n, 0), blobs_scene(target_seed, n, 0), poses
 
 
 def batch_config(seed: int = 5, n: int = 3_000_000, n_views: int = 16):

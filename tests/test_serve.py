@@ -167,3 +167,27 @@ def test_threaded_server_drains():
     futs = [srv.submit(_req("AB"[i % 2], 0.0)) for i in range(20)]
     srv.stop(drain=True, timeout=10)
     assert all(f.done() and f.result().image.startswith("img") for f in futs)
+
+
+def test_gpu_backend_memory_estimate_covers_what_a_renderer_allocates():
+    """bytes_for of the GPU backend, from the library's size helpers, is at
+    least the bytes of every buffer a Renderer of that batch allocates at the
+    capacity the backend would give it (sized here with CPU tensors: building
+    a Renderer with a fixed capacity touches no GPU)."""
+    from paper_2605_18334_amd import _abi
+    from paper_2605_18334_amd.raster import CameraBatch, GaussianSet, Renderer
+    from paper_2605_18334_amd.serve import GpuBackend
+    import numpy as np
+    rng = np.random.default_rng(3)
+    for enhanced, sh in ((False, 3), (True, 1)):
+        sc = S.blobs_scene(2, 1000, sh, enhanced=enhanced)
+        gs = GaussianSet.from_scene(sc, "cpu")
+        be = object.__new__(GpuBackend)          # no streams: sizing only
+        be.scenes, be.opt, be.ipp, be.headroom = {"A": gs}, _abi.default_options(), {"A": 11.0}, 1.3
+        for views in (1, 3):
+            poses = [S.random_request_pose(rng) for _ in range(views)]
+            cams = CameraBatch.from_poses(poses, be.opt, device="cpu")
+            R = Renderer(gs, cams, be.opt, capacity=be.capacity_for("A", cams.total_pixels))
+            est = be.bytes_for("A", poses)
+            assert est >= R.device_bytes() > 0
+            assert est == R.device_bytes()        # the same expressions, nothing missed or extra
