@@ -672,7 +672,38 @@ def render_grad(scene, pose_or_cam, dL_dC: np.ndarray, pixels: np.ndarray | None
     derivative.  Returns float64 numpy arrays in the scene's SoA shapes."""
     cam = pose_or_cam if isinstance(pose_or_cam, Camera) else camera_from_pose(pose_or_cam)
     P = to_tensors(scene, requires_grad=True)
-    total, _ = _loss_graph(P, scene.sh_degree, cam, dL_dC, pixels, opt, chunk_elems)
+    pr = project(P, scene.sh_degree, cam, opt)
+    # chain rule in two stages (memory stays bounded for large scenes): the
+    # gradient of L with respect to the projected quantities, accumulated over
+    # pixel chunks, then pulled back through the projection once
+    names = [f for f in ("mu2d", "conic", "rho", "o1", "o2", "beta2d", "w2d", "rgb")
+             if getattr(pr, f) is not None and getattr(pr, f).requires_grad]
+    det = {f: getattr(pr, f).detach().requires_grad_(True) for f in names}
+    prd = Projected(**{**{k: v for k, v in pr.__dict__.items()}, **det})
+    acc = {f: torch.zeros_like(det[f]) for f in names}
+    order = depth_order(pr)
+    pixels, pc = pixel_centres(cam, pixels)
+    g = torch.from_numpy(np.asarray(dL_dC, np.float64).reshape(-1, 3))
+    bg = torch.from_numpy(cam.bg.astype(np.float64))
+    step = max(1, chunk_elems // max(1, order.numel()))
+    for s in range(0, pc.shape[0], step):
+        pcs = pc[s:s + step]
+        with torch.no_grad():     # decisions on the full ordered list
+            inc = inclusion(alpha_tilde(pcs, prd, order, opt), opt)
+            cols = torch.nonzero(inc.any(0)).flatten()
+        if cols.numel() == 0:
+            continue
+        # pairs never included have no value and no derivative: keep only the
+        # Gaussians included at some pixel of the chunk, with the same decisions
+        sub = order[cols]
+        at = alpha_tilde(pcs, prd, sub, opt)
+        C, _ = composite(at, prd.rgb[sub], bg, inc[:, cols], opt)
+        lc = (C * g[s:s + step]).sum()
+        gr = torch.autograd.grad(lc, [det[f] for f in names], allow_unused=True)
+        for f, v in zip(names, gr):
+            if v is not None:
+                acc[f] += v
+    total = sum((getattr(pr, f) * acc[f]).sum() for f in names)
     leaves = {k: v for k, v in P.items() if v is not None}
     grads = torch.autograd.grad(total, list(leaves.values()), allow_unused=True)
     out = {}
