@@ -25,13 +25,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# fp32 vector issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s,
-# an FMA counting 2 flops -> 78.6 TFLOP/s (packed FP32 is not used)
-ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
-# flops of Alg. 1 per composited (pixel, Gaussian) pair, exp and erf 1 each:
-# offsets 2, quadratic form 9, exp 1, skew argument 4, erf 1, 1+erf 1,
-# alpha 2, T(1-alpha) 2, colour accumulation 7
-FLOPS_PER_PAIR = 29
+# MI355X's published fp32 vector peak (packed FP32, an FMA counting 2 flops)
+ALU_PEAK_TFLOPS = 157.3
+# the rate without packed FP32 (which this build disables): 256 CUs x 4 SIMD
+# x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s, an FMA counting 2 -> 78.6 TFLOP/s
+ALU_PEAK_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# flops of Alg. 1 per pair, exp and erf counted 1 each: evaluating alpha of a
+# pair (offsets 2, quadratic form 9, exp 1, skew argument 4, erf 1, 1+erf 1,
+# alpha product and clamp 2) = 20, for every pair past the exponent test;
+# compositing a pair (T(1-alpha) 2, colour accumulation 7) = 9 more
+FLOPS_EVAL = 20
+FLOPS_COMPOSITE = 9
 
 
 def log(*a):
@@ -80,12 +84,12 @@ def timed_forward(R, steps: int, warmup: int):
     the step)."""
     import torch
     for _ in range(warmup):
-        R.forward()
+        R.forward(count=False)
     torch.cuda.synchronize()
     t_w = time.perf_counter()
     while time.perf_counter() - t_w < 0.3:
         for _ in range(10):
-            R.forward()
+            R.forward(count=False)
         torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     for e in ev:
@@ -94,7 +98,7 @@ def timed_forward(R, steps: int, warmup: int):
         e[1].record()
         R.bin_sort()
         e[2].record()
-        R.blend()
+        R.blend(count=False)
         e[3].record()
     torch.cuda.synchronize()
     stages = {"preprocess": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
@@ -110,13 +114,30 @@ def timed_forward(R, steps: int, warmup: int):
         R.preprocess()
         R.bin_sort()
         b[0].record()
-        R.blend()
+        R.blend(count=False)
         b[1].record()
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     blend_ms = float(np.mean([b[0].elapsed_time(b[1]) for b in bl]))
     return start.elapsed_time(end) / steps, wall, stages, blend_ms
+
+
+def host_cpu() -> dict:
+    """The host the CPU baseline ran on: logical CPUs, the affinity mask's
+    size, OMP_NUM_THREADS, torch's thread count and the CPU model."""
+    import torch
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"), "torch_threads": torch.get_num_threads(),
+            "cpu_model": model}
 
 
 def cpu_baseline(sc, pose, target_s: float):
@@ -138,7 +159,55 @@ def cpu_baseline(sc, pose, target_s: float):
         n = int(min(max(2 * n, n * target_s / max(t, 1e-3)), 1 << 16))
     return {"value": n / t / 1e6, "unit": "Mpix/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} seeded tile-stratified pixels of the same 300k-Gaussian 1280x720 view, "
-                      f"brute force over all Gaussians in FP64 ({t:.1f} s)"}
+                      f"brute force over all Gaussians in FP64 ({t:.1f} s); the full-size parity tests "
+                      f"use 4096 such pixels, computed beforehand",
+            "host": host_cpu()}
+
+
+def sort_stage_bytes(m: int, n_inst: int, total_tiles: int, depth_passes: int) -> dict:
+    """Algorithmic HBM bytes of the bin/sort stage (sort mode 1) and, for
+    comparison, of the plain form the method describes (duplicate with
+    64-bit (tile, depth) keys, LSD sort of 8-bit digits over all key bits)."""
+    tb = max(1, math.ceil(math.log2(max(total_tiles, 2))))
+    moved = (m * (4 + depth_passes * 16)          # depth presort: histogram read, passes r+w key and id
+             + m * 12                             # offsets: order, tile count in; offset out
+             + m * 64                             # expansion: one record line per record
+             + n_inst * 8                         # expansion writes key and value
+             + n_inst * 16 * math.ceil(tb / 8))   # tile-key passes: read + write key and value
+    passes64 = math.ceil((tb + 32) / 8)
+    plain = m * (8 + 16) + n_inst * 12 + n_inst * (8 + passes64 * 24)
+    return {"moved": moved, "plain_64bit_lsd": plain}
+
+
+def stage_bandwidth(pre_bytes: int, sb: dict, stages: dict) -> dict:
+    """Algorithmic HBM rates of the preprocess and bin/sort stages (all their
+    kernels, whole-stage times); the bin/sort also as the rate at which the
+    plain 64-bit-key LSD form's bytes would have to move to finish as soon."""
+    out = {"preprocess": {"GB/s": pre_bytes / (stages["preprocess"] / 1e3) / 1e9},
+           "bin_sort": {"GB/s": sb["moved"] / (stages["bin_sort"] / 1e3) / 1e9,
+                        "plain_64bit_lsd_equivalent_GB/s": sb["plain_64bit_lsd"] / (stages["bin_sort"] / 1e3) / 1e9}}
+    for v in out.values():
+        v["frac"] = v["GB/s"] / HBM_PEAK_GBS
+    return out
+
+
+def stage_times(R, reps: int = 20) -> dict:
+    """Per-stage times of the forward (events between the stages, a loop of
+    its own)."""
+    import torch
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+    for e in ev:
+        e[0].record()
+        R.preprocess()
+        e[1].record()
+        R.bin_sort()
+        e[2].record()
+        R.blend(count=False)
+        e[3].record()
+    torch.cuda.synchronize()
+    return {"preprocess": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
+            "bin_sort": float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
+            "blend_fwd": float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))}
 
 
 def fwd_bwd(steps: int, warmup: int):
@@ -178,7 +247,11 @@ def fwd_bwd(steps: int, warmup: int):
     wall = time.perf_counter() - t0
     gpu_ms = ev[0][0].elapsed_time(ev[-1][2])
     assert not R.overflowed()
+    stages = stage_times(R)
+    pre_bytes = sc.n * (56 + sh_bytes(sc.sh_degree)) + sc.n * 64
+    sbw = stage_bandwidth(pre_bytes, sort_stage_bytes(sc.n, R.n_inst(), cams.total_tiles, 3), stages)
     return {"metric": "fwd+bwd iters/s at 1M Gaussians", "value": steps / (gpu_ms / 1e3), "unit": "iters/s",
+            "stages_ms": stages, "stage_bandwidth": sbw,
             "wall_iters_s": steps / wall,
             "ms_fwd": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
             "ms_bwd": float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
@@ -187,14 +260,81 @@ def fwd_bwd(steps: int, warmup: int):
                                    "L1 loss vs a separately seeded 1M target"}}
 
 
-def batched(steps: int, warmup: int):
-    """16 views of mixed resolution of a 3M-Gaussian scene: one HIP-graph
-    launch of the autotuned batch vs 16 sequential single-view renders."""
+def train_multiview(steps: int, warmup: int):
+    """Multi-view training step at 1M Gaussians: 4 views of 1600x1064 in one
+    tile space, per-view L1 gradient, one backward accumulating all views,
+    Adam; the whole step replayed as one HIP graph.  Beside it, the same
+    work as 4 single-view forward/backward passes and one Adam step, eager."""
+    import torch
+    import paper_2605_18334_amd as P
+    from paper_2605_18334_amd.train import Adam, MultiViewTrainer, l1_weights
+    import sgs_synth as S
+    sc, tgt, poses = S.train_config()
+    opt = P.default_options()
+    cams = P.CameraBatch.from_poses(poses, opt)
+    T = P.Renderer(P.GaussianSet.from_scene(tgt), cams, opt)
+    target = T.forward().clone()
+    del T, tgt
+    tr = MultiViewTrainer(P.GaussianSet.from_scene(sc), poses, target, opt, headroom=1.25)
+    tr.capture()
+    for _ in range(warmup):
+        tr.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+    assert not tr.overflowed()
+    n_inst = tr.R.n_inst()
+    del tr
+    torch.cuda.empty_cache()
+    # the same step as V single-view passes (eager), gradients summed, one Adam
+    gs = P.GaussianSet.from_scene(sc)
+    singles = []
+    for v, p in enumerate(poses):
+        c1 = P.CameraBatch.from_poses([p], opt)
+        c = cams.view(v)
+        singles.append((P.Renderer(gs, c1, opt, headroom=1.25), target[:, c.pix_base:c.pix_base + c.width * c.height],
+                        l1_weights(c1, target.device)))
+    ad = Adam(gs)
+    total = {f: torch.zeros_like(getattr(gs, f)) for f in ad.names}
+
+    def seq_step():
+        for f in ad.names:
+            total[f].zero_()
+        for R, tv, w in singles:
+            out = R.forward()
+            g = R.backward(torch.sign(out - tv).mul_(w))
+            for f in ad.names:
+                total[f].add_(g[f])
+        ad.step(total)
+
+    for _ in range(warmup):
+        seq_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        seq_step()
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3 / steps
+    assert not any(R.overflowed() for R, _, _ in singles)
+    return {"metric": "multi-view training iters/s at 1M Gaussians", "value": 1e3 / ms_graph, "unit": "iters/s",
+            "ms_step_graph": ms_graph, "ms_step_sequential": ms_seq, "speedup_vs_sequential": ms_seq / ms_graph,
+            "views_per_s": len(poses) * 1e3 / ms_graph, "n_inst": n_inst,
+            "config": {"workload": "1M skew Gaussians (4-blob generator, SH0), 4 spline views at 1600x1064, "
+                                   "L1 loss vs a separately seeded 1M target, Adam; one HIP graph per step"}}
+
+
+def batched(steps: int, warmup: int, small: bool = False):
+    """16 views of mixed resolution of a 3M-Gaussian scene (small: 16
+    640x480 views of the 300k clustered scene): one HIP-graph launch of the
+    autotuned batch vs 16 sequential single-view renders."""
     import torch
     import paper_2605_18334_amd as P
     from paper_2605_18334_amd.batch import BatchRenderer, autotune
     import sgs_synth as S
-    sc, poses = S.batch_config()
+    sc, poses = S.small_batch_config() if small else S.batch_config()
     gs = P.GaussianSet.from_scene(sc)
     del sc
     cfg, timings = autotune(gs, poses, reps=2, log=log)
@@ -227,11 +367,16 @@ def batched(steps: int, warmup: int):
            "ms_batched": ms_b, "ms_sequential": ms_s, "speedup_vs_sequential": ms_s / ms_b,
            "sequential_mpix_s": px / (ms_s / 1e3) / 1e6, "bit_identical_to_single_views": same,
            "n_inst": br.n_inst(), "tuned": {k: v for k, v in cfg.__dict__.items()},
-           "config": {"workload": "3M skew Gaussians (4-blob generator, SH0), 16 spline poses at "
-                                  "640x480/1280x720/1600x1064/1920x1080 (4 each)"}}
+           "config": {"workload": ("300k skew Gaussians (32-cluster generator, SH3), 16 orbit views at 640x480"
+                                   if small else
+                                   "3M skew Gaussians (4-blob generator, SH0), 16 spline poses at "
+                                   "640x480/1280x720/1600x1064/1920x1080 (4 each)")}}
     del br, singles
     torch.cuda.empty_cache()
     return out
+
+
+SERVE_RATES = [60, 120, 240, 600]
 
 
 def serving(duration_s: float, rates):
@@ -290,8 +435,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
-    ap.add_argument("--only", choices=["fwd", "fwdbwd", "batch", "serve"], default=None,
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--only", choices=["fwd", "fwdbwd", "train", "batch", "serve"], default=None,
                     help="run one workload only (for profiler runs)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
@@ -317,11 +463,15 @@ def main():
     if args.only == "fwdbwd":
         print(json.dumps(fwd_bwd(max(3, args.steps // 2), 2)), flush=True)
         return
+    if args.only == "train":
+        print(json.dumps(train_multiview(max(3, args.steps // 4), 2)), flush=True)
+        return
     if args.only == "batch":
-        print(json.dumps(batched(max(3, args.steps // 4), 1)), flush=True)
+        print(json.dumps({"batched": batched(max(3, args.steps // 4), 1),
+                          "batched_small": batched(max(10, args.steps // 2), 3, small=True)}), flush=True)
         return
     if args.only == "serve":
-        print(json.dumps(serving(args.serve_seconds, [60, 240, 600])), flush=True)
+        print(json.dumps(serving(args.serve_seconds, SERVE_RATES)), flush=True)
         return
     sc, pose = S.clustered_config()
     opt = P.default_options()
@@ -331,31 +481,28 @@ def main():
     ms, wall, stages, blend_ms = timed_forward(R, args.steps, args.warmup)
     assert not R.overflowed()
     n_inst = R.n_inst()
+    # the work counters run outside the timed region (the counting variant of
+    # the blend has extra instructions)
+    R.forward(count=True)
     pairs = int(R.bufs["count"].to(torch.int64).sum().item())
+    evaluated = int(R.bufs["eval"].to(torch.int64).sum().item())
     npix = pose.width * pose.height
     mpix_s = npix / (ms / 1e3) / 1e6
     log(f"forward {ms:.3f} ms/step, stages {stages}, n_inst {n_inst}, pairs {pairs}")
 
     # roofline of the dominant kernel: the blend forward is the longest single
     # launch (bin/sort is a dozen kernels, each far shorter; see profiles/)
-    achieved = pairs * FLOPS_PER_PAIR / (blend_ms / 1e3) / 1e12
+    flops = evaluated * FLOPS_EVAL + pairs * FLOPS_COMPOSITE
+    achieved = flops / (blend_ms / 1e3) / 1e12
     roof = {"kernel": "k_blend_fwd", "bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
             "traffic": measured_traffic("k_blend_fwd"),
-            "units": f"{pairs} composited pairs x {FLOPS_PER_PAIR} flops"}
+            "peak_nonpacked": ALU_PEAK_NONPACKED_TFLOPS, "frac_nonpacked": achieved / ALU_PEAK_NONPACKED_TFLOPS,
+            "units": f"{evaluated} evaluated pairs x {FLOPS_EVAL} + {pairs} composited pairs x "
+                     f"{FLOPS_COMPOSITE} flops, per launch"}
     # algorithmic HBM rates of the other stages (whole stage, all its kernels)
     pre_bytes = sc.n * (56 + sh_bytes(sc.sh_degree)) + sc.n * 64
-    tb = max(1, math.ceil(math.log2(max(cams.total_tiles, 2))))
-    sort_bytes = (sc.n * (4 + 4 * 16)                # depth presort: histogram read, 4 passes r+w key, id
-                  + sc.n * 12                        # offsets: order, tile count in; offset out
-                  + n_inst * 8                       # expansion writes key and value
-                  + n_inst * 16 * math.ceil(tb / 8))   # tile-key passes: read + write key and value
-    stage_bw = {
-        "preprocess": {"GB/s": pre_bytes / (stages["preprocess"] / 1e3) / 1e9},
-        "bin_sort": {"GB/s": sort_bytes / (stages["bin_sort"] / 1e3) / 1e9},
-    }
-    for v in stage_bw.values():
-        v["frac"] = v["GB/s"] / HBM_PEAK_GBS
+    stage_bw = stage_bandwidth(pre_bytes, sort_stage_bytes(sc.n, n_inst, cams.total_tiles, 3), stages)
 
     out = {
         "metric": "Mpix/s render fwd", "value": mpix_s, "unit": "Mpix/s", "n_gpus": 1,
@@ -364,7 +511,7 @@ def main():
         "config": {"workload": "300k skew Gaussians (32-cluster generator), SH3, one 1280x720 view, "
                                "fov 60, radius-15 orbit; forward = preprocess + bin/sort + blend",
                    "global_batch": 1, "seq_len": None, "parallelism": "1 GPU"},
-        "stages_ms": stages, "n_inst": n_inst, "composited_pairs": pairs,
+        "stages_ms": stages, "n_inst": n_inst, "composited_pairs": pairs, "evaluated_pairs": evaluated,
         "roofline": roof, "stage_bandwidth": stage_bw,
     }
     if not args.no_bwd and args.only is None:
@@ -372,12 +519,18 @@ def main():
         torch.cuda.empty_cache()
         out["fwd_bwd"] = fwd_bwd(max(3, args.steps // 2), 2)
         log(f"fwd+bwd {out['fwd_bwd']}")
+    if not args.no_train and args.only is None:
+        torch.cuda.empty_cache()
+        out["train_multiview"] = train_multiview(max(3, args.steps // 4), 2)
+        log(f"train {out['train_multiview']}")
     if not args.no_batch and args.only is None:
         torch.cuda.empty_cache()
         out["batched"] = batched(max(3, args.steps // 4), 1)
+        torch.cuda.empty_cache()
+        out["batched_small"] = batched(max(10, args.steps // 2), 3, small=True)
     if not args.no_serve and args.only is None:
         torch.cuda.empty_cache()
-        out["served"] = serving(args.serve_seconds, [60, 240, 600])
+        out["served"] = serving(args.serve_seconds, SERVE_RATES)
     if not args.no_cpu and args.only is None:
         out["cpu_baseline"] = cpu_baseline(sc, pose, args.cpu_seconds)
     print(json.dumps(out), flush=True)

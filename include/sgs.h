@@ -148,8 +148,10 @@ typedef struct {
                               mode 1): 8 (4 passes over the 32-bit keys),
                               10 (3 passes over keys shifted to 30 bits; needs
                               every near_z > 0 and at most 16.7M records,
-                              else 8 is used), 0: 10 when possible.  Same
-                              order either way.                             */
+                              else 8 is used), 0: 8 (the fewer, wider
+                              passes measured slower on gfx950: each pass's
+                              LDS ranking grows with the digit).  Same order
+                              either way.                                   */
 } sgs_options;
 
 /* Projected per-record data written by sgs_preprocess, record m = v*N + i for

@@ -1075,7 +1075,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
                            uint32_t* n_inst, uint32_t* tile_order, void* scratch, float near_min,
                            hipStream_t s) {
   const int mode = opt->sort_mode;
-  const bool wide = mode == 1 && opt->depth_digit_bits != 8 && wide_depth((uint64_t)m, near_min);
+  const bool wide = mode == 1 && opt->depth_digit_bits == 10 && wide_depth((uint64_t)m, near_min);
   const BinLayout L = bin_layout(reinterpret_cast<uintptr_t>(scratch), m, cap, total_tiles, mode);
   const uint64_t T = (uint64_t)total_tiles, C = (uint64_t)cap;
   uint32_t* err = L.misc;
