@@ -164,19 +164,46 @@ def cpu_baseline(sc, pose, target_s: float):
             "host": host_cpu()}
 
 
-def sort_stage_bytes(m: int, n_inst: int, total_tiles: int, depth_passes: int) -> dict:
-    """Algorithmic HBM bytes of the bin/sort stage (sort mode 1) and, for
-    comparison, of the plain form the method describes (duplicate with
+def sort_stage_bytes(m: int, n_inst: int, total_tiles: int, depth_passes: int, mode: int = 1,
+                     n_items: int = 0, item_passes: int = 1) -> dict:
+    """Algorithmic HBM bytes of the bin/sort stage in the sort mode that ran
+    (1: duplicate + tile-key sort; 2: row items + row sort + placement) and,
+    for comparison, of the plain form the method describes (duplicate with
     64-bit (tile, depth) keys, LSD sort of 8-bit digits over all key bits)."""
     tb = max(1, math.ceil(math.log2(max(total_tiles, 2))))
-    moved = (m * (4 + depth_passes * 16)          # depth presort: histogram read, passes r+w key and id
-             + m * 12                             # offsets: order, tile count in; offset out
-             + m * 64                             # expansion: one record line per record
-             + n_inst * 8                         # expansion writes key and value
-             + n_inst * 16 * math.ceil(tb / 8))   # tile-key passes: read + write key and value
+    common = (m * (4 + depth_passes * 16)     # depth presort: histogram read, passes r+w key and id
+              + m * 12                        # offsets: order, count in; offset out
+              + m * 64)                       # expansion / emission: one record line per record
+    if mode == 2:
+        moved = (common
+                 + n_items * 8                    # emission writes item key and record
+                 + n_items * 16 * item_passes     # row passes: read + write key and record
+                 + n_items * 4                    # piece counts: item keys
+                 + n_items * 8 + n_inst * 4)      # placement: items in, record per instance out
+    else:
+        moved = (common
+                 + n_inst * 8                     # expansion writes key and value
+                 + n_inst * 16 * math.ceil(tb / 8))   # tile-key passes: read + write key and value
     passes64 = math.ceil((tb + 32) / 8)
     plain = m * (8 + 16) + n_inst * 12 + n_inst * (8 + passes64 * 24)
-    return {"moved": moved, "plain_64bit_lsd": plain}
+    return {"moved": moved, "plain_64bit_lsd": plain, "sort_mode": mode, "n_items": n_items}
+
+
+def sort_info(R) -> dict:
+    """The sort mode the library runs for a Renderer and, for mode 2, its row
+    items (the non-empty tile rows of all records) and row-sort passes."""
+    import ctypes as C
+    lib = R.lib
+    mode = int(lib.sgs_bin_sort_mode(C.byref(R.opt), R.capacity, R.cams.host, R.cams.n_views, 1))
+    n_items = int(R.bufs["rows"][:R.m].to(torch_int64()).sum().item()) if mode == 2 else 0
+    rows = sum(R.cams.view(v).tiles_y for v in range(R.cams.n_views))
+    item_passes = 1 if rows <= 256 else 2
+    return {"mode": mode, "n_items": n_items, "item_passes": item_passes}
+
+
+def torch_int64():
+    import torch
+    return torch.int64
 
 
 def stage_bandwidth(pre_bytes: int, sb: dict, stages: dict) -> dict:
@@ -185,7 +212,9 @@ def stage_bandwidth(pre_bytes: int, sb: dict, stages: dict) -> dict:
     plain 64-bit-key LSD form's bytes would have to move to finish as soon."""
     out = {"preprocess": {"GB/s": pre_bytes / (stages["preprocess"] / 1e3) / 1e9},
            "bin_sort": {"GB/s": sb["moved"] / (stages["bin_sort"] / 1e3) / 1e9,
-                        "plain_64bit_lsd_equivalent_GB/s": sb["plain_64bit_lsd"] / (stages["bin_sort"] / 1e3) / 1e9}}
+                        "plain_64bit_lsd_equivalent_GB/s": sb["plain_64bit_lsd"] / (stages["bin_sort"] / 1e3) / 1e9,
+                        "sort_mode": sb["sort_mode"], "moved_MB": sb["moved"] / 1e6,
+                        "row_items": sb["n_items"]}}
     for v in out.values():
         v["frac"] = v["GB/s"] / HBM_PEAK_GBS
     return out
@@ -216,7 +245,7 @@ def fwd_bwd(steps: int, warmup: int):
     import paper_2605_18334_amd as P
     import sgs_synth as S
     sc, tgt, pose = S.diff_config()
-    opt = P.default_options()
+    opt = P.default_options(**OPT_OVER)
     cams = P.CameraBatch.from_poses([pose], opt)
     T = P.Renderer(P.GaussianSet.from_scene(tgt), cams, opt)
     target = T.forward().clone()
@@ -249,7 +278,9 @@ def fwd_bwd(steps: int, warmup: int):
     assert not R.overflowed()
     stages = stage_times(R)
     pre_bytes = sc.n * (56 + sh_bytes(sc.sh_degree)) + sc.n * 64
-    sbw = stage_bandwidth(pre_bytes, sort_stage_bytes(sc.n, R.n_inst(), cams.total_tiles, 3), stages)
+    si = sort_info(R)
+    sbw = stage_bandwidth(pre_bytes, sort_stage_bytes(sc.n, R.n_inst(), cams.total_tiles, 4, si["mode"],
+                                                      si["n_items"], si["item_passes"]), stages)
     return {"metric": "fwd+bwd iters/s at 1M Gaussians", "value": steps / (gpu_ms / 1e3), "unit": "iters/s",
             "stages_ms": stages, "stage_bandwidth": sbw,
             "wall_iters_s": steps / wall,
@@ -270,7 +301,7 @@ def train_multiview(steps: int, warmup: int):
     from paper_2605_18334_amd.train import Adam, MultiViewTrainer, l1_weights
     import sgs_synth as S
     sc, tgt, poses = S.train_config()
-    opt = P.default_options()
+    opt = P.default_options(**OPT_OVER)
     cams = P.CameraBatch.from_poses(poses, opt)
     T = P.Renderer(P.GaussianSet.from_scene(tgt), cams, opt)
     target = T.forward().clone()
@@ -349,7 +380,7 @@ def batched(steps: int, warmup: int, small: bool = False):
     torch.cuda.synchronize()
     ms_b = (time.perf_counter() - t0) * 1e3 / steps
     assert not br.overflowed()
-    o = P.default_options()
+    o = P.default_options(**OPT_OVER)
     singles = [P.Renderer(gs, P.CameraBatch.from_poses([p], o), o) for p in poses]
     for _ in range(warmup):
         for r in singles:
@@ -377,6 +408,7 @@ def batched(steps: int, warmup: int, small: bool = False):
 
 
 SERVE_RATES = [60, 120, 240, 600]
+OPT_OVER: dict = {}        # option overrides from the command line (--sort-mode)
 
 
 def serving(duration_s: float, rates):
@@ -439,10 +471,14 @@ def main():
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--only", choices=["fwd", "fwdbwd", "train", "batch", "serve"], default=None,
                     help="run one workload only (for profiler runs)")
+    ap.add_argument("--sort-mode", type=int, default=None, choices=[0, 1, 2],
+                    help="override the library's default sort mode in every workload")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
                          "kernel that scales hardware byte counters)")
     args = ap.parse_args()
+    if args.sort_mode is not None:
+        OPT_OVER["sort_mode"] = args.sort_mode
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
         print("bench.py measures one GPU: this build renders on a single MI355X "
@@ -474,7 +510,7 @@ def main():
         print(json.dumps(serving(args.serve_seconds, SERVE_RATES)), flush=True)
         return
     sc, pose = S.clustered_config()
-    opt = P.default_options()
+    opt = P.default_options(**OPT_OVER)
     gs = P.GaussianSet.from_scene(sc)
     cams = P.CameraBatch.from_poses([pose], opt)
     R = P.Renderer(gs, cams, opt, count=True)
@@ -502,7 +538,9 @@ def main():
                      f"{FLOPS_COMPOSITE} flops, per launch"}
     # algorithmic HBM rates of the other stages (whole stage, all its kernels)
     pre_bytes = sc.n * (56 + sh_bytes(sc.sh_degree)) + sc.n * 64
-    stage_bw = stage_bandwidth(pre_bytes, sort_stage_bytes(sc.n, n_inst, cams.total_tiles, 3), stages)
+    si = sort_info(R)
+    stage_bw = stage_bandwidth(pre_bytes, sort_stage_bytes(sc.n, n_inst, cams.total_tiles, 4, si["mode"],
+                                                           si["n_items"], si["item_passes"]), stages)
 
     out = {
         "metric": "Mpix/s render fwd", "value": mpix_s, "unit": "Mpix/s", "n_gpus": 1,

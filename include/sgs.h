@@ -121,6 +121,9 @@ typedef struct {
   int64_t pix_base;        /* first pixel of this view in the output planes */
 } sgs_camera;
 
+/* Instance capacity from which sort_mode -1 runs mode 2. */
+#define SGS_AUTO_ROWBIN_CAPACITY ((int64_t)1 << 22)
+
 /* Pipeline options; sgs_default_options fills the values in brackets. */
 typedef struct {
   int32_t tile_w, tile_h;  /* [16, 16]; also 16x8 and 8x8                  */
@@ -130,10 +133,19 @@ typedef struct {
   float alpha_min;         /* [1/255] pairs below are skipped               */
   float alpha_max;         /* [0.99] alpha clamp                            */
   float t_min;             /* [1e-4] a pixel stops before T drops below     */
-  int32_t sort_mode;       /* [1] 0: 64-bit (tile<<32 | depth) keys, one LSD
+  int32_t sort_mode;       /* [-1] 0: 64-bit (tile<<32 | depth) keys, one LSD
                               sort; 1: stable depth presort of the records,
                               duplicate in depth order, LSD sort of 32-bit
-                              tile keys.  Both give the identical order.    */
+                              tile keys; 2: depth presort, one item per
+                              non-empty tile row of each record, stable sort
+                              of the items by tile row, then each row's
+                              items placed into its tiles (needs
+                              sgs_geom.rows, at most 64 views, 256 tiles per
+                              row and 65536 tile rows per call; otherwise
+                              mode 1 runs); -1: mode 2 from an instance
+                              capacity of SGS_AUTO_ROWBIN_CAPACITY up, else
+                              mode 1 (measured faster at small sizes).  All
+                              give the identical order.                     */
   int32_t blend_batch;     /* [0] records staged in LDS per batch: 64, 128, 256; 0: 128 in the
                               forward blend, 256 in the backward */
   int32_t split_tiles;     /* [-1] with 16x16 tiles and a tile order (and no
@@ -177,6 +189,9 @@ typedef struct {
   uint32_t* block_off;     /* [sgs_geom_block_entries(N, V)] exclusive prefix of the
                               tile counts per block of 256 records of one view
                               (view-major); the last entry is the total      */
+  uint32_t* rows;          /* [M] number of tile rows of the rect with at
+                              least one covered tile (0 = culled); written
+                              when non-NULL, needed by sort_mode 2          */
   int32_t enhanced;        /* 1: records carry enhanced opacity (slot 3)   */
   int32_t _pad;
 } sgs_geom;
@@ -238,6 +253,13 @@ int64_t sgs_geom_block_entries(int64_t n, int32_t n_views);
  * number of tiles (same options). */
 size_t sgs_bin_sort_scratch_bytes(int64_t m, int64_t inst_capacity, int64_t total_tiles,
                                   const sgs_options* opt);
+
+/* The sort mode (0, 1 or 2) sgs_bin_sort runs for these options, capacity
+ * and cameras (host array), given whether sgs_geom.rows is set; -1 for
+ * arguments sgs_bin_sort rejects.  For reports and tests: the results are
+ * the same in every mode. */
+int32_t sgs_bin_sort_mode(const sgs_options* opt, int64_t inst_capacity, const sgs_camera* cams_host,
+                          int32_t n_views, int32_t have_rows);
 
 /* ------------------------------------------------------------------ calls */
 

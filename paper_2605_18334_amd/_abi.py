@@ -42,7 +42,7 @@ class Options(C.Structure):
 
 
 class Geom(C.Structure):
-    _fields_ = [("rec", P), ("depth", P), ("rect", P), ("tiles", P), ("block_off", P),
+    _fields_ = [("rec", P), ("depth", P), ("rect", P), ("tiles", P), ("block_off", P), ("rows", P),
                 ("enhanced", C.c_int32), ("_pad", C.c_int32)]
 
 
@@ -91,6 +91,7 @@ SIGNATURES = {
     "sgs_geom_rec_floats": (C.c_int64, [C.c_int64, C.c_int32]),
     "sgs_geom_block_entries": (C.c_int64, [C.c_int64, C.c_int32]),
     "sgs_bin_sort_scratch_bytes": (C.c_size_t, [C.c_int64, C.c_int64, C.c_int64, C.POINTER(Options)]),
+    "sgs_bin_sort_mode": (C.c_int32, [C.POINTER(Options), C.c_int64, P, C.c_int32, C.c_int32]),
     "sgs_preprocess": (C.c_int, [C.POINTER(Params), C.POINTER(Camera), P, C.c_int32,
                                  C.POINTER(Options), C.POINTER(Geom), P]),
     "sgs_bin_sort": (C.c_int, [C.POINTER(Geom), C.c_int64, C.POINTER(Camera), P, C.c_int32,

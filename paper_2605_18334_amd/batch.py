@@ -31,7 +31,7 @@ class LaunchConfig:
     tile_w: int = 16
     tile_h: int = 16
     blend_batch: int = 256
-    sort_mode: int = 1
+    sort_mode: int = -1            # -1: the library's choice by capacity; 1 tile keys; 2 row binning
     tile_order: bool = True
     persistent: bool = False
     views_per_launch: int = 16
@@ -130,6 +130,11 @@ DEFAULT_CANDIDATES = [
     LaunchConfig(16, 16, 0, 1, True, False, 4, 10),
     LaunchConfig(16, 16, 0, 1, True, False, 16, 8),
     LaunchConfig(16, 16, 0, 1, True, False, 16, 10),
+    # the sort: row binning (mode 2) against the tile-key sort above
+    LaunchConfig(16, 16, 256, 2, True, False, 4),
+    LaunchConfig(16, 16, 0, 2, True, False, 4),
+    LaunchConfig(16, 16, 0, 2, True, False, 16),
+    LaunchConfig(16, 8, 128, 2, True, False, 4),
 ]
 
 

@@ -57,6 +57,10 @@ constexpr int EC = 64;             // expansion blocks per chunk of the count sc
 // ran 5% slower at 52M keys, 1024 slower still)
 constexpr uint64_t RS_WIDE_MAX_BLOCKS = 4096;
 constexpr int RS_MAX_PASSES = 8;
+// pass grids: workgroups resident at once on 256 CUs (1024 threads: 2 per
+// CU; 512 threads: 3 per CU, by LDS)
+constexpr uint64_t RS_GRID_1024 = 512;
+constexpr uint64_t RS_GRID_512 = 768;
 constexpr uint64_t ST_AGG = 1ull << 32;    // status: block's own digit count
 constexpr uint64_t ST_INC = 2ull << 32;    // status: inclusive prefix over blocks
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
@@ -262,13 +266,17 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
   __shared__ K skey[RS_TILE];
   __shared__ uint32_t sval[RS_TILE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const uint32_t n = count_of(n_dev, n_host, cap);
+  // the workgroups take block ids in order until the data ends (a grid
+  // smaller than the block count loops; every id waited on is held by a
+  // running workgroup)
+  for (;;) {
   if (t == 0) s_bid = atomicAdd(counter, 1u);
   for (int k = t; k < NW * DB; k += NT) (&wc[0][0])[k] = 0;
   __syncthreads();
   const uint32_t b = s_bid;
-  const uint32_t n = count_of(n_dev, n_host, cap);
   const uint64_t bbase = (uint64_t)b * RS_TILE;
-  if (bbase >= n) return;   // ids past the data: no later block waits on them
+  if (bbase >= n) break;   // ids past the data: no later block waits on them
   const uint32_t mask = (1u << nbits) - 1u;
   const uint64_t base = bbase + (uint64_t)w * (IPT * 64) + lane;
   const uint64_t lt = lanemask_lt();
@@ -424,6 +432,11 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
       }
     }
   }
+  // a grid that covers every data block in its first round of ids takes no
+  // second id (that would cost one more atomic round trip)
+  if ((uint64_t)gridDim.x * RS_TILE >= n) break;
+  __syncthreads();   // (LDS reused by the next block id)
+  }
 }
 
 // ------------------------------------------------------------- duplicate
@@ -433,6 +446,7 @@ struct DupArgs {
   int32_t tile_w, tile_h;
   const uint32_t* rect;
   const uint32_t* tiles;
+  const uint32_t* rows;  // mode 2: non-empty tile rows per record
   const float* depth;
   const uint32_t* block_off;
   const sgs_camera* cams;
@@ -495,23 +509,28 @@ __global__ void __launch_bounds__(256) k_duplicate64(DupArgs a) {
 }
 
 
-// Mode 1, step 2: exclusive instance offset of every record in depth order,
-// one pass: each block of SO_TILE entries scans its tile counts, publishes
-// its total and looks back over the published totals of the blocks before
-// it, 64 at a time (one per lane of wave 0).  The block that takes the last
-// id writes the instance count (N_INVALID after a failed look-back, here or
-// in the depth sort; saturated at 2^32 - 2).  Each record also marks the
-// expansion blocks whose first instance it owns: bstart[b] = its position.
+// Modes 1 and 2, step 2: exclusive offset of every record in depth order of
+// its count (mode 1: tiles, the instance offsets; mode 2: non-empty tile
+// rows, the row-item offsets), one pass: each block of SO_TILE entries scans
+// its counts, publishes its total and looks back over the published totals
+// of the blocks before it, 64 at a time (one per lane of wave 0).  The block
+// that takes the last id writes the total to *n_out (N_INVALID after a failed
+// look-back, here or in the depth sort; saturated at 2^32 - 2); with
+// inst_total (mode 2) it also writes *n_inst = *inst_total (the preprocess's
+// instance count) under the same rule.  Each record also marks the expansion
+// blocks whose first entry it owns: bstart[b] = its position.
 constexpr int SO_IPT = 8;
 constexpr int SO_TILE = 256 * SO_IPT;
 
 __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restrict__ order,
                                                         const uint32_t* __restrict__ tiles,
                                                         int64_t m, uint32_t* __restrict__ offs,
-                                                        uint32_t* __restrict__ n_inst,
+                                                        uint32_t* __restrict__ n_out,
                                                         uint64_t* status, uint32_t* counter,
                                                         uint32_t* err, uint32_t* __restrict__ bstart,
-                                                        uint32_t n_bstart, int ex_shift) {
+                                                        uint32_t n_bstart, int ex_shift,
+                                                        const uint32_t* __restrict__ inst_total,
+                                                        uint32_t* __restrict__ n_inst) {
   constexpr uint64_t VMASK = (1ull << 62) - 1;   // 62-bit running totals, 2 flag bits
   constexpr uint64_t F_AGG = 1ull << 62, F_INC = 2ull << 62;
   __shared__ uint32_t ws[4];
@@ -564,7 +583,8 @@ __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restri
           if (++spins > SPIN_LIMIT) {
             if (lane == 0) {
               atomicOr(err, 1u);
-              atomicExch(n_inst, N_INVALID);
+              atomicExch(n_out, N_INVALID);
+              if (inst_total) atomicExch(n_inst, N_INVALID);
             }
             break;
           }
@@ -592,7 +612,9 @@ __global__ void __launch_bounds__(256) k_sorted_offsets(const uint32_t* __restri
   }
   if (b == gridDim.x - 1 && t == 0) {
     const uint64_t total = s_excl + tot;
-    atomicMax(n_inst, *err ? N_INVALID : (total < N_INVALID ? (uint32_t)total : N_INVALID - 1u));
+    const bool bad = *err != 0u;
+    atomicMax(n_out, bad ? N_INVALID : (total < N_INVALID ? (uint32_t)total : N_INVALID - 1u));
+    if (inst_total) atomicMax(n_inst, bad ? N_INVALID : min(*inst_total, N_INVALID - 1u));
   }
 }
 
@@ -883,6 +905,600 @@ __global__ void __launch_bounds__(1024) k_order_tiles(uint32_t* __restrict__ ran
   }
 }
 
+// ------------------------------------------------------ row binning (mode 2)
+// Sort mode 2 moves row items instead of instances.  Each non-empty tile row
+// of a record's rect becomes one item (global tile row, first column,
+// width; record), emitted in the records' depth order; a stable radix sort
+// by the row (one or two passes over at most 10 bits) groups the items by
+// row with depth order kept inside a row; then each row's items, in pieces,
+// place their record into the row's tiles.  Per tile the record list is the
+// one the tile-key sort of mode 1 produces (depth order, record index among
+// equal depths), in the same global positions.  At 1M Gaussians a record
+// covers about 6.6 tiles per row, so about 7 times fewer entries are sorted.
+//
+// Item key: row | first column << 16 | (width - 1) << 24 (tiles_x <= 256 per
+// view, at most 1024 rows per launch, at most 64 views: the host falls back
+// to mode 1 otherwise).  Global rows number the views' tile rows view by
+// view, so row order is tile order.
+constexpr int RB_MAX_VIEWS = 64;
+constexpr int RB_MAX_ROWS = 1024;
+constexpr int RB_MAX_GRID = 2048;  // grid-stride blocks of the piece kernels
+constexpr int RB_STG = 2048;       // staged placements per group of 256 items
+
+__device__ __forceinline__ uint32_t item_row(uint32_t k) { return k & 0xffffu; }
+__device__ __forceinline__ uint32_t item_x0(uint32_t k) { return (k >> 16) & 0xffu; }
+__device__ __forceinline__ uint32_t item_w(uint32_t k) { return (k >> 24) + 1u; }
+
+// Items per piece: 2^nb_shift, from the capacity (the per-piece column
+// counts are sized by it: at most about 2048 pieces per 2^22 capacity,
+// plus one partial piece per row).
+static inline int nb_shift_for(uint64_t cap) {
+  int sh = 8;
+  while (sh < 11 && (cap >> sh) > 2048) ++sh;
+  return sh;
+}
+
+// Mode 2, step 3: row items.  Same traversal as k_expand32 (block b owns
+// items [b*EXT, (b+1)*EXT) of the depth-ordered item list, records in chunks
+// of 256 with their spans in LDS, (record, rect row) pairs enumerated 256 at
+// a time), but a pair becomes one item when its row has tiles, at the
+// record's item offset plus the number of non-empty rows before it.  Counts
+// the row digits for the row sort (per block for the first pass) and the
+// items of each row (row_cnt, R rows).
+template <int EXT>
+__global__ void __launch_bounds__(256) k_emit_rows(DupArgs a, const uint32_t* __restrict__ n_items_p,
+                                                   uint32_t* __restrict__ row_cnt, int n_rows, int n_views,
+                                                   uint32_t n_eblocks) {
+  constexpr int NSP = 13;
+  __shared__ float s_sp[NSP][256];
+  __shared__ uint32_t s_r0[256], s_r1[256];
+  __shared__ uint32_t s_rec[256];
+  __shared__ uint32_t s_grow[256];        // global row of the record's first rect row
+  __shared__ uint32_t s_rows[257];
+  __shared__ uint32_t s_mark[256];
+  __shared__ uint32_t s_wmax[4];
+  __shared__ uint32_t s_vrb[RB_MAX_VIEWS];   // first global row of each view
+  __shared__ uint32_t hist[2][256];
+  __shared__ uint32_t s_rc[RB_MAX_ROWS];     // items per row
+  __shared__ uint32_t ws[4];
+  __shared__ uint32_t s_tot, s_j0, s_w;
+  const int t = threadIdx.x;
+  const uint32_t total = *n_items_p;
+  const uint32_t n = total < a.cap ? total : a.cap;
+  const uint32_t dmask = (1u << a.hwidth) - 1u;
+  for (int k = t; k < n_rows; k += 256) s_rc[k] = 0u;
+  for (int k = t; k < 2 * 256; k += 256) (&hist[0][0])[k] = 0u;
+  if (t < 64) {
+    const uint32_t ty = t < n_views ? (uint32_t)a.cams[t].tiles_y : 0u;
+    s_vrb[t] = wave_incl_scan(ty) - ty;
+  }
+  // emission blocks eb = blockIdx.x, + gridDim.x, ...
+  for (uint32_t eb = blockIdx.x; eb < n_eblocks; eb += gridDim.x) {
+  const uint64_t o0 = (uint64_t)eb * EXT;
+  if (o0 >= n) {   // no items: zero counts for the first pass's column scan
+    if (a.cnt0) a.cnt0[(uint64_t)eb * 256 + t] = 0u;
+    continue;
+  }
+  const uint64_t o1 = min(o0 + (uint64_t)EXT, (uint64_t)n);
+  if (t == 0) {
+    const uint64_t jlo = min((uint64_t)a.bstart[eb], (uint64_t)a.m - 1);
+    s_j0 = (uint32_t)jlo;
+    s_w = (uint32_t)min((uint64_t)EXT + 1, (uint64_t)a.m - jlo);
+  }
+  __syncthreads();
+  const uint32_t j0 = s_j0, W = s_w;
+  uint64_t run = a.offs[j0];    // item offset of the next (record, row) pair with tiles
+  for (uint32_t c = 0; c < W && run < o1; c += 256) {
+    const uint32_t k = c + t;
+    uint32_t rows = 0;
+    if (k < W) {
+      const uint64_t j = (uint64_t)j0 + k;
+      const uint32_t rec = a.order[j];
+      s_rec[t] = rec;
+      const uint32_t off = a.offs[j];
+      bool has = false;
+      if ((k == 0 || off < o1) && rec < (uint64_t)a.m)
+        has = j + 1 < (uint64_t)a.m ? a.offs[j + 1] > off : a.rows[rec] > 0;
+      if (has) {
+        const float4* rp = a.rec + 4 * (uint64_t)rec;
+        const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2];
+        uint2 r;
+        if (a.enhanced) {
+          r = reinterpret_cast<const uint2*>(a.rect)[rec];
+        } else {
+          const float4 q3 = rp[3];
+          r = make_uint2(__float_as_uint(q3.x), __float_as_uint(q3.y));
+        }
+        rows = (r.y >> 16) - min(r.x >> 16, r.y >> 16);
+        s_r0[t] = r.x;
+        s_r1[t] = r.y;
+        Span sp;
+        span_setup(q0.x, q0.y, q0.z, q0.w, q1.x, q2.w, q1.y, q1.z, record_zcut(a, q1), sp);
+        s_sp[0][t] = sp.mx;  s_sp[1][t] = sp.my;  s_sp[2][t] = sp.b;   s_sp[3][t] = sp.det;
+        s_sp[4][t] = sp.ia;  s_sp[5][t] = sp.aR2; s_sp[6][t] = sp.ey;  s_sp[7][t] = sp.ex;
+        s_sp[8][t] = sp.yx;  s_sp[9][t] = sp.bx;  s_sp[10][t] = sp.by; s_sp[11][t] = sp.need;
+        s_sp[12][t] = __uint_as_float((sp.ok ? 1u : 0u) | (sp.cut ? 2u : 0u));
+        const uint32_t v = rec / (uint32_t)a.n;
+        s_grow[t] = (v < RB_MAX_VIEWS ? s_vrb[v] : 0u) + (r.x >> 16);
+      }
+    }
+    const uint32_t e = block_scan256_total(rows, ws, &s_tot);
+    s_rows[t] = e;
+    if (t == 255) s_rows[256] = e + rows;
+    __syncthreads();
+    const uint32_t R = s_rows[256];
+    for (uint32_t base = 0; base < R && run < o1; base += 256) {
+      const uint32_t i = base + t;
+      s_mark[t] = 0u;
+      __syncthreads();
+      if (rows > 0 && e < base + 256 && e + rows > base) s_mark[(e > base ? e : base) - base] = (uint32_t)t + 1u;
+      __syncthreads();
+      const uint32_t wm = wave_incl_max(s_mark[t]);
+      if ((t & 63) == 63) s_wmax[t >> 6] = wm;
+      __syncthreads();
+      uint32_t own = wm;
+      for (int q = 0; q < (t >> 6); ++q) own = max(own, s_wmax[q]);
+      uint32_t ne = 0, item = 0, rec = 0;
+      if (i < R) {
+        const uint32_t lo = own - 1u;
+        rec = s_rec[lo];
+        Span sp;
+        sp.mx = s_sp[0][lo];  sp.my = s_sp[1][lo];  sp.b = s_sp[2][lo];   sp.det = s_sp[3][lo];
+        sp.ia = s_sp[4][lo];  sp.aR2 = s_sp[5][lo]; sp.ey = s_sp[6][lo];  sp.ex = s_sp[7][lo];
+        sp.yx = s_sp[8][lo];  sp.bx = s_sp[9][lo];  sp.by = s_sp[10][lo]; sp.need = s_sp[11][lo];
+        const uint32_t fl = __float_as_uint(s_sp[12][lo]);
+        sp.ok = (fl & 1u) != 0u;
+        sp.cut = (fl & 2u) != 0u;
+        const uint32_t r0 = s_r0[lo];
+        const int x0 = r0 & 0xffffu, x1 = s_r1[lo] & 0xffffu;
+        const uint32_t dy = i - s_rows[lo];
+        int c0, c1;
+        span_row(sp, (int)(r0 >> 16) + (int)dy, a.tile_w, a.tile_h, x0, x1, c0, c1);
+        if (c1 > c0) {
+          ne = 1;
+          item = ((s_grow[lo] + dy) & 0xffffu) | ((uint32_t)c0 << 16) | ((uint32_t)(c1 - c0 - 1) << 24);
+        }
+      }
+      const uint32_t e2 = block_scan256_total(ne, ws, &s_tot);
+      const uint64_t pos = run + e2;
+      if (ne && pos >= o0 && pos < o1) {
+        a.keys32[pos] = item;
+        a.vals[pos] = rec;
+        const uint32_t row = item_row(item);
+        atomicAdd(&hist[0][row & dmask], 1u);
+        if (a.hpasses > 1) atomicAdd(&hist[1][(row >> a.hwidth) & dmask], 1u);
+        if (row < (uint32_t)n_rows) atomicAdd(&s_rc[row], 1u);
+      }
+      run += s_tot;
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (a.cnt0) a.cnt0[(uint64_t)eb * 256 + t] = hist[0][t];
+  uint32_t* hdst = a.hpart + (size_t)(eb % (unsigned)a.hcopies) * a.hpasses * 256;
+  for (int p = 0; p < a.hpasses; ++p) {
+    if (hist[p][t]) atomicAdd(&hdst[p * 256 + t], hist[p][t]);
+    hist[p][t] = 0u;
+  }
+  __syncthreads();
+  }
+  __syncthreads();
+  for (int k = t; k < n_rows; k += 256)
+    if (s_rc[k]) atomicAdd(&row_cnt[k], s_rc[k]);
+}
+
+// The views' first global rows, tiles per row and first tiles, in LDS
+// (wave 0 of the block loads them; n_views <= RB_MAX_VIEWS); the caller
+// synchronises before use.
+struct ViewTable {
+  uint32_t rb[RB_MAX_VIEWS + 1], tx[RB_MAX_VIEWS], tb[RB_MAX_VIEWS];
+};
+
+__device__ __forceinline__ void load_views(const sgs_camera* cams, int n_views, ViewTable& vt) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const bool on = t < n_views;
+    const uint32_t ty = on ? (uint32_t)cams[t].tiles_y : 0u;
+    const uint32_t inc = wave_incl_scan(ty);
+    vt.rb[t] = inc - ty;
+    vt.tx[t] = on ? (uint32_t)cams[t].tiles_x : 0u;
+    vt.tb[t] = on ? (uint32_t)cams[t].tile_base : 0u;
+    if (t == 63) vt.rb[RB_MAX_VIEWS] = inc;
+  }
+}
+
+// First tile of a global tile row and its view's tiles_x.
+__device__ __forceinline__ void row_view(const ViewTable& vt, int n_views, uint32_t row, uint32_t& tile0,
+                                         uint32_t& tx) {
+  int lo = 0, hi = n_views;   // rb[lo] <= row < rb[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (vt.rb[mid] <= row) lo = mid; else hi = mid;
+  }
+  tx = vt.tx[lo];
+  tile0 = vt.tb[lo] + (row - vt.rb[lo]) * tx;
+}
+
+// Pieces: each row's sorted items in runs of at most 2^nb_shift (rows
+// without items have none).  ptab = [pp[0..R], rs[0..R]]: pp[r] the first
+// piece of row r, rs[r] its first item (exclusive scans of the per-row
+// piece and item counts); pp[R] pieces in all.  Built in LDS by every block
+// of the counting kernel from the per-row item counts (R <= RB_MAX_ROWS).
+
+__device__ __forceinline__ void piece_table(const uint32_t* __restrict__ row_cnt, int R, int nb_shift,
+                                            uint32_t* pp, uint32_t* rs, uint32_t* ws4) {
+  const int t = threadIdx.x;
+  uint32_t ci[4], cp[4], si = 0, sp = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = t * 4 + k;
+    ci[k] = r < R ? row_cnt[r] : 0u;
+    cp[k] = (ci[k] + (1u << nb_shift) - 1) >> nb_shift;
+    si += ci[k];
+    sp += cp[k];
+  }
+  uint32_t ei = block_excl_scan256(si, ws4);
+  uint32_t ep = block_excl_scan256(sp, ws4);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = t * 4 + k;
+    if (r <= R) {
+      pp[r] = ep;
+      rs[r] = ei;
+    }
+    ep += cp[k];
+    ei += ci[k];
+  }
+  if (t == 255 && R == RB_MAX_ROWS) {
+    pp[R] = ep;
+    rs[R] = ei;
+  }
+}
+
+// Largest r <= R - 1 with pp[r] <= p (rows without pieces are skipped).
+__device__ __forceinline__ uint32_t piece_row(const uint32_t* pp, int R, uint32_t p) {
+  uint32_t lo = 0, hi = (uint32_t)R;   // pp[lo] <= p < pp[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (pp[mid] <= p) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Mode 2, step 5: per piece, the count of its items covering each of the
+// 256 columns (LDS difference array over the columns, then a block scan);
+// block 0 also stores the piece table for the next steps.
+__global__ void __launch_bounds__(256) k_piece_count(const uint32_t* __restrict__ ik,
+                                                     const uint32_t* __restrict__ row_cnt, int R, int nb_shift,
+                                                     uint32_t* __restrict__ cntp, uint32_t* __restrict__ ptab) {
+  __shared__ uint32_t pp[RB_MAX_ROWS + 1], rs[RB_MAX_ROWS + 1];
+  __shared__ uint32_t D[257];
+  __shared__ uint32_t ws[4];
+  const int t = threadIdx.x;
+  piece_table(row_cnt, R, nb_shift, pp, rs, ws);
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int r = t; r <= R; r += 256) {
+      ptab[r] = pp[r];
+      ptab[R + 1 + r] = rs[r];
+    }
+  const uint32_t P = pp[R];
+  for (uint32_t p = blockIdx.x; p < P; p += gridDim.x) {
+    const uint32_t r = piece_row(pp, R, p);
+    const uint32_t s = rs[r] + ((p - pp[r]) << nb_shift);
+    const uint32_t e = min(s + (1u << nb_shift), rs[r + 1]);
+    D[t] = 0u;
+    if (t == 0) D[256] = 0u;
+    __syncthreads();
+    for (uint32_t i = s + t; i < e; i += 256) {
+      const uint32_t key = ik[i];
+      const uint32_t x0 = item_x0(key), x1 = x0 + item_w(key);
+      atomicAdd(&D[x0], 1u);
+      atomicAdd(&D[min(x1, 256u)], 0xffffffffu);   // (-1; column 256 is never read)
+    }
+    __syncthreads();
+    const uint32_t d = D[t];
+    cntp[(uint64_t)p * 256 + t] = block_excl_scan256(d, ws) + d;
+  }
+}
+
+// Mode 2, step 6: per (row, column), the counts of the row's pieces before
+// each piece (pre_col) and the row's total (the tile's instance count).
+// One block per row, one thread per column.
+__global__ void __launch_bounds__(256) k_col_scan(const uint32_t* __restrict__ cntp,
+                                                  const uint32_t* __restrict__ ptab, int R,
+                                                  const sgs_camera* cams, int n_views,
+                                                  uint32_t* __restrict__ pre_col, uint32_t* __restrict__ cnt_tile,
+                                                  uint32_t n_tiles) {
+  __shared__ ViewTable vt;
+  load_views(cams, n_views, vt);
+  const uint32_t r = blockIdx.x;
+  const uint32_t c = threadIdx.x;
+  const uint32_t p0 = ptab[r], p1 = ptab[r + 1];
+  uint32_t run = 0;
+  uint32_t p = p0;
+  for (; p + 8 <= p1; p += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = cntp[(uint64_t)(p + k) * 256 + c];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      pre_col[(uint64_t)(p + k) * 256 + c] = run;
+      run += v[k];
+    }
+  }
+  for (; p < p1; ++p) {
+    pre_col[(uint64_t)p * 256 + c] = run;
+    run += cntp[(uint64_t)p * 256 + c];
+  }
+  __syncthreads();
+  uint32_t t0, tx;
+  row_view(vt, n_views, r, t0, tx);
+  if (c < tx && (uint64_t)t0 + c < n_tiles) cnt_tile[t0 + c] = run;
+}
+
+// Mode 2, step 8: placement, one block per piece (grid-stride), its items
+// in groups of 256 (one per thread, in order).  Within a group, wave w
+// marks in LDS, per column, the lanes whose item starts there and those
+// whose item ends there; OR prefixes over the columns turn them into the
+// lanes covering each column, so an instance (item, column) ranks among the
+// group's items by popcount (lanes below it in its wave, plus the earlier
+// waves' counts).  Its position: the tile's start + the row's count before
+// this piece + the earlier groups' count + that rank.  The group's
+// placements are staged column by column in LDS and written out in that
+// order (runs of consecutive positions); a group with more than RB_STG
+// placements (or with keys requested) writes them directly.
+__global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ ik, const uint32_t* __restrict__ iv,
+                                                   const uint32_t* __restrict__ ptab, int R, int nb_shift,
+                                                   const sgs_camera* cams, int n_views,
+                                                   const uint32_t* __restrict__ pre_col,
+                                                   const uint32_t* __restrict__ ranges, uint32_t n_tiles,
+                                                   uint32_t cap, uint32_t* __restrict__ vals,
+                                                   uint64_t* __restrict__ keys, const float* __restrict__ depth,
+                                                   uint64_t m) {
+  __shared__ uint64_t S[4][256];              // per wave: lanes whose item starts at / covers each column
+  __shared__ union {
+    uint64_t e[4][256];                       // per wave: lanes whose item ends at each column
+    uint2 b[4][256];                          // then per wave and column: (staging base, global base)
+  } EB;
+  __shared__ union {
+    uint2 st[RB_STG];                         // staged placements (record, global position)
+    uint32_t cnt[4][256];                     // per wave: covering lanes per column (before staging)
+  } SG;
+  __shared__ uint32_t gb[256];                // next global position of each column in this piece
+  __shared__ uint32_t ws[4];
+  __shared__ uint32_t s_info[4];
+  __shared__ uint32_t s_tot;
+  __shared__ uint32_t pt[2 * (RB_MAX_ROWS + 1)];   // the piece table
+  __shared__ ViewTable vt;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const uint32_t P = ptab[R];
+  for (int k = t; k < 2 * (R + 1); k += 256) pt[k] = ptab[k];
+  load_views(cams, n_views, vt);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    S[wv][4 * lane + q] = 0ull;
+    EB.e[wv][4 * lane + q] = 0ull;
+  }
+  __syncthreads();
+  const uint64_t lt = lanemask_lt();
+  // pieces in 8 contiguous chunks, one per XCD (workgroup i runs on XCD
+  // i mod 8): neighbouring pieces, whose runs of a column abut in the
+  // output, share an L2 and complete each other's lines there
+  const uint32_t xcd = blockIdx.x & 7u, nx = gridDim.x >> 3;
+  const uint32_t chunk = (P + 7) >> 3;
+  const uint32_t pend = min((xcd + 1) * chunk, P);
+  for (uint32_t p = xcd * chunk + (blockIdx.x >> 3); p < pend; p += nx) {
+    if (t == 0) {
+      const uint32_t r = piece_row(pt, R, p);
+      const uint32_t s = pt[R + 1 + r] + ((p - pt[r]) << nb_shift);
+      uint32_t t0, tx;
+      row_view(vt, n_views, r, t0, tx);
+      s_info[0] = s;
+      s_info[1] = min(s + (1u << nb_shift), pt[R + 1 + r + 1]);
+      s_info[2] = t0;
+      s_info[3] = tx;
+    }
+    __syncthreads();
+    const uint32_t s = s_info[0], e = s_info[1], t0 = s_info[2], tx = s_info[3];
+    {
+      const bool ok = (uint32_t)t < tx && (uint64_t)t0 + t < n_tiles;
+      gb[t] = (ok ? ranges[2 * (uint64_t)(t0 + t)] : 0u) + pre_col[(uint64_t)p * 256 + t];
+    }
+    uint32_t nkey = s + t < e ? ik[s + t] : 0u;
+    uint32_t nval = s + t < e ? iv[s + t] : 0u;
+    for (uint32_t g0 = s; g0 < e; g0 += 256) {
+      const uint32_t i = g0 + t;
+      const bool valid = i < e;
+      const uint32_t key = nkey, val = nval;
+      {
+        // the next group's items, in flight during this group
+        const uint32_t i2 = i + 256;
+        nkey = i2 < e ? ik[i2] : 0u;
+        nval = i2 < e ? iv[i2] : 0u;
+      }
+      const uint32_t x0 = item_x0(key), w = valid ? item_w(key) : 0u;
+      // (this wave's S and E rows are zero here)
+      if (valid) {
+        atomicOr(reinterpret_cast<unsigned long long*>(&S[wv][x0]), 1ull << lane);
+        if (x0 + w < 256u) atomicOr(reinterpret_cast<unsigned long long*>(&EB.e[wv][x0 + w]), 1ull << lane);
+      }
+      __builtin_amdgcn_wave_barrier();
+      {
+        // inclusive OR prefixes over the columns (lane l: columns 4l..4l+3),
+        // then cover = started & ~ended
+        uint64_t a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a[q] = S[wv][4 * lane + q];
+          b[q] = EB.e[wv][4 * lane + q];
+          if (q > 0) {
+            a[q] |= a[q - 1];
+            b[q] |= b[q - 1];
+          }
+        }
+        uint64_t xa = a[3], xb = b[3];
+        for (int off = 1; off < 64; off <<= 1) {
+          const uint64_t ya = __shfl_up(xa, off), yb = __shfl_up(xb, off);
+          if (lane >= off) {
+            xa |= ya;
+            xb |= yb;
+          }
+        }
+        uint64_t pa = __shfl_up(xa, 1), pb = __shfl_up(xb, 1);
+        if (lane == 0) pa = pb = 0ull;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint64_t cov = (a[q] | pa) & ~(b[q] | pb);
+          S[wv][4 * lane + q] = cov;
+          SG.cnt[wv][4 * lane + q] = (uint32_t)__popcll(cov);
+        }
+      }
+      __syncthreads();
+      uint32_t c0, c1, c2, gc;
+      {
+        c0 = SG.cnt[0][t];
+        c1 = SG.cnt[1][t];
+        c2 = SG.cnt[2][t];
+        gc = c0 + c1 + c2 + SG.cnt[3][t];
+      }
+      const uint32_t gs = block_scan256_total(gc, ws, &s_tot);   // (synchronises)
+      {
+        const uint32_t g = gb[t];
+        EB.b[0][t] = make_uint2(gs, g);
+        EB.b[1][t] = make_uint2(gs + c0, g + c0);
+        EB.b[2][t] = make_uint2(gs + c0 + c1, g + c0 + c1);
+        EB.b[3][t] = make_uint2(gs + c0 + c1 + c2, g + c0 + c1 + c2);
+        gb[t] = g + gc;
+      }
+      __syncthreads();
+      const uint32_t T = s_tot;
+      const bool stage = T <= (uint32_t)RB_STG && !keys;
+      // (four columns per step: their LDS reads are in flight together)
+      for (uint32_t kk = 0; kk < w; kk += 4) {
+        uint2 bs[4];
+        uint64_t cv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t c = min(x0 + kk + u, 255u);
+          bs[u] = EB.b[wv][c];
+          cv[u] = S[wv][c];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (kk + u < w) {
+            const uint32_t rank = (uint32_t)__popcll(cv[u] & lt);
+            if (stage) {
+              SG.st[bs[u].x + rank] = make_uint2(val, bs[u].y + rank);
+            } else if (bs[u].y + rank < cap) {
+              vals[bs[u].y + rank] = val;
+              if (keys)
+                keys[bs[u].y + rank] = ((uint64_t)(t0 + x0 + kk + u) << 32) |
+                                       (val < m ? (uint64_t)__float_as_uint(depth[val]) : 0ull);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (stage) {
+        uint32_t q = t;
+        for (; q + 768 < T; q += 1024) {
+          uint2 v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = SG.st[q + 256 * u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (v[u].y < cap) vals[v[u].y] = v[u].x;
+        }
+        for (; q < T; q += 256) {
+          const uint2 v = SG.st[q];
+          if (v.y < cap) vals[v.y] = v.x;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        S[wv][4 * lane + q] = 0ull;
+        EB.e[wv][4 * lane + q] = 0ull;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Mode 2, step 7: tile ranges from the tile counts (one workgroup): an
+// exclusive scan, [start, end) clamped to the capacity, [0, 0) for empty
+// tiles; with order, the tile order by decreasing count (as k_order_tiles).
+__global__ void __launch_bounds__(1024) k_tile_scan(const uint32_t* __restrict__ cnt_tile, uint32_t T, uint32_t cap,
+                                                    uint32_t* __restrict__ ranges, uint32_t* __restrict__ order) {
+  __shared__ uint64_t wsum[16];
+  __shared__ uint64_t carry_s;
+  __shared__ uint32_t bcnt[OT_BUCKETS], bpos[OT_BUCKETS];
+  __shared__ uint32_t s_w0;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t == 0) carry_s = 0;
+  if (t < OT_BUCKETS) bcnt[t] = 0;
+  __syncthreads();
+  for (uint64_t base = 0; base < T; base += 4096) {
+    uint32_t c[4];
+    uint64_t v[4], loc = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t idx = base + (uint64_t)t * 4 + k;
+      c[k] = idx < T ? cnt_tile[idx] : 0u;
+      v[k] = loc;
+      loc += c[k];
+    }
+    uint64_t inc = loc;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint64_t y = __shfl_up(inc, off);
+      if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+      const uint64_t s0 = lane < 16 ? wsum[lane] : 0ull;
+      uint64_t wi = s0;
+      for (int off = 1; off < 16; off <<= 1) {
+        const uint64_t y = __shfl_up(wi, off);
+        if (lane >= off) wi += y;
+      }
+      if (lane < 16) wsum[lane] = wi - s0;
+    }
+    __syncthreads();
+    const uint64_t pre = carry_s + wsum[w] + inc - loc;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t idx = base + (uint64_t)t * 4 + k;
+      if (idx < T) {
+        const uint64_t st = pre + v[k];
+        const uint32_t a0 = c[k] ? (uint32_t)min(st, (uint64_t)cap) : 0u;
+        const uint32_t a1 = c[k] ? (uint32_t)min(st + c[k], (uint64_t)cap) : 0u;
+        ranges[2 * idx] = a0;
+        ranges[2 * idx + 1] = a1;
+        if (order) atomicAdd(&bcnt[len_bucket(c[k])], 1u);
+      }
+    }
+    __syncthreads();
+    if (t == 1023) carry_s = pre + loc;
+    __syncthreads();
+  }
+  if (!order) return;
+  static_assert(OT_BUCKETS == 128, "two full waves scan the buckets");
+  uint32_t cb = 0, incb = 0;
+  if (t < OT_BUCKETS) {
+    cb = bcnt[OT_BUCKETS - 1 - t];
+    incb = wave_incl_scan(cb);
+    if (t == 63) s_w0 = incb;
+  }
+  __syncthreads();
+  if (t < OT_BUCKETS) bpos[OT_BUCKETS - 1 - t] = incb - cb + (t >= 64 ? s_w0 : 0u);
+  __syncthreads();
+  for (uint32_t i = t; i < T; i += 1024) {
+    const uint32_t p = atomicAdd(&bpos[len_bucket(cnt_tile[i])], 1u);
+    if (p < T) order[p] = i;
+  }
+}
+
 // ------------------------------------------------------------------ host side
 static inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -975,14 +1591,16 @@ static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32
     const int dst = (passes - 1 - p) & 1;
     const K* ki = p == 0 ? kin : kb[dst ^ 1];
     const uint32_t* vi = p == 0 ? vin : vb[dst ^ 1];
+    // (grids of at most the workgroups that fit at once: they loop over
+    // the block ids, so a capacity far above the count costs no launches)
     if (blocks <= RS_WIDE_MAX_BLOCKS)
-      k_os_pass<K, 1024, LB_W, DB><<<(unsigned)blocks, 1024, 0, s>>>(
+      k_os_pass<K, 1024, LB_W, DB><<<(unsigned)std::min<uint64_t>(blocks, RS_GRID_1024), 1024, 0, s>>>(
         ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * DB,
         sc.status + (size_t)p * blocks * DB, sc.counters + p, sc.err, sc.n_fold,
         p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot,
         p == 0 ? xf : none);
     else if constexpr (DB == 256)
-      k_os_pass<K, 512, LB_W><<<(unsigned)blocks, 512, 0, s>>>(
+      k_os_pass<K, 512, LB_W><<<(unsigned)std::min<uint64_t>(blocks, RS_GRID_512), 512, 0, s>>>(
         ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
         sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
         p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot,
@@ -1016,7 +1634,11 @@ struct BinLayout {
   uint64_t n_bstart;              //         (= number of expansion blocks)
   uint32_t* cnt0;                 // mode 1: [expansion blocks][256] first-digit counts
   uint32_t* ctot;                 // mode 1: [chunks][256] their chunk totals
-  uint32_t* tk[2];                // mode 1: tile keys
+  uint32_t* tk[2];                // mode 1: tile keys; mode 2: row items
+  uint32_t* cntp;                 // mode 2: per piece, items covering each column [pieces][256]
+  uint32_t* pre_col;              // mode 2: the row's count before each piece [pieces][256]
+  uint32_t* ptab;                 // mode 2: piece table [2][RB_MAX_ROWS + 1]
+  uint32_t* cnt_tile;             // mode 2: instances per tile [T], then items per row [RB_MAX_ROWS]
   size_t bytes;
 };
 
@@ -1027,7 +1649,10 @@ static BinLayout bin_layout(uintptr_t base, int64_t m, int64_t cap, int64_t tota
   auto take = [&](size_t bytes) { uintptr_t r = p; p += align_up(bytes); return r; };
   const uint64_t T = (uint64_t)total_tiles, C = (uint64_t)cap, M = (uint64_t)m;
   const int tb = tile_bits(total_tiles);
+  // (mode 2 sorts row items over at most 16 bits: room for 2 passes, or
+  // for the tile-key passes of mode 1 when it falls back)
   L.main_passes = rs_passes(mode == 0 ? 32 + tb : tb);
+  if (mode == 2) L.main_passes = std::max(L.main_passes, 2);
   L.misc = reinterpret_cast<uint32_t*>(take(64 * 4));
   L.rs_main = reinterpret_cast<uint32_t*>(take(rs_words(C, L.main_passes) * 4));
   if (mode == 0) {
@@ -1051,6 +1676,13 @@ static BinLayout bin_layout(uintptr_t base, int64_t m, int64_t cap, int64_t tota
       L.ctot = reinterpret_cast<uint32_t*>(take(cdiv(L.n_bstart, EC) * 256 * 4));
     }
     L.valt = reinterpret_cast<uint32_t*>(take(C * 4));
+    if (mode == 2) {
+      const uint64_t pieces = cdiv(C, 1ull << nb_shift_for(C)) + RB_MAX_ROWS;
+      L.cntp = reinterpret_cast<uint32_t*>(take(pieces * 256 * 4));
+      L.pre_col = reinterpret_cast<uint32_t*>(take(pieces * 256 * 4));
+      L.ptab = reinterpret_cast<uint32_t*>(take(2 * (RB_MAX_ROWS + 1) * 4));
+      L.cnt_tile = reinterpret_cast<uint32_t*>(take((T + RB_MAX_ROWS) * 4));
+    }
   }
   L.bytes = (size_t)(p - p0) + 256;
   return L;
@@ -1069,14 +1701,87 @@ static bool wide_depth(uint64_t m, float near_min) {
 }
 constexpr int DEPTH_BITS_WIDE = 30;
 
+// Sort mode 2 after the depth presort (see the row binning kernels).
+static sgs_status bin_rows(const sgs_geom* g, DupArgs a, const BinLayout& L, const RsScratch& sc_main,
+                           const uint32_t* order, int64_t m, int32_t n_views, const sgs_camera* cams_dev,
+                           uint64_t T, uint64_t C, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                           uint32_t* n_inst, uint32_t* tile_order, int32_t rb_rows, hipStream_t s) {
+  uint32_t* err = L.misc;
+  uint32_t* n_items = L.misc + 1;   // row items (zeroed with misc)
+  uint32_t* row_cnt = L.cnt_tile + T;
+  const uint64_t mm = (uint64_t)m;
+  const int ex_shift = ex_shift_for(C);
+  const int nb_shift = nb_shift_for(C);
+  const int R = rb_rows;
+  const uint64_t nb_total = (uint64_t)a.nbx * (uint64_t)n_views;
+  k_sorted_offsets<<<(unsigned)cdiv(mm, SO_TILE), 256, 0, s>>>(
+      order, g->rows, m, L.offs, n_items, reinterpret_cast<uint64_t*>(L.so_status + 64), L.so_status, err,
+      L.bstart, (uint32_t)L.n_bstart, ex_shift, g->block_off + nb_total, n_inst);
+  SGS_LAUNCH_CHECK();
+  const int rbits = tile_bits(R);
+  const int rpasses = rs_passes(rbits);
+  uint32_t* ik[2] = {L.tk[0], L.tk[1]};
+  uint32_t* iv[2] = {L.valt, vals};   // sorted items land in (tk[0], valt); vals is free until the placement
+  const int src = rpasses & 1;
+  a.order = order;
+  a.offs = L.offs;
+  a.bstart = L.bstart;
+  a.rows = g->rows;
+  a.keys32 = ik[src];
+  a.vals = iv[src];
+  const uint64_t ex_blocks = cdiv(C, 1ull << ex_shift);
+  a.hcopies = ex_blocks > HC_MIN_BLOCKS ? HC : 1;
+  a.hpart = a.hcopies > 1 ? sc_main.hpart : sc_main.ghist;
+  const bool scan0 = cdiv(C, (uint64_t)RS_T * RS_IPT) > RS_WIDE_MAX_BLOCKS;
+  a.cnt0 = scan0 ? L.cnt0 : nullptr;
+  a.hpasses = rpasses;
+  a.hwidth = rs_width(rbits);
+  const unsigned pgrid = (unsigned)std::min<uint64_t>(cdiv(C, 1ull << nb_shift) + (uint64_t)R, RB_MAX_GRID);
+  if (C > 0) {
+    const unsigned egrid = (unsigned)std::min<uint64_t>(ex_blocks, RB_MAX_GRID);
+    if (ex_shift == 10)
+      k_emit_rows<EX_TILE_S><<<egrid, 256, 0, s>>>(a, n_items, row_cnt, R, n_views, (uint32_t)ex_blocks);
+    else
+      k_emit_rows<EX_TILE><<<egrid, 256, 0, s>>>(a, n_items, row_cnt, R, n_views, (uint32_t)ex_blocks);
+    SGS_LAUNCH_CHECK();
+    if (scan0) {
+      const uint32_t nch = (uint32_t)cdiv(ex_blocks, EC);
+      k_chunk_scan<<<nch, 256, 0, s>>>(L.cnt0, (uint32_t)ex_blocks, L.ctot);
+      SGS_LAUNCH_CHECK();
+      k_chunk_totals<<<256, 256, 0, s>>>(L.ctot, nch);
+      SGS_LAUNCH_CHECK();
+    }
+    const sgs_status st = radix_sort<uint32_t>(ik[src], iv[src], ik, iv, n_items, 0, C, rbits, sc_main, s, true,
+                                               ex_blocks, nullptr, 0, a.cnt0, scan0 ? L.ctot : nullptr);
+    if (st != SGS_OK) return st;
+    k_piece_count<<<pgrid, 256, 0, s>>>(ik[0], row_cnt, R, nb_shift, L.cntp, L.ptab);
+    SGS_LAUNCH_CHECK();
+    k_col_scan<<<(unsigned)R, 256, 0, s>>>(L.cntp, L.ptab, R, cams_dev, n_views, L.pre_col, L.cnt_tile,
+                                           (uint32_t)T);
+    SGS_LAUNCH_CHECK();
+  }
+  k_tile_scan<<<1, 1024, 0, s>>>(L.cnt_tile, (uint32_t)T, (uint32_t)C, ranges, tile_order);
+  SGS_LAUNCH_CHECK();
+  if (C > 0) {
+    const unsigned rgrid = (pgrid + 7u) & ~7u;   // a multiple of 8 (the XCD chunks)
+    k_row_place<<<rgrid, 256, 0, s>>>(ik[0], iv[0], L.ptab, R, nb_shift, cams_dev, n_views, L.pre_col, ranges,
+                                      (uint32_t)T, (uint32_t)C, vals, keys, g->depth, mm);
+    SGS_LAUNCH_CHECK();
+  }
+  return SGS_OK;
+}
+
 sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_camera* cams_dev,
                            int32_t n_views, int64_t total_tiles, const sgs_options* opt,
                            int64_t cap, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                            uint32_t* n_inst, uint32_t* tile_order, void* scratch, float near_min,
-                           hipStream_t s) {
-  const int mode = opt->sort_mode;
-  const bool wide = mode == 1 && opt->depth_digit_bits == 10 && wide_depth((uint64_t)m, near_min);
-  const BinLayout L = bin_layout(reinterpret_cast<uintptr_t>(scratch), m, cap, total_tiles, mode);
+                           int32_t rb_rows, hipStream_t s) {
+  // sort mode 2 runs when the caller found its conditions met (rb_rows > 0:
+  // the global tile rows); otherwise mode 1, in the same (larger) scratch
+  // layout
+  const int mode = opt->sort_mode == 2 && rb_rows == 0 ? 1 : opt->sort_mode;
+  const bool wide = mode >= 1 && opt->depth_digit_bits == 10 && wide_depth((uint64_t)m, near_min);
+  const BinLayout L = bin_layout(reinterpret_cast<uintptr_t>(scratch), m, cap, total_tiles, opt->sort_mode);
   const uint64_t T = (uint64_t)total_tiles, C = (uint64_t)cap;
   uint32_t* err = L.misc;
   // one fill zeroes the ranges, the instance count and every sort's state
@@ -1093,14 +1798,16 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
     z.ev[nz] = ev;
     ++nz;
   };
-  // mode 1 writes ranges from the last sort pass by atomic min / max
-  zero(ranges, 2 * T, mode == 1 ? 0xffffffffu : 0u);
+  // mode 1 writes ranges from the last sort pass by atomic min / max; mode
+  // 2 writes every range from the tile counts
+  if (mode != 2) zero(ranges, 2 * T, mode == 1 ? 0xffffffffu : 0u);
+  if (mode == 2) zero(L.cnt_tile, T + RB_MAX_ROWS);   // tile counts and row item counts
   zero(n_inst, 1);
   zero(L.misc, 64);
   if (C > 0) {
     // large mode-1 sorts: the first pass takes scanned offsets and has no
     // look-back, so its block statuses stay untouched (not cleared)
-    const bool scan0 = mode == 1 && cdiv(C, (uint64_t)RS_T * RS_IPT) > RS_WIDE_MAX_BLOCKS;
+    const bool scan0 = mode >= 1 && cdiv(C, (uint64_t)RS_T * RS_IPT) > RS_WIDE_MAX_BLOCKS;
     const uint64_t words = rs_words(C, L.main_passes);
     const uint64_t head = 64 + (uint64_t)L.main_passes * 256 * (1 + HC);   // counters, histograms
     const uint64_t st0 = rs_blocks(C) * 256 * 2;                             // pass 0's statuses
@@ -1111,7 +1818,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
       zero(L.rs_main, words);
     }
   }
-  if (mode == 1 && m > 0) {
+  if (mode >= 1 && m > 0) {
     zero(L.rs_depth, wide ? rs_words((uint64_t)m, 3, 1024) : rs_words((uint64_t)m, 4));
     zero(L.so_status, L.so_words);
     zero(L.bstart, L.n_bstart);
@@ -1171,7 +1878,12 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
     return order_tiles();
   }
   // mode 1
-  if (m == 0) return order_tiles();
+  if (m == 0) {
+    if (mode != 2) return order_tiles();
+    k_tile_scan<<<1, 1024, 0, s>>>(L.cnt_tile, (uint32_t)T, (uint32_t)C, ranges, tile_order);   // all empty
+    SGS_LAUNCH_CHECK();
+    return SGS_OK;
+  }
   const int tb = tile_bits(total_tiles);
   uint32_t* dk[2] = {L.dk[0], L.dk[1]};
   uint32_t* dv[2] = {L.dv[0], L.dv[1]};
@@ -1194,9 +1906,11 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   }
   if (st != SGS_OK) return st;
   const uint32_t* order = dv[0];
+  if (mode == 2) return bin_rows(g, a, L, sc_main, order, m, n_views, cams_dev, T, C, keys, vals, ranges, n_inst,
+                                 tile_order, rb_rows, s);
   k_sorted_offsets<<<(unsigned)cdiv(mm, SO_TILE), 256, 0, s>>>(
       order, g->tiles, m, L.offs, n_inst, reinterpret_cast<uint64_t*>(L.so_status + 64), L.so_status, err,
-      L.bstart, (uint32_t)L.n_bstart, ex_shift_for(C));
+      L.bstart, (uint32_t)L.n_bstart, ex_shift_for(C), nullptr, nullptr);
   SGS_LAUNCH_CHECK();
   const int passes = L.main_passes;
   const int src = passes & 1;

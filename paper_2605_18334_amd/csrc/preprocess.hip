@@ -25,6 +25,7 @@ struct PreArgs {
   uint32_t* rect;
   uint32_t* tiles;
   uint32_t* block_sums;
+  uint32_t* rows;        // per record: tile rows with at least one tile (optional)
   int64_t n;
   int64_t m;
   int32_t nbx;
@@ -212,6 +213,7 @@ template <int DEG>
 __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
   __shared__ uint32_t s_pref[4][65];   // per wave: exclusive prefix of the records' rows
   __shared__ uint32_t s_cnt[256];
+  __shared__ uint32_t s_ne[256];       // rows with at least one tile
   __shared__ float s_span[16][4][64];  // per field, wave and lane: the record's Span and tile rect
   __shared__ uint32_t s_mark[4][64];   // per wave: owner marks of the current row window
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -285,6 +287,7 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
   s_pref[w][lane] = first;
   if (lane == 63) s_pref[w][64] = incl;
   s_cnt[t] = 0;
+  s_ne[t] = 0;
   {
     const float f[16] = {sp.mx, sp.my, sp.b, sp.det, sp.ia, sp.aR2, sp.ey, sp.ex,
                          sp.yx, sp.bx, sp.by, sp.need,
@@ -319,7 +322,10 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
       int c0, c1;
       span_row(so, __float_as_int(q3.w) + (int)(it - s_pref[w][o]), a.opt.tile_w, a.opt.tile_h,
                __float_as_int(q3.y), __float_as_int(q3.z), c0, c1);
-      if (c1 > c0) atomicAdd(&s_cnt[w * 64 + o], (uint32_t)(c1 - c0));
+      if (c1 > c0) {
+        atomicAdd(&s_cnt[w * 64 + o], (uint32_t)(c1 - c0));
+        atomicAdd(&s_ne[w * 64 + o], 1u);
+      }
     }
   }
   __syncthreads();
@@ -328,6 +334,7 @@ __global__ void __launch_bounds__(256) k_preprocess(PreArgs a) {
     // records without tiles get all-ones bits: they sort after every finite depth
     a.depth[m] = ntiles ? tz : __uint_as_float(0xffffffffu);
     a.tiles[m] = ntiles;
+    if (a.rows) a.rows[m] = s_ne[t];
     reinterpret_cast<uint2*>(a.rect)[m] = make_uint2(rx, ry);
   }
   // block sum of tile counts (for the instance offsets)
@@ -627,6 +634,7 @@ sgs_status launch_preprocess(const sgs_params* p, const sgs_camera* cams_dev, in
   a.depth = g->depth;
   a.rect = g->rect;
   a.tiles = g->tiles;
+  a.rows = g->rows;
   a.n = p->n;
   a.m = p->n * n_views;
   a.nbx = (int32_t)((p->n + 255) / 256);

@@ -20,7 +20,7 @@ size_t bin_sort_scratch_bytes(int64_t m, int64_t cap, int64_t total_tiles, int m
 sgs_status launch_bin_sort(const sgs_geom*, int64_t m, int64_t n, const sgs_camera*, int32_t,
                            int64_t total_tiles, const sgs_options*, int64_t cap, uint64_t*,
                            uint32_t*, uint32_t*, uint32_t*, uint32_t* tile_order, void*,
-                           float near_min, hipStream_t);
+                           float near_min, int32_t rb_rows, hipStream_t);
 sgs_status launch_blend_fwd(const sgs_geom*, int64_t, const uint32_t*, int64_t, const uint32_t*,
                             const sgs_schedule*, const sgs_camera*, int32_t, int64_t, int,
                             const sgs_options*, float*, float*, uint32_t*, uint32_t*, uint32_t*,
@@ -46,7 +46,7 @@ bool options_ok(const sgs_options* o) {
   return tile && batch && isfinite(o->filter_s) && o->filter_s >= 0.0f && isfinite(o->guard) &&
          o->guard > 0.0f && o->alpha_min > 0.0f && o->alpha_min < o->alpha_max &&
          o->alpha_max < 1.0f && o->t_min > 0.0f && o->t_min < 1.0f &&
-         (o->sort_mode == 0 || o->sort_mode == 1) && o->split_tiles >= -1 &&
+         (o->sort_mode >= -1 && o->sort_mode <= 2) && o->split_tiles >= -1 &&
          (o->depth_digit_bits == 0 || o->depth_digit_bits == 8 || o->depth_digit_bits == 10);
 }
 
@@ -121,7 +121,7 @@ void sgs_default_options(sgs_options* o) {
   o->alpha_min = 1.0f / 255.0f;
   o->alpha_max = 0.99f;
   o->t_min = 1e-4f;
-  o->sort_mode = 1;
+  o->sort_mode = -1;
   o->blend_batch = 0;
   o->split_tiles = -1;
   o->depth_digit_bits = 0;
@@ -234,10 +234,18 @@ int64_t sgs_geom_block_entries(int64_t n, int32_t n_views) {
   return (int64_t)n_views * ((n + 255) / 256) + 1;
 }
 
+// The sort mode a call runs: sort_mode, or with -1 (auto) row binning
+// (mode 2) from SGS_AUTO_ROWBIN_CAPACITY instances of capacity up (where it
+// measured faster) and the tile-key sort (mode 1) below.
+static int32_t sort_mode_for(const sgs_options* opt, int64_t cap) {
+  if (opt->sort_mode >= 0) return opt->sort_mode;
+  return cap >= SGS_AUTO_ROWBIN_CAPACITY ? 2 : 1;
+}
+
 size_t sgs_bin_sort_scratch_bytes(int64_t m, int64_t cap, int64_t total_tiles,
                                   const sgs_options* opt) {
   if (!opt || m < 0 || cap < 0) return 0;
-  return sgs::bin_sort_scratch_bytes(m, cap, total_tiles, opt->sort_mode);
+  return sgs::bin_sort_scratch_bytes(m, cap, total_tiles, sort_mode_for(opt, cap));
 }
 
 sgs_status sgs_preprocess(const sgs_params* p, const sgs_camera* cams_host,
@@ -252,6 +260,28 @@ sgs_status sgs_preprocess(const sgs_params* p, const sgs_camera* cams_host,
   return sgs::launch_preprocess(p, cams_dev, n_views, opt, g, (hipStream_t)stream);
 }
 
+// Sort mode 2 needs the row counts, at most 64 views, 256 tiles per view
+// row and 1024 tile rows in all: the number of global tile rows then, else
+// 0 (mode 1 sorts; same results).
+static int32_t rowbin_rows(const sgs_camera* cams_host, int32_t n_views, bool have_rows) {
+  if (!have_rows || n_views > 64) return 0;
+  int64_t rows = 0;
+  int32_t tx_max = 1;
+  for (int v = 0; v < n_views; ++v) {
+    rows += cams_host[v].tiles_y;
+    tx_max = std::max(tx_max, cams_host[v].tiles_x);
+  }
+  return rows <= 1024 && tx_max <= 256 ? (int32_t)std::max<int64_t>(rows, 1) : 0;
+}
+
+int32_t sgs_bin_sort_mode(const sgs_options* opt, int64_t inst_capacity, const sgs_camera* cams_host,
+                          int32_t n_views, int32_t have_rows) {
+  if (!options_ok(opt) || !cams_ok(cams_host, n_views) || inst_capacity < 0) return -1;
+  const int32_t mode = sort_mode_for(opt, inst_capacity);
+  if (mode == 2 && rowbin_rows(cams_host, n_views, have_rows != 0) == 0) return 1;
+  return mode;
+}
+
 sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_host,
                         const sgs_camera* cams_dev, int32_t n_views, const sgs_options* opt,
                         int64_t inst_capacity, uint64_t* keys, uint32_t* vals,
@@ -262,17 +292,21 @@ sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_hos
     return SGS_EINVAL;
   if (m % n_views != 0 || m >= ((int64_t)1 << 32)) return SGS_EINVAL;
   if (inst_capacity > 0 && !vals) return SGS_EINVAL;
-  if (opt->sort_mode == 0 && inst_capacity > 0 && !keys) return SGS_EINVAL;
+  const int32_t mode = sort_mode_for(opt, inst_capacity);
+  if (mode == 0 && inst_capacity > 0 && !keys) return SGS_EINVAL;
   if (m > 0 && (!g->rec || !g->depth || !g->rect || !g->tiles || !g->block_off)) return SGS_EINVAL;
   if (g->enhanced != 0 && g->enhanced != 1) return SGS_EINVAL;
   const int64_t tt = tiles_total(cams_host, n_views);
-  if (!scratch || scratch_bytes < sgs::bin_sort_scratch_bytes(m, inst_capacity, tt, opt->sort_mode))
+  if (!scratch || scratch_bytes < sgs::bin_sort_scratch_bytes(m, inst_capacity, tt, mode))
     return SGS_ECAPACITY;
   float near_min = cams_host[0].near_z;
   for (int v = 1; v < n_views; ++v) near_min = std::min(near_min, cams_host[v].near_z);
-  return sgs::launch_bin_sort(g, m, m / n_views, cams_dev, n_views, tt, opt, inst_capacity, keys,
+  const int32_t rb_rows = mode == 2 ? rowbin_rows(cams_host, n_views, m == 0 || g->rows) : 0;
+  sgs_options o = *opt;
+  o.sort_mode = mode;
+  return sgs::launch_bin_sort(g, m, m / n_views, cams_dev, n_views, tt, &o, inst_capacity, keys,
                               vals, tile_ranges, n_inst_dev, sched ? sched->tile_order : nullptr,
-                              scratch, near_min, (hipStream_t)stream);
+                              scratch, near_min, rb_rows, (hipStream_t)stream);
 }
 
 sgs_status sgs_bin_sort_noalloc(const sgs_geom* g, int64_t m, const sgs_camera* cams_host,
@@ -286,7 +320,7 @@ sgs_status sgs_bin_sort_noalloc(const sgs_geom* g, int64_t m, const sgs_camera* 
       inst_capacity < 0 || inst_capacity >= ((int64_t)1 << 32))
     return SGS_EINVAL;
   const size_t need = sgs::bin_sort_scratch_bytes(m, inst_capacity, tiles_total(cams_host, n_views),
-                                                  opt->sort_mode);
+                                                  sort_mode_for(opt, inst_capacity));
   if (need > (size_t)SGS_NOALLOC_SCRATCH_BYTES) return SGS_ECAPACITY;
   void* ws = nullptr;
   const sgs_status st = noalloc_scratch(&ws);

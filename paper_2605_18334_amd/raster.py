@@ -154,9 +154,10 @@ def alloc_geom(m: int, n: int, n_views: int, enhanced: bool, device=DEV) -> tupl
         "rect": torch.empty(max(2 * m, 2), dtype=torch.int32, device=device),
         "tiles": torch.empty(max(m, 1), dtype=torch.int32, device=device),
         "block_off": torch.empty(int(lib.sgs_geom_block_entries(n, n_views)), dtype=torch.int32, device=device),
+        "rows": torch.empty(max(m, 1), dtype=torch.int32, device=device),
     }
     g = _abi.Geom(_ptr(b["rec"]), _ptr(b["depth"]), _ptr(b["rect"]), _ptr(b["tiles"]), _ptr(b["block_off"]),
-                  int(enhanced), 0)
+                  _ptr(b["rows"]), int(enhanced), 0)
     return g, b
 
 
@@ -335,7 +336,7 @@ def renderer_device_bytes(n: int, n_views: int, enhanced: bool, total_tiles: int
     m = n * n_views
     cap = max(int(capacity), 1)
     geom = (4 * int(lib.sgs_geom_rec_floats(m, int(enhanced))) + 4 * max(m, 1) + 4 * max(2 * m, 2)
-            + 4 * max(m, 1) + 4 * int(lib.sgs_geom_block_entries(n, n_views)))
+            + 8 * max(m, 1) + 4 * int(lib.sgs_geom_block_entries(n, n_views)))
     sort = (4 * cap + 8 * total_tiles + 4 + (8 * cap if (keep_keys or opt.sort_mode == 0) else 0)
             + int(lib.sgs_bin_sort_scratch_bytes(m, int(capacity), total_tiles, C.byref(opt))))
     out = 20 * total_pixels + (8 * total_pixels if count else 0)

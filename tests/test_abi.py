@@ -45,7 +45,7 @@ def test_struct_sizes_match_binding():
 def test_default_options_and_status_strings():
     _abi, lib = _lib()
     o = _abi.default_options()
-    assert (o.tile_w, o.tile_h, o.blend_batch, o.sort_mode, o.compensate) == (16, 16, 0, 1, 1)
+    assert (o.tile_w, o.tile_h, o.blend_batch, o.sort_mode, o.compensate) == (16, 16, 0, -1, 1)
     assert o.split_tiles == -1 and o.depth_digit_bits == 0
     assert o.alpha_min == pytest.approx(1 / 255) and o.alpha_max == pytest.approx(0.99)
     assert o.t_min == pytest.approx(1e-4) and o.filter_s == pytest.approx(0.3)
@@ -138,7 +138,7 @@ def test_options_are_validated_on_the_host():
     ok = _abi.default_options()
     assert lib.sgs_camera_layout(cams, 1, C.byref(ok), C.byref(tt), C.byref(tp)) == 0
     assert (tt.value, tp.value) == (4 * 3, 64 * 48)
-    for bad in (dict(tile_w=32), dict(blend_batch=100), dict(sort_mode=2), dict(split_tiles=-2),
+    for bad in (dict(tile_w=32), dict(blend_batch=100), dict(sort_mode=3), dict(sort_mode=-2), dict(split_tiles=-2),
                 dict(alpha_min=0.0), dict(t_min=1.0), dict(depth_digit_bits=11)):
         o = _abi.default_options(**bad)
         assert lib.sgs_camera_layout(cams, 1, C.byref(o), C.byref(tt), C.byref(tp)) == 1, bad
@@ -173,3 +173,33 @@ def test_package_never_reaches_the_oracle():
                 if re.search(r"\boracle\b", text):
                     found.append(os.path.relpath(os.path.join(dirpath, f), ROOT))
     assert not found, found
+
+
+def test_bin_sort_mode_choice_on_the_host():
+    """sgs_bin_sort_mode (no GPU): auto picks row binning from 2^22 instances
+    of capacity, the tile-key sort below; row binning needs the row counts,
+    at most 256 tiles per row and 1024 tile rows, else the tile-key sort
+    runs; explicit modes are kept; bad arguments give -1."""
+    _abi, lib = _lib()
+    o = _abi.default_options()
+    cams = (_abi.Camera * 2)()
+    for k in range(2):
+        cams[k].width, cams[k].height, cams[k].fx, cams[k].fy = 1600, 1064, 900.0, 900.0
+    tt, tp = C.c_int64(), C.c_int64()
+    assert lib.sgs_camera_layout(cams, 2, C.byref(o), C.byref(tt), C.byref(tp)) == 0
+    big, small = 1 << 22, (1 << 22) - 1
+    assert lib.sgs_bin_sort_mode(C.byref(o), big, cams, 2, 1) == 2
+    assert lib.sgs_bin_sort_mode(C.byref(o), small, cams, 2, 1) == 1
+    assert lib.sgs_bin_sort_mode(C.byref(o), big, cams, 2, 0) == 1          # no row counts
+    for mode in (0, 1, 2):
+        assert lib.sgs_bin_sort_mode(C.byref(_abi.default_options(sort_mode=mode)), 1000, cams, 2, 1) == mode
+    wide = (_abi.Camera * 1)()
+    wide[0].width, wide[0].height, wide[0].fx, wide[0].fy = 4112, 64, 900.0, 900.0   # 257 tiles per row
+    assert lib.sgs_camera_layout(wide, 1, C.byref(o), C.byref(tt), C.byref(tp)) == 0
+    assert lib.sgs_bin_sort_mode(C.byref(o), big, wide, 1, 1) == 1
+    tall = (_abi.Camera * 1)()
+    tall[0].width, tall[0].height, tall[0].fx, tall[0].fy = 64, 16400, 900.0, 900.0  # 1025 tile rows
+    assert lib.sgs_camera_layout(tall, 1, C.byref(o), C.byref(tt), C.byref(tp)) == 0
+    assert lib.sgs_bin_sort_mode(C.byref(o), big, tall, 1, 1) == 1
+    assert lib.sgs_bin_sort_mode(C.byref(_abi.default_options(sort_mode=5)), big, cams, 2, 1) == -1
+    assert lib.sgs_bin_sort_mode(C.byref(o), -1, cams, 2, 1) == -1
