@@ -36,6 +36,12 @@ ALU_PEAK_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # compositing a pair (T(1-alpha) 2, colour accumulation 7) = 9 more
 FLOPS_EVAL = 20
 FLOPS_COMPOSITE = 9
+# backward per composited pair (the pairs Alg. 2 walks): the evaluation again
+# (20) and the gradient terms: 1/(1-alpha), T and the weight 3, dL/dalpha 8,
+# shared factors 6, the 11 record-gradient terms 27, colour-behind update 6,
+# their sums over the tile's pixels 11 -> 20 + 61 flops; pairs skipped behind
+# the last contributor are not counted (a lower bound of the work)
+FLOPS_BWD_COMPOSITE = 81
 
 
 def log(*a):
@@ -250,11 +256,11 @@ def fwd_bwd(steps: int, warmup: int):
     T = P.Renderer(P.GaussianSet.from_scene(tgt), cams, opt)
     target = T.forward().clone()
     del T
-    R = P.Renderer(P.GaussianSet.from_scene(sc), cams, opt)
+    R = P.Renderer(P.GaussianSet.from_scene(sc), cams, opt, count=True)   # (counts only when asked)
     npx = target.numel()
 
     def step():
-        out = R.forward()
+        out = R.forward(count=False)
         dL = torch.sign(out - target).mul_(1.0 / npx)
         return R.backward(dL)
 
@@ -263,26 +269,38 @@ def fwd_bwd(steps: int, warmup: int):
     torch.cuda.synchronize()
     # steps back to back (a training loop does not wait per step); events at
     # the step boundaries give the forward / backward split
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
     t0 = time.perf_counter()
     for e in ev:
         e[0].record()
-        out = R.forward()
+        out = R.forward(count=False)
         e[1].record()
         dL = torch.sign(out - target).mul_(1.0 / npx)
-        R.backward(dL)
+        R.backward(dL, events=(e[3], e[4]))
         e[2].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev[0][0].elapsed_time(ev[-1][2])
     assert not R.overflowed()
     stages = stage_times(R)
+    # backward roofline: the library call (blend backward + chain rule), the
+    # composited pairs from a counting forward outside the timed loop
+    bwd_ms = float(np.mean([e[3].elapsed_time(e[4]) for e in ev]))
+    R.forward(count=True)
+    torch.cuda.synchronize()
+    pairs = int(R.bufs["count"].to(torch.int64).sum().item())
+    achieved = pairs * FLOPS_BWD_COMPOSITE / (bwd_ms / 1e3) / 1e12
+    roof_bwd = {"kernel": "k_blend_bwd + k_preprocess_bwd (sgs_render_bwd)", "bound": "alu",
+                "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / ALU_PEAK_TFLOPS, "peak_nonpacked": ALU_PEAK_NONPACKED_TFLOPS,
+                "frac_nonpacked": achieved / ALU_PEAK_NONPACKED_TFLOPS, "ms": bwd_ms,
+                "units": f"{pairs} composited pairs x {FLOPS_BWD_COMPOSITE} flops, per call"}
     pre_bytes = sc.n * (56 + sh_bytes(sc.sh_degree)) + sc.n * 64
     si = sort_info(R)
     sbw = stage_bandwidth(pre_bytes, sort_stage_bytes(sc.n, R.n_inst(), cams.total_tiles, 4, si["mode"],
                                                       si["n_items"], si["item_passes"]), stages)
     return {"metric": "fwd+bwd iters/s at 1M Gaussians", "value": steps / (gpu_ms / 1e3), "unit": "iters/s",
-            "stages_ms": stages, "stage_bandwidth": sbw,
+            "stages_ms": stages, "stage_bandwidth": sbw, "roofline_bwd": roof_bwd,
             "wall_iters_s": steps / wall,
             "ms_fwd": float(np.mean([e[0].elapsed_time(e[1]) for e in ev])),
             "ms_bwd": float(np.mean([e[1].elapsed_time(e[2]) for e in ev])),
@@ -422,7 +440,7 @@ def serving(duration_s: float, rates):
     be = GpuBackend({"A": scA, "B": scB})
     del scA, scB
     res = {}
-    runs = [(f"batched@{r}", r, 8, 2) for r in rates] + [(f"fifo@{r}", r, 1, 1) for r in rates[1:]]
+    runs = [(f"batched@{r}", r, 8, 2) for r in rates] + [(f"fifo@{r}", r, 1, 1) for r in rates]
     for name, rate, mb, mi in runs:
         rng = np.random.default_rng(8)
         srv = RenderServer(be, budget_bytes=64 << 30, max_batch=mb, max_inflight=mi)
@@ -431,6 +449,7 @@ def serving(duration_s: float, rates):
         srv.submit(Request("A", S.random_request_pose(rng))).result(timeout=120)
         srv.submit(Request("B", S.random_request_pose(rng))).result(timeout=120)
         srv.results.clear()
+        reruns0 = be.reruns
         t0 = time.perf_counter()
         t = 0.0
         n = 0
@@ -446,6 +465,7 @@ def serving(duration_s: float, rates):
             n += 1
         srv.stop(drain=True, timeout=120)
         st = srv.stats()
+        st["reruns"] = be.reruns - reruns0     # overflowed batches rendered again (this run)
         st["offered_req_s"] = rate
         st["mpix_s"] = pix / max(st.get("span_s", 1e-9), 1e-9) / 1e6
         res[name] = st

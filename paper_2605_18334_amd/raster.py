@@ -477,10 +477,12 @@ class Renderer:
         return self.out_rgb[:, c.pix_base:c.pix_base + c.width * c.height].reshape(3, c.height, c.width)
 
     # ---- backward
-    def backward(self, dL_drgb: torch.Tensor, stream=None, densify: dict | None = None) -> dict:
+    def backward(self, dL_drgb: torch.Tensor, stream=None, densify: dict | None = None,
+                 events=None) -> dict:
         """Gradients (fresh zeroed buffers reused across calls) for dL/dC;
         ``densify`` (from densify_stats) accumulates the densification
-        statistics of this backward."""
+        statistics of this backward; ``events`` (two torch.cuda.Events on
+        the current stream) are recorded around the library call alone."""
         gs = self.gs
         if self._bwd is None:
             # the 2D gradients and every parameter gradient are views of one
@@ -500,11 +502,15 @@ class Renderer:
         pg = _params_grad(grads, densify)
         flat.zero_()
         b = self.bufs
+        if events is not None:
+            events[0].record()
         check("sgs_render_bwd", self.lib.sgs_render_bwd(
             C.byref(self.params), C.byref(self.geom), self.m, _ptr(b["vals"]), self.capacity,
             _ptr(b["ranges"]), C.byref(self.sched), self.cams.host, _ptr(self.cams.dev), self.cams.n_views, C.byref(self.opt),
             _ptr(self.out_T), _ptr(self.out_last), _ptr(dL_drgb), self.cams.total_pixels,
             C.byref(gg), C.byref(pg), _stream(stream)))
+        if events is not None:
+            events[1].record()
         return grads
 
 

@@ -86,7 +86,7 @@ class RenderServer:
         self.inflight: list[_Batch] = []
         self.in_use = 0
         self.lock = threading.Lock()
-        self.results: list[Result] = []
+        self.results: list[Result] = []         # completed requests (timing only, no images)
         self.batches = 0
         self.failed = 0
         self.concurrency = []     # requests admitted and not yet done, after each launch
@@ -150,7 +150,9 @@ class RenderServer:
                     f.set_exception(ServerError(f"batch failed: {err!r}"))
                     continue
                 res = Result(r.rid, imgs[k] if r.want_image else None, r.t_arrival, t, len(b.reqs))
-                self.results.append(res)
+                # the server keeps the timing only: the image goes to the
+                # caller's future and lives as long as the caller keeps it
+                self.results.append(Result(r.rid, None, r.t_arrival, t, len(b.reqs)))
                 f.set_result(res)
             self.backend.release(b.handle)
             self.in_use -= b.nbytes
@@ -320,7 +322,9 @@ class GpuBackend:
         n = int(h["n_host"][0]) & 0xFFFFFFFF
         check_instance_count(n, R.capacity)
         P = R.cams.total_pixels
-        self.ipp[h["scene"]] = max(0.5 * self.ipp[h["scene"]], n / max(P, 1))
+        # a slowly decaying maximum: poses of one scene differ a lot in
+        # instances per pixel, and an overflow costs a second render
+        self.ipp[h["scene"]] = max(0.98 * self.ipp[h["scene"]], n / max(P, 1))
         out = []
         for v in range(len(h["poses"])):
             c = R.cams.view(v)
