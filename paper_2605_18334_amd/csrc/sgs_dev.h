@@ -178,8 +178,10 @@ __device__ __forceinline__ void span_row(const Span& s, int row, int tw, int th,
   u0 = fmaxf(u0, -s.ey);
   u1 = fminf(u1, s.ey);
   if (!(u0 <= u1)) return;
-  const float r0 = sqrtf(fmaxf(s.aR2 - s.det * u0 * u0, 0.0f));
-  const float r1 = sqrtf(fmaxf(s.aR2 - s.det * u1 * u1, 0.0f));
+  // (hardware square root and reciprocal, within an ulp or two: far inside
+  // the widening margins below; every caller runs this same code)
+  const float r0 = __builtin_amdgcn_sqrtf(fmaxf(s.aR2 - s.det * u0 * u0, 0.0f));
+  const float r1 = __builtin_amdgcn_sqrtf(fmaxf(s.aR2 - s.det * u1 * u1, 0.0f));
   float xr = fmaxf((-s.b * u0 + r0) * s.ia, (-s.b * u1 + r1) * s.ia);
   float xl = fminf((-s.b * u0 - r0) * s.ia, (-s.b * u1 - r1) * s.ia);
   if (s.yx >= u0 && s.yx <= u1) xr = s.ex;
@@ -190,8 +192,9 @@ __device__ __forceinline__ void span_row(const Span& s, int row, int tw, int th,
   const float px0 = ceilf(s.mx + xl - 0.5f), px1 = floorf(s.mx + xr - 0.5f);
   if (!(px0 <= px1) || !(px1 >= 0.0f)) return;
   const float lo = fmaxf(px0, 0.0f);
-  const int t0 = (int)fminf(lo, 1e9f) / tw;
-  const int t1 = (int)fminf(px1, 1e9f) / tw + 1;
+  const int tsh = 31 - __clz(tw);             // tile widths are powers of two
+  const int t0 = (int)fminf(lo, 1e9f) >> tsh;
+  const int t1 = ((int)fminf(px1, 1e9f) >> tsh) + 1;
   c0 = max(x0, t0);
   c1 = min(x1, t1);
   // skew cut over the tiles of this row (tile boxes: half extents tw/2, th/2)
@@ -201,11 +204,12 @@ __device__ __forceinline__ void span_row(const Span& s, int row, int tw, int th,
     const float base = skew_box_max(s.bx, s.by, hx, cy, s.mx, s.my, hx, hy);   // column 0
     const float step = s.bx * (float)tw;                                        // per column
     const float slack = 1e-3f * (1.0f + fabsf(base) + fabsf(s.need) + fabsf(step) * (float)c1);
+    const float istep = __builtin_amdgcn_rcpf(step);
     if (step > 0.0f) {
-      const float k = (s.need - base - slack) / step;
+      const float k = (s.need - base - slack) * istep;
       if (k > (float)c0) c0 = min(c1, (int)ceilf(fminf(k, 1e9f)));
     } else if (step < 0.0f) {
-      const float k = (s.need - base - slack) / step;    // columns <= k survive
+      const float k = (s.need - base - slack) * istep;   // columns <= k survive
       if (k < (float)(c1 - 1)) c1 = max(c0, (int)floorf(fmaxf(k, -1e9f)) + 1);
     } else if (base + slack < s.need) {
       c1 = c0;

@@ -476,6 +476,10 @@ class Renderer:
         c = self.cams.view(v)
         return self.out_rgb[:, c.pix_base:c.pix_base + c.width * c.height].reshape(3, c.height, c.width)
 
+    def transmittance(self, v: int = 0) -> torch.Tensor:
+        c = self.cams.view(v)
+        return self.out_T[c.pix_base:c.pix_base + c.width * c.height].reshape(c.height, c.width)
+
     # ---- backward
     def backward(self, dL_drgb: torch.Tensor, stream=None, densify: dict | None = None,
                  events=None) -> dict:
