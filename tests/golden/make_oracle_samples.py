@@ -1,6 +1,6 @@
 """Writes the FP64 oracle's expected values for the full-size parity tests.
 
-    python tests/golden/make_oracle_samples.py [clustered] [blobs1m]
+    python tests/golden/make_oracle_samples.py [clustered] [blobs1m] [batch16] [serve]
 
 The brute-force oracle takes minutes per workload at these sizes (every
 Gaussian at every sampled pixel), so its results are stored once and read by
@@ -12,6 +12,14 @@ clustered_300k_4096px.npz: the clustered workload (300k skew Gaussians, SH3,
   transmittance, the oracle's ambiguity flags (decisions within the margins
   where float32 may decide the other way) and, for ambiguous pixels, the
   colour and transmittance of every outcome of their uncertain decisions.
+
+batch16_3m_2views_1024px.npz: the 16-view batch workload (3M skew Gaussians,
+  4-blob generator, SH0, 16 spline poses of mixed resolution): 1024 seeded
+  tile-stratified pixels of views 0 and 9, as for the clustered frame.
+
+serve_5m2m_4requests_512px.npz: the serving scenes (5M skew and 2M zero-skew
+  clustered SH3): two seeded requests per scene (the served-request pose
+  generator), 512 seeded pixels of each.
 
 blobs_1m_masked_4096px.npz: the differentiation workload (1M skew Gaussians,
   4-blob generator, SH0, one 1600x1064 view) with a masked loss
@@ -87,9 +95,59 @@ def blobs1m(path: str) -> None:
     print(f"blobs1m: {len(reached)} Gaussians reached, {len(sample)} sampled", flush=True)
 
 
+BATCH_VIEWS = (0, 9)          # two of the 16 views (different resolutions)
+N_PIX_BATCH = 1024
+SERVE_SEED = 123
+N_SERVE = 2                   # requests per scene
+N_PIX_SERVE = 512
+
+
+def batch16(path: str) -> None:
+    sc, poses = S.batch_config()
+    out = {}
+    for v in BATCH_VIEWS:
+        pose = poses[v]
+        px = S.sample_pixels(PIXEL_SEED_BLOBS + v, pose.width, pose.height, N_PIX_BATCH)
+        t0 = time.time()
+        r = O.render(sc, pose, pixels=px)
+        print(f"batch16 view {v} ({pose.width}x{pose.height}): {time.time() - t0:.0f} s, "
+              f"ambiguous {r.ambiguous.mean():.4f}", flush=True)
+        for k, val in (("pixels", px), ("color", r.color), ("T", r.T), ("ambiguous", r.ambiguous),
+                       ("alt_start", r.alt_start), ("alt_rows", r.alt_rows)):
+            out[f"v{v}_{k}"] = val
+    np.savez_compressed(path, views=np.array(BATCH_VIEWS), **out)
+
+
+def serve_requests():
+    """The seeded requests the serving parity test sends: N_SERVE per scene,
+    scene A first, poses from the served-request generator."""
+    rng = np.random.default_rng(SERVE_SEED)
+    return [(name, S.random_request_pose(rng)) for name in ("A",) * N_SERVE + ("B",) * N_SERVE]
+
+
+def serve(path: str) -> None:
+    scA, scB = S.serve_scenes()
+    out = {}
+    for i, (name, pose) in enumerate(serve_requests()):
+        sc = scA if name == "A" else scB
+        px = S.sample_pixels(SERVE_SEED + i, pose.width, pose.height, N_PIX_SERVE)
+        t0 = time.time()
+        r = O.render(sc, pose, pixels=px)
+        print(f"serve request {i} (scene {name}, {pose.width}x{pose.height}): {time.time() - t0:.0f} s, "
+              f"ambiguous {r.ambiguous.mean():.4f}", flush=True)
+        for k, val in (("pixels", px), ("color", r.color), ("T", r.T), ("ambiguous", r.ambiguous),
+                       ("alt_start", r.alt_start), ("alt_rows", r.alt_rows)):
+            out[f"r{i}_{k}"] = val
+    np.savez_compressed(path, n=np.array(len(serve_requests())), **out)
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["clustered", "blobs1m"]
+    which = sys.argv[1:] or ["clustered", "blobs1m", "batch16", "serve"]
     if "clustered" in which:
         clustered(os.path.join(HERE, "clustered_300k_4096px.npz"))
     if "blobs1m" in which:
         blobs1m(os.path.join(HERE, "blobs_1m_masked_4096px.npz"))
+    if "batch16" in which:
+        batch16(os.path.join(HERE, "batch16_3m_2views_1024px.npz"))
+    if "serve" in which:
+        serve(os.path.join(HERE, "serve_5m2m_4requests_512px.npz"))
