@@ -1256,14 +1256,16 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
                                                    uint32_t cap, uint32_t* __restrict__ vals,
                                                    uint64_t* __restrict__ keys, const float* __restrict__ depth,
                                                    uint64_t m) {
-  __shared__ uint64_t S[4][256];              // per wave: lanes whose item starts at / covers each column
-  __shared__ union {
-    uint64_t e[4][256];                       // per wave: lanes whose item ends at each column
-    uint2 b[4][256];                          // then per wave and column: (staging base, global base)
-  } EB;
+  // per-column arrays are indexed by pc(c) = c + c / 32: lane l scans
+  // columns 4l..4l+3, which the padding spreads over the banks
+  constexpr int PC = 256 + 8;
+  auto pc = [](uint32_t c) { return c + (c >> 5); };
+  __shared__ uint64_t S[4][PC];               // per wave: lanes whose item starts at / covers each column
+  __shared__ uint64_t E[4][PC];               // per wave: lanes whose item ends at each column
+  __shared__ uint2 BS[4][PC];                 // per wave and column: (staging base, global base)
   __shared__ union {
     uint2 st[RB_STG];                         // staged placements (record, global position)
-    uint32_t cnt[4][256];                     // per wave: covering lanes per column (before staging)
+    uint32_t cnt[4][PC];                      // per wave: covering lanes per column (before staging)
   } SG;
   __shared__ uint32_t gb[256];                // next global position of each column in this piece
   __shared__ uint32_t ws[4];
@@ -1277,8 +1279,8 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
   load_views(cams, n_views, vt);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    S[wv][4 * lane + q] = 0ull;
-    EB.e[wv][4 * lane + q] = 0ull;
+    S[wv][pc(4 * lane + q)] = 0ull;
+    E[wv][pc(4 * lane + q)] = 0ull;
   }
   __syncthreads();
   const uint64_t lt = lanemask_lt();
@@ -1320,55 +1322,54 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
       const uint32_t x0 = item_x0(key), w = valid ? item_w(key) : 0u;
       // (this wave's S and E rows are zero here)
       if (valid) {
-        atomicOr(reinterpret_cast<unsigned long long*>(&S[wv][x0]), 1ull << lane);
-        if (x0 + w < 256u) atomicOr(reinterpret_cast<unsigned long long*>(&EB.e[wv][x0 + w]), 1ull << lane);
+        atomicOr(reinterpret_cast<unsigned long long*>(&S[wv][pc(x0)]), 1ull << lane);
+        if (x0 + w < 256u) atomicOr(reinterpret_cast<unsigned long long*>(&E[wv][pc(x0 + w)]), 1ull << lane);
       }
       __builtin_amdgcn_wave_barrier();
       {
         // inclusive OR prefixes over the columns (lane l: columns 4l..4l+3),
         // then cover = started & ~ended
+        // (E is cleared as it is read: the next group's atomics need it zero)
         uint64_t a[4], b[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          a[q] = S[wv][4 * lane + q];
-          b[q] = EB.e[wv][4 * lane + q];
+          a[q] = S[wv][pc(4 * lane + q)];
+          b[q] = E[wv][pc(4 * lane + q)];
+          E[wv][pc(4 * lane + q)] = 0ull;
           if (q > 0) {
             a[q] |= a[q - 1];
             b[q] |= b[q - 1];
           }
         }
-        uint64_t xa = a[3], xb = b[3];
-        for (int off = 1; off < 64; off <<= 1) {
-          const uint64_t ya = __shfl_up(xa, off), yb = __shfl_up(xb, off);
-          if (lane >= off) {
-            xa |= ya;
-            xb |= yb;
-          }
-        }
+        // inclusive OR over the lanes' totals (DPP, per 32-bit half), then
+        // the exclusive one from the lane below
+        const uint64_t xa = ((uint64_t)wave_incl_or((uint32_t)(a[3] >> 32)) << 32) | wave_incl_or((uint32_t)a[3]);
+        const uint64_t xb = ((uint64_t)wave_incl_or((uint32_t)(b[3] >> 32)) << 32) | wave_incl_or((uint32_t)b[3]);
         uint64_t pa = __shfl_up(xa, 1), pb = __shfl_up(xb, 1);
         if (lane == 0) pa = pb = 0ull;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const uint64_t cov = (a[q] | pa) & ~(b[q] | pb);
-          S[wv][4 * lane + q] = cov;
-          SG.cnt[wv][4 * lane + q] = (uint32_t)__popcll(cov);
+          S[wv][pc(4 * lane + q)] = cov;
+          SG.cnt[wv][pc(4 * lane + q)] = (uint32_t)__popcll(cov);
         }
       }
       __syncthreads();
       uint32_t c0, c1, c2, gc;
       {
-        c0 = SG.cnt[0][t];
-        c1 = SG.cnt[1][t];
-        c2 = SG.cnt[2][t];
-        gc = c0 + c1 + c2 + SG.cnt[3][t];
+        const uint32_t pt_ = pc(t);
+        c0 = SG.cnt[0][pt_];
+        c1 = SG.cnt[1][pt_];
+        c2 = SG.cnt[2][pt_];
+        gc = c0 + c1 + c2 + SG.cnt[3][pt_];
       }
       const uint32_t gs = block_scan256_total(gc, ws, &s_tot);   // (synchronises)
       {
-        const uint32_t g = gb[t];
-        EB.b[0][t] = make_uint2(gs, g);
-        EB.b[1][t] = make_uint2(gs + c0, g + c0);
-        EB.b[2][t] = make_uint2(gs + c0 + c1, g + c0 + c1);
-        EB.b[3][t] = make_uint2(gs + c0 + c1 + c2, g + c0 + c1 + c2);
+        const uint32_t g = gb[t], pt_ = pc(t);
+        BS[0][pt_] = make_uint2(gs, g);
+        BS[1][pt_] = make_uint2(gs + c0, g + c0);
+        BS[2][pt_] = make_uint2(gs + c0 + c1, g + c0 + c1);
+        BS[3][pt_] = make_uint2(gs + c0 + c1 + c2, g + c0 + c1 + c2);
         gb[t] = g + gc;
       }
       __syncthreads();
@@ -1380,8 +1381,8 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
         uint64_t cv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const uint32_t c = min(x0 + kk + u, 255u);
-          bs[u] = EB.b[wv][c];
+          const uint32_t c = pc(min(x0 + kk + u, 255u));
+          bs[u] = BS[wv][c];
           cv[u] = S[wv][c];
         }
 #pragma unroll
@@ -1416,10 +1417,7 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        S[wv][4 * lane + q] = 0ull;
-        EB.e[wv][4 * lane + q] = 0ull;
-      }
+      for (int q = 0; q < 4; ++q) S[wv][pc(4 * lane + q)] = 0ull;
       __syncthreads();
     }
   }
