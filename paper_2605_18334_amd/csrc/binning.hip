@@ -241,7 +241,10 @@ __global__ void __launch_bounds__(256) k_hist_final(const uint32_t* __restrict__
 // is the pass time.
 // DB: bins per digit; thread t < DB handles digit t (DB <= NT).  xf: the key
 // transform applied where the first pass reads its keys (see KeyXf).
-template <typename K, int NT, int LB_W, int DB = 256>
+// LOOP: the grid is smaller than the block count and its workgroups loop
+// over the block ids (without it each workgroup takes one id and the loop
+// compiles away).
+template <typename K, int NT, int LB_W, int DB = 256, bool LOOP = false>
 __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
                                                 const uint32_t* __restrict__ vin,
                                                 K* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -434,7 +437,7 @@ __global__ void __launch_bounds__(NT) k_os_pass(const K* __restrict__ kin,
   }
   // a grid that covers every data block in its first round of ids takes no
   // second id (that would cost one more atomic round trip)
-  if ((uint64_t)gridDim.x * RS_TILE >= n) break;
+  if (!LOOP || (uint64_t)gridDim.x * RS_TILE >= n) break;
   __syncthreads();   // (LDS reused by the next block id)
   }
 }
@@ -1591,18 +1594,20 @@ static sgs_status radix_sort(const K* kin, const uint32_t* vin, K* kb[2], uint32
     const uint32_t* vi = p == 0 ? vin : vb[dst ^ 1];
     // (grids of at most the workgroups that fit at once: they loop over
     // the block ids, so a capacity far above the count costs no launches)
-    if (blocks <= RS_WIDE_MAX_BLOCKS)
-      k_os_pass<K, 1024, LB_W, DB><<<(unsigned)std::min<uint64_t>(blocks, RS_GRID_1024), 1024, 0, s>>>(
-        ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * DB,
-        sc.status + (size_t)p * blocks * DB, sc.counters + p, sc.err, sc.n_fold,
-        p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot,
-        p == 0 ? xf : none);
-    else if constexpr (DB == 256)
-      k_os_pass<K, 512, LB_W><<<(unsigned)std::min<uint64_t>(blocks, RS_GRID_512), 512, 0, s>>>(
-        ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * 256,
-        sc.status + (size_t)p * blocks * 256, sc.counters + p, sc.err, sc.n_fold,
-        p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot,
-        p == 0 ? xf : none);
+#define SGS_PASS_ARGS(D)                                                                          \
+  ki, vi, kb[dst], vb[dst], n_dev, n_host, (uint32_t)cap, width * p, nb, sc.ghist + p * (D),        \
+      sc.status + (size_t)p * blocks * (D), sc.counters + p, sc.err, sc.n_fold,                     \
+      p == passes - 1 ? ranges : nullptr, n_tiles, p == 0 ? pre0 : nullptr, pre0_tot, p == 0 ? xf : none
+    if (blocks <= RS_WIDE_MAX_BLOCKS) {
+      if (blocks <= RS_GRID_1024)
+        k_os_pass<K, 1024, LB_W, DB, false><<<(unsigned)blocks, 1024, 0, s>>>(SGS_PASS_ARGS(DB));
+      else
+        k_os_pass<K, 1024, LB_W, DB, true><<<(unsigned)RS_GRID_1024, 1024, 0, s>>>(SGS_PASS_ARGS(DB));
+    } else if constexpr (DB == 256) {
+      k_os_pass<K, 512, LB_W, 256, true><<<(unsigned)std::min<uint64_t>(blocks, RS_GRID_512), 512, 0, s>>>(
+          SGS_PASS_ARGS(256));
+    }
+#undef SGS_PASS_ARGS
     SGS_LAUNCH_CHECK();
   }
   return SGS_OK;
