@@ -1366,7 +1366,14 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
         c2 = SG.cnt[2][pt_];
         gc = c0 + c1 + c2 + SG.cnt[3][pt_];
       }
-      const uint32_t gs = block_scan256_total(gc, ws, &s_tot);   // (synchronises)
+      // staging start of column t: an exclusive scan over the columns (DPP
+      // within each wave, the waves' totals through LDS)
+      const uint32_t inc = wave_incl_scan(gc);
+      if (lane == 63) ws[wv] = inc;
+      __syncthreads();
+      uint32_t gs = inc - gc;
+      for (int q = 0; q < wv; ++q) gs += ws[q];
+      const uint32_t T = ws[0] + ws[1] + ws[2] + ws[3];
       {
         const uint32_t g = gb[t], pt_ = pc(t);
         BS[0][pt_] = make_uint2(gs, g);
@@ -1376,7 +1383,6 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
         gb[t] = g + gc;
       }
       __syncthreads();
-      const uint32_t T = s_tot;
       const bool stage = T <= (uint32_t)RB_STG && !keys;
       // (four columns per step: their LDS reads are in flight together)
       for (uint32_t kk = 0; kk < w; kk += 4) {
