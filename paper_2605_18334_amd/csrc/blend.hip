@@ -273,7 +273,10 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
     // that are finished or outside a record's ellipse are masked
     const int nw = __builtin_amdgcn_readfirstlane(S.n[w]);   // wave-uniform
     int jn = nw > 0 ? S.list[w][0] : 0;
-    for (int i = 0; i < nw; ++i) {
+    // (a guarded body and a wave-uniform exit flag in the loop condition,
+    // rather than continue and break)
+    bool ended = false;
+    for (int i = 0; i < nw && !ended; ++i) {
       const uint32_t e = (uint32_t)__builtin_amdgcn_readfirstlane(jn);
       const int j = (int)(e & LIST_SLOT);
       if (i + 1 < nw) jn = S.list[w][i + 1];
@@ -283,33 +286,34 @@ __device__ __forceinline__ void fwd_tile(const BlendArgs& a, int tile, Stage<TW,
       const float dx = fx - r0.x, dy = fy - r0.y;
       const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
       const bool in = !done && l2 >= r2.w;
-      if (!wave_any(in)) continue;
-      if (CNT && in) ++evals;
-      Pair2 p;
-      pair_eval2(l2, r1.y, r1.z, dx, dy, (e & LIST_SKEW) != 0u, p);
-      float at = p.at;
-      if (ENH) {
-        const float4 r3 = S.r3[j];
-        float eu, ee;
-        at *= enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
+      if (wave_any(in)) {
+        if (CNT && in) ++evals;
+        Pair2 p;
+        pair_eval2(l2, r1.y, r1.z, dx, dy, (e & LIST_SKEW) != 0u, p);
+        float at = p.at;
+        if (ENH) {
+          const float4 r3 = S.r3[j];
+          float eu, ee;
+          at *= enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
+        }
+        const float alpha = fminf(a.alpha_max, at);
+        // the skip test again rather than `in`: a bool kept across the branch
+        // above costs two VALU instructions to rebuild as a lane mask
+        const bool take = !done && l2 >= r2.w && alpha >= a.alpha_min;
+        const float Tn = T * (1.0f - alpha);
+        const bool stop = take && Tn < a.t_min;
+        if (take && !stop) {
+          const float wgt = alpha * T;
+          C0 = fmaf(r2.x, wgt, C0);
+          C1 = fmaf(r2.y, wgt, C1);
+          C2 = fmaf(r2.z, wgt, C2);
+          T = Tn;
+          last = base - rg.x + (uint32_t)j + 1u;
+          if (CNT) ++count;
+        }
+        done = done || stop;
+        ended = wave_any(stop) && wave_all(done);
       }
-      const float alpha = fminf(a.alpha_max, at);
-      // the skip test again rather than `in`: a bool kept across the branch
-      // above costs two VALU instructions to rebuild as a lane mask
-      const bool take = !done && l2 >= r2.w && alpha >= a.alpha_min;
-      const float Tn = T * (1.0f - alpha);
-      const bool stop = take && Tn < a.t_min;
-      if (take && !stop) {
-        const float wgt = alpha * T;
-        C0 = fmaf(r2.x, wgt, C0);
-        C1 = fmaf(r2.y, wgt, C1);
-        C2 = fmaf(r2.z, wgt, C2);
-        T = Tn;
-        last = base - rg.x + (uint32_t)j + 1u;
-        if (CNT) ++count;
-      }
-      done = done || stop;
-      if (wave_any(stop) && wave_all(done)) break;
     }
   }
   if (ts.inside) {
@@ -364,7 +368,8 @@ __device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quart
     const int cnt = (int)min((uint32_t)B, rg.y - base);
     stage_batch<16, 16, B, ENH, 4>(a, ts, base, cnt, S);
     const int nw = __builtin_amdgcn_readfirstlane(S.n[w]);   // wave-uniform
-    for (int i = 0; i < nw; i += 4) {
+    bool ended = false;   // (a wave-uniform exit flag rather than a break)
+    for (int i = 0; i < nw && !ended; i += 4) {
       const int k = i + sub;
       const bool has = k < nw;
       const uint32_t e = has ? S.list[w][k] : 0u;
@@ -414,7 +419,7 @@ __device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quart
       SGS_QUAD_STEP(2)
       SGS_QUAD_STEP(3)
 #undef SGS_QUAD_STEP
-      if (wave_all(done)) break;
+      ended = wave_all(done);
     }
   }
   if (CNT)   // the quad's four lanes evaluated disjoint records of the pixel
@@ -554,68 +559,72 @@ __device__ __forceinline__ void bwd_tile(const BlendArgs& a, int tile, BwdShared
       const float dx = fx - r0.x, dy = fy - r0.y;
       const float l2 = pair_log2(r0.z, r0.w, r1.x, r1.w, dx, dy);
       const bool in = (uint32_t)(start + j) < last && l2 >= r2.w;
-      if (!wave_any(in)) continue;
-      // from here on every lane computes; lanes without a contribution get
-      // zero weights through selects (nested branches made the compiler
-      // re-zero all gradient registers on every path)
-      Pair2 p;
-      pair_eval2(l2, r1.y, r1.z, dx, dy, skew, p);
-      float at = p.at, o = 1.0f, eu = 0.0f, ee = 1.0f;
-      float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (ENH) {
-        r3 = S.r3[j];
-        o = enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
-        at *= o;
+      // (guarded blocks rather than continue: the loop's control flow
+      // then stays a plain counted loop in scalar code)
+      if (wave_any(in)) {
+        // from here on every lane computes; lanes without a contribution get
+        // zero weights through selects (nested branches made the compiler
+        // re-zero all gradient registers on every path)
+        Pair2 p;
+        pair_eval2(l2, r1.y, r1.z, dx, dy, skew, p);
+        float at = p.at, o = 1.0f, eu = 0.0f, ee = 1.0f;
+        float4 r3 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ENH) {
+          r3 = S.r3[j];
+          o = enh_opacity(r3.x, r3.y, r3.z, r3.w, dx, dy, eu, ee);
+          at *= o;
+        }
+        const float alpha = fminf(a.alpha_max, at);
+        const bool hit = in && alpha >= a.alpha_min;
+        if (wave_any(hit)) {
+          const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+          const float Tn = T * inv;                 // transmittance in front of this pair
+          T = hit ? Tn : T;
+          const float wgt = hit ? alpha * Tn : 0.0f;
+          const bool unc = hit && at <= a.alpha_max;   // alpha not clamped: gradients reach it
+          const float dLda = unc ? ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) * Tn -
+                                       Tfinal * inv * bgdot
+                                 : 0.0f;
+          const float ath = unc ? at : 0.0f;
+          // common = dL/dalpha d o G'; (qa, qc) = Q delta and beta from the
+          // staged base-2 constants
+          const float common = unc ? dLda * o * p.dG : 0.0f;
+          const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
+          const float qa = -SGS_LN2 * fmaf(2.0f * r0.z, dx, r0.w * dy);
+          const float qc = -SGS_LN2 * fmaf(r0.w, dx, 2.0f * r1.x * dy);
+          float gv[NG];
+          gv[0] = common * (qa * p.E - s2pi * (SGS_IKZ * r1.y));
+          gv[1] = common * (qc * p.E - s2pi * (SGS_IKZ * r1.z));
+          gv[2] = -0.5f * dx * dx * dLda * ath;
+          gv[3] = -dx * dy * dLda * ath;
+          gv[4] = -0.5f * dy * dy * dLda * ath;
+          gv[5] = common * s2pi * dx;
+          gv[6] = common * s2pi * dy;
+          gv[7] = common * p.E * S.idv[j];
+          gv[8] = wgt * g0;
+          gv[9] = wgt * g1;
+          gv[10] = wgt * g2;
+          if constexpr (ENH) {
+            const float base = unc ? p.at : 0.0f;        // rho G' (1 + erf z)
+            const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
+            gv[0] -= dLda * base * dodw * r3.z;
+            gv[1] -= dLda * base * dodw * r3.w;
+            gv[11] = dLda * base * 0.5f * (1.0f + eu);
+            gv[12] = dLda * base * 0.5f * (1.0f - eu);
+            gv[13] = dLda * base * dodw * dx;
+            gv[14] = dLda * base * dodw * dy;
+          }
+          S0 = hit ? fmaf(alpha, r2.x - S0, S0) : S0;
+          S1 = hit ? fmaf(alpha, r2.y - S1, S1) : S1;
+          S2 = hit ? fmaf(alpha, r2.z - S2, S2) : S2;
+          // transposing sum over each 16-lane row (DPP): lane l of a row ends
+          // with the row's sum of value l, then one LDS atomic per lane; the
+          // VALU is this kernel's bound, the LDS pipe has room
+          const float sv = row_transpose_sum<NG>(gv, lane);
+          const int q = lane & 15;
+          if (q < NG && sv != 0.0f) atomicAdd(&sg[q][j], sv);
+        }
       }
-      const float alpha = fminf(a.alpha_max, at);
-      const bool hit = in && alpha >= a.alpha_min;
-      if (!wave_any(hit)) continue;
-      const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-      const float Tn = T * inv;                 // transmittance in front of this pair
-      T = hit ? Tn : T;
-      const float wgt = hit ? alpha * Tn : 0.0f;
-      const bool unc = hit && at <= a.alpha_max;   // alpha not clamped: gradients reach it
-      const float dLda = unc ? ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) * Tn -
-                                   Tfinal * inv * bgdot
-                             : 0.0f;
-      const float ath = unc ? at : 0.0f;
-      // common = dL/dalpha d o G'; (qa, qc) = Q delta and beta from the
-      // staged base-2 constants
-      const float common = unc ? dLda * o * p.dG : 0.0f;
-      const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
-      const float qa = -SGS_LN2 * fmaf(2.0f * r0.z, dx, r0.w * dy);
-      const float qc = -SGS_LN2 * fmaf(r0.w, dx, 2.0f * r1.x * dy);
-      float gv[NG];
-      gv[0] = common * (qa * p.E - s2pi * (SGS_IKZ * r1.y));
-      gv[1] = common * (qc * p.E - s2pi * (SGS_IKZ * r1.z));
-      gv[2] = -0.5f * dx * dx * dLda * ath;
-      gv[3] = -dx * dy * dLda * ath;
-      gv[4] = -0.5f * dy * dy * dLda * ath;
-      gv[5] = common * s2pi * dx;
-      gv[6] = common * s2pi * dy;
-      gv[7] = common * p.E * S.idv[j];
-      gv[8] = wgt * g0;
-      gv[9] = wgt * g1;
-      gv[10] = wgt * g2;
-      if constexpr (ENH) {
-        const float base = unc ? p.at : 0.0f;        // rho G' (1 + erf z)
-        const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
-        gv[0] -= dLda * base * dodw * r3.z;
-        gv[1] -= dLda * base * dodw * r3.w;
-        gv[11] = dLda * base * 0.5f * (1.0f + eu);
-        gv[12] = dLda * base * 0.5f * (1.0f - eu);
-        gv[13] = dLda * base * dodw * dx;
-        gv[14] = dLda * base * dodw * dy;
-      }
-      S0 = hit ? fmaf(alpha, r2.x - S0, S0) : S0;
-      S1 = hit ? fmaf(alpha, r2.y - S1, S1) : S1;
-      S2 = hit ? fmaf(alpha, r2.z - S2, S2) : S2;
-      // transposing sum over each 16-lane row (DPP): lane l of a row ends
-      // with the row's sum of value l, then one LDS atomic per lane; the
-      // VALU is this kernel's bound, the LDS pipe has room
-      const float sv = row_transpose_sum<NG>(gv, lane);
-      const int q = lane & 15;
-      if (q < NG && sv != 0.0f) atomicAdd(&sg[q][j], sv);
     }
     __syncthreads();
     flush_batch<TW, TH, B, ENH>(a, cnt, X);
@@ -702,76 +711,77 @@ __device__ __forceinline__ void bwd_quad(const BlendArgs& a, int tile, int quart
         alpha = fminf(a.alpha_max, at);
       }
       const bool hit = in && alpha >= a.alpha_min;
-      if (!wave_any(hit)) continue;
-      // transmittance and colour-behind recursion, records in list order
-      // (latest first), replicated on the quad
-      const int hi = hit ? 1 : 0;
-      const float cr = r2.x, cg = r2.y, cb = r2.z;
-      float Tm = 0.0f, Sm0 = 0.0f, Sm1 = 0.0f, Sm2 = 0.0f;
-#define SGS_QUAD_BACK(Q)                                                     \
-      if (quad_bcast<Q>(hi)) {                                               \
-        const float al = quad_bcast<Q>(alpha);                               \
-        T = T * __builtin_amdgcn_rcpf(1.0f - al);                            \
-        if (sub == Q) {                                                      \
-          Tm = T;                                                            \
-          Sm0 = S0;                                                          \
-          Sm1 = S1;                                                          \
-          Sm2 = S2;                                                          \
-        }                                                                    \
-        S0 = fmaf(al, quad_bcast<Q>(cr) - S0, S0);                           \
-        S1 = fmaf(al, quad_bcast<Q>(cg) - S1, S1);                           \
-        S2 = fmaf(al, quad_bcast<Q>(cb) - S2, S2);                           \
-      }
-      SGS_QUAD_BACK(0)
-      SGS_QUAD_BACK(1)
-      SGS_QUAD_BACK(2)
-      SGS_QUAD_BACK(3)
-#undef SGS_QUAD_BACK
-      // every lane computes; lanes without a contribution get zero weights
-      // through selects (no nested branches around the gradient registers)
-      const float wgt = hit ? alpha * Tm : 0.0f;
-      const bool unc = hit && at <= a.alpha_max;   // alpha not clamped: gradients reach it
-      const float dLda = unc ? ((r2.x - Sm0) * g0 + (r2.y - Sm1) * g1 + (r2.z - Sm2) * g2) * Tm -
-                                   Tfinal * __builtin_amdgcn_rcpf(1.0f - alpha) * bgdot
-                             : 0.0f;
-      const float ath = unc ? at : 0.0f;
-      const float common = unc ? dLda * o * p.dG : 0.0f;
-      const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
-      const float qa = -SGS_LN2 * fmaf(2.0f * r0.z, dx, r0.w * dy);
-      const float qc = -SGS_LN2 * fmaf(r0.w, dx, 2.0f * r1.x * dy);
-      float gv[NG];
-      gv[0] = common * (qa * p.E - s2pi * (SGS_IKZ * r1.y));
-      gv[1] = common * (qc * p.E - s2pi * (SGS_IKZ * r1.z));
-      gv[2] = -0.5f * dx * dx * dLda * ath;
-      gv[3] = -dx * dy * dLda * ath;
-      gv[4] = -0.5f * dy * dy * dLda * ath;
-      gv[5] = common * s2pi * dx;
-      gv[6] = common * s2pi * dy;
-      gv[7] = common * p.E * S.idv[j];
-      gv[8] = wgt * g0;
-      gv[9] = wgt * g1;
-      gv[10] = wgt * g2;
-      if constexpr (ENH) {
-        const float base = unc ? p.at : 0.0f;
-        const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
-        gv[0] -= dLda * base * dodw * r3.z;
-        gv[1] -= dLda * base * dodw * r3.w;
-        gv[11] = dLda * base * 0.5f * (1.0f + eu);
-        gv[12] = dLda * base * 0.5f * (1.0f - eu);
-        gv[13] = dLda * base * dodw * dx;
-        gv[14] = dLda * base * dodw * dy;
-      }
-      // sums over the 16 pixels of each sublane (lanes equal mod 4): within
-      // a row by DPP row rotations by 4 and 8, across rows by shuffles;
-      // lanes 0..3 hold sublanes 0..3
-#pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        float v = gv[q];
-        v += dpp_src<0x124>(v);   // row_ror:4
-        v += dpp_src<0x128>(v);   // row_ror:8
-        v += __shfl_xor(v, 16);
-        v += __shfl_xor(v, 32);
-        if (lane < 4 && has && v != 0.0f) atomicAdd(&sg[q][j], v);
+      if (wave_any(hit)) {   // (a guarded block rather than continue)
+        // transmittance and colour-behind recursion, records in list order
+        // (latest first), replicated on the quad
+        const int hi = hit ? 1 : 0;
+        const float cr = r2.x, cg = r2.y, cb = r2.z;
+        float Tm = 0.0f, Sm0 = 0.0f, Sm1 = 0.0f, Sm2 = 0.0f;
+  #define SGS_QUAD_BACK(Q)                                                     \
+        if (quad_bcast<Q>(hi)) {                                               \
+          const float al = quad_bcast<Q>(alpha);                               \
+          T = T * __builtin_amdgcn_rcpf(1.0f - al);                            \
+          if (sub == Q) {                                                      \
+            Tm = T;                                                            \
+            Sm0 = S0;                                                          \
+            Sm1 = S1;                                                          \
+            Sm2 = S2;                                                          \
+          }                                                                    \
+          S0 = fmaf(al, quad_bcast<Q>(cr) - S0, S0);                           \
+          S1 = fmaf(al, quad_bcast<Q>(cg) - S1, S1);                           \
+          S2 = fmaf(al, quad_bcast<Q>(cb) - S2, S2);                           \
+        }
+        SGS_QUAD_BACK(0)
+        SGS_QUAD_BACK(1)
+        SGS_QUAD_BACK(2)
+        SGS_QUAD_BACK(3)
+  #undef SGS_QUAD_BACK
+        // every lane computes; lanes without a contribution get zero weights
+        // through selects (no nested branches around the gradient registers)
+        const float wgt = hit ? alpha * Tm : 0.0f;
+        const bool unc = hit && at <= a.alpha_max;   // alpha not clamped: gradients reach it
+        const float dLda = unc ? ((r2.x - Sm0) * g0 + (r2.y - Sm1) * g1 + (r2.z - Sm2) * g2) * Tm -
+                                     Tfinal * __builtin_amdgcn_rcpf(1.0f - alpha) * bgdot
+                               : 0.0f;
+        const float ath = unc ? at : 0.0f;
+        const float common = unc ? dLda * o * p.dG : 0.0f;
+        const float s2pi = SGS_SQRT_2_OVER_PI * p.ez;
+        const float qa = -SGS_LN2 * fmaf(2.0f * r0.z, dx, r0.w * dy);
+        const float qc = -SGS_LN2 * fmaf(r0.w, dx, 2.0f * r1.x * dy);
+        float gv[NG];
+        gv[0] = common * (qa * p.E - s2pi * (SGS_IKZ * r1.y));
+        gv[1] = common * (qc * p.E - s2pi * (SGS_IKZ * r1.z));
+        gv[2] = -0.5f * dx * dx * dLda * ath;
+        gv[3] = -dx * dy * dLda * ath;
+        gv[4] = -0.5f * dy * dy * dLda * ath;
+        gv[5] = common * s2pi * dx;
+        gv[6] = common * s2pi * dy;
+        gv[7] = common * p.E * S.idv[j];
+        gv[8] = wgt * g0;
+        gv[9] = wgt * g1;
+        gv[10] = wgt * g2;
+        if constexpr (ENH) {
+          const float base = unc ? p.at : 0.0f;
+          const float dodw = (r3.x - r3.y) * SGS_INV_SQRT_2PI * ee;
+          gv[0] -= dLda * base * dodw * r3.z;
+          gv[1] -= dLda * base * dodw * r3.w;
+          gv[11] = dLda * base * 0.5f * (1.0f + eu);
+          gv[12] = dLda * base * 0.5f * (1.0f - eu);
+          gv[13] = dLda * base * dodw * dx;
+          gv[14] = dLda * base * dodw * dy;
+        }
+        // sums over the 16 pixels of each sublane (lanes equal mod 4): within
+        // a row by DPP row rotations by 4 and 8, across rows by shuffles;
+        // lanes 0..3 hold sublanes 0..3
+  #pragma unroll
+        for (int q = 0; q < NG; ++q) {
+          float v = gv[q];
+          v += dpp_src<0x124>(v);   // row_ror:4
+          v += dpp_src<0x128>(v);   // row_ror:8
+          v += __shfl_xor(v, 16);
+          v += __shfl_xor(v, 32);
+          if (lane < 4 && has && v != 0.0f) atomicAdd(&sg[q][j], v);
+        }
       }
     }
     __syncthreads();
