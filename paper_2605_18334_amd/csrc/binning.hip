@@ -1383,28 +1383,47 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
         gb[t] = g + gc;
       }
       __syncthreads();
-      const bool stage = T <= (uint32_t)RB_STG && !keys;
-      // (four columns per step: their LDS reads are in flight together)
-      for (uint32_t kk = 0; kk < w; kk += 4) {
-        uint2 bs[4];
-        uint64_t cv[4];
+      // (block-uniform, tested once: two loops rather than a test per
+      // column; four columns per step, their LDS reads in flight together)
+      const bool stage = __builtin_amdgcn_readfirstlane(T) <= (uint32_t)RB_STG && !keys;
+      if (stage) {
+        for (uint32_t kk = 0; kk < w; kk += 4) {
+          uint2 bs[4];
+          uint64_t cv[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const uint32_t c = pc(min(x0 + kk + u, 255u));
-          bs[u] = BS[wv][c];
-          cv[u] = S[wv][c];
-        }
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t c = pc(min(x0 + kk + u, 255u));
+            bs[u] = BS[wv][c];
+            cv[u] = S[wv][c];
+          }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (kk + u < w) {
-            const uint32_t rank = (uint32_t)__popcll(cv[u] & lt);
-            if (stage) {
+          for (int u = 0; u < 4; ++u) {
+            if (kk + u < w) {
+              const uint32_t rank = (uint32_t)__popcll(cv[u] & lt);
               SG.st[bs[u].x + rank] = make_uint2(val, bs[u].y + rank);
-            } else if (bs[u].y + rank < cap) {
-              vals[bs[u].y + rank] = val;
-              if (keys)
-                keys[bs[u].y + rank] = ((uint64_t)(t0 + x0 + kk + u) << 32) |
-                                       (val < m ? (uint64_t)__float_as_uint(depth[val]) : 0ull);
+            }
+          }
+        }
+      } else {
+        for (uint32_t kk = 0; kk < w; kk += 4) {
+          uint2 bs[4];
+          uint64_t cv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t c = pc(min(x0 + kk + u, 255u));
+            bs[u] = BS[wv][c];
+            cv[u] = S[wv][c];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (kk + u < w) {
+              const uint32_t rank = (uint32_t)__popcll(cv[u] & lt);
+              if (bs[u].y + rank < cap) {
+                vals[bs[u].y + rank] = val;
+                if (keys)
+                  keys[bs[u].y + rank] = ((uint64_t)(t0 + x0 + kk + u) << 32) |
+                                         (val < m ? (uint64_t)__float_as_uint(depth[val]) : 0ull);
+              }
             }
           }
         }
