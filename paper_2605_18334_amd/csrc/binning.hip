@@ -1267,7 +1267,8 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
   __shared__ uint64_t E[4][PC];               // per wave: lanes whose item ends at each column
   __shared__ uint2 BS[4][PC];                 // per wave and column: (staging base, global base)
   __shared__ union {
-    uint2 st[RB_STG];                         // staged placements (record, global position)
+    uint2 st[RB_STG + 64];                    // staged placements (record, global position),
+                                              // then one spare slot per lane
     uint32_t cnt[4][PC];                      // per wave: covering lanes per column (before staging)
   } SG;
   __shared__ uint32_t gb[256];                // next global position of each column in this piece
@@ -1396,12 +1397,13 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
             bs[u] = BS[wv][c];
             cv[u] = S[wv][c];
           }
+          // (columns past the item's end go to the lane's spare slot: no
+          // branch per column)
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            if (kk + u < w) {
-              const uint32_t rank = (uint32_t)__popcll(cv[u] & lt);
-              SG.st[bs[u].x + rank] = make_uint2(val, bs[u].y + rank);
-            }
+            const uint32_t rank = (uint32_t)__popcll(cv[u] & lt);
+            const uint32_t slot = kk + u < w ? bs[u].x + rank : (uint32_t)RB_STG + (uint32_t)lane;
+            SG.st[slot] = make_uint2(val, bs[u].y + rank);
           }
         }
       } else {
