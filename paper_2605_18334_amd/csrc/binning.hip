@@ -1258,7 +1258,7 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
                                                    const uint32_t* __restrict__ ranges, uint32_t n_tiles,
                                                    uint32_t cap, uint32_t* __restrict__ vals,
                                                    uint64_t* __restrict__ keys, const float* __restrict__ depth,
-                                                   uint64_t m) {
+                                                   uint64_t m, const uint32_t* __restrict__ n_total) {
   // per-column arrays are indexed by pc(c) = c + c / 32: lane l scans
   // columns 4l..4l+3, which the padding spreads over the banks
   constexpr int PC = 256 + 8;
@@ -1279,6 +1279,9 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
   __shared__ ViewTable vt;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const uint32_t P = ptab[R];
+  // every position below the capacity (the usual case): the write-out
+  // stores need no test
+  const bool fits = *n_total <= cap;
   for (int k = t; k < 2 * (R + 1); k += 256) pt[k] = ptab[k];
   load_views(cams, n_views, vt);
 #pragma unroll
@@ -1431,7 +1434,20 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
         }
       }
       __syncthreads();
-      if (stage) {
+      if (stage && fits) {
+        uint32_t q = t;
+        for (; q + 768 < T; q += 1024) {
+          uint2 v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = SG.st[q + 256 * u];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) vals[v[u].y] = v[u].x;
+        }
+        for (; q < T; q += 256) {
+          const uint2 v = SG.st[q];
+          vals[v.y] = v.x;
+        }
+      } else if (stage) {
         uint32_t q = t;
         for (; q + 768 < T; q += 1024) {
           uint2 v[4];
@@ -1795,7 +1811,7 @@ static sgs_status bin_rows(const sgs_geom* g, DupArgs a, const BinLayout& L, con
   if (C > 0) {
     const unsigned rgrid = (pgrid + 7u) & ~7u;   // a multiple of 8 (the XCD chunks)
     k_row_place<<<rgrid, 256, 0, s>>>(ik[0], iv[0], L.ptab, R, nb_shift, cams_dev, n_views, L.pre_col, ranges,
-                                      (uint32_t)T, (uint32_t)C, vals, keys, g->depth, mm);
+                                      (uint32_t)T, (uint32_t)C, vals, keys, g->depth, mm, n_inst);
     SGS_LAUNCH_CHECK();
   }
   return SGS_OK;
