@@ -941,31 +941,33 @@ static inline int nb_shift_for(uint64_t cap) {
   return sh;
 }
 
-// Mode 2, step 3: row items.  Same traversal as k_expand32 (block b owns
-// items [b*EXT, (b+1)*EXT) of the depth-ordered item list, records in chunks
-// of 256 with their spans in LDS, (record, rect row) pairs enumerated 256 at
-// a time), but a pair becomes one item when its row has tiles, at the
-// record's item offset plus the number of non-empty rows before it.  Counts
-// the row digits for the row sort (per block for the first pass) and the
-// items of each row (row_cnt, R rows).
+// Mode 2, step 3: row items.  Block b owns items [b*EXT, (b+1)*EXT) of the
+// depth-ordered item list (grid-stride over such emission blocks).  Its
+// records, from the one owning item b*EXT on, go to the block's waves in
+// chunks of 64 (wave w takes chunks w, w + 4, ...): a chunk's items are one
+// contiguous output range starting at its first record's item offset, so a
+// wave enumerates its chunk's (record, rect row) pairs 64 at a time on its
+// own (each record's span in LDS, found by a max-scan of marks), and a pair
+// whose row has tiles becomes one item at that offset plus the count of
+// such pairs before it (a DPP scan).  Counts the row digits for the row
+// sort (per block for the first pass) and the items of each row (row_cnt,
+// R rows).
 template <int EXT>
 __global__ void __launch_bounds__(256) k_emit_rows(DupArgs a, const uint32_t* __restrict__ n_items_p,
                                                    uint32_t* __restrict__ row_cnt, int n_rows, int n_views,
                                                    uint32_t n_eblocks) {
   constexpr int NSP = 13;
-  __shared__ float s_sp[NSP][256];
+  __shared__ float s_sp[NSP][256];        // per wave and lane: its record's span
   __shared__ uint32_t s_r0[256], s_r1[256];
   __shared__ uint32_t s_rec[256];
   __shared__ uint32_t s_grow[256];        // global row of the record's first rect row
-  __shared__ uint32_t s_rows[257];
-  __shared__ uint32_t s_mark[256];
-  __shared__ uint32_t s_wmax[4];
+  __shared__ uint32_t s_first[256];       // the record's first pair in its wave's chunk
+  __shared__ uint32_t s_mark[4][64];
   __shared__ uint32_t s_vrb[RB_MAX_VIEWS];   // first global row of each view
   __shared__ uint32_t hist[2][256];
   __shared__ uint32_t s_rc[RB_MAX_ROWS];     // items per row
-  __shared__ uint32_t ws[4];
-  __shared__ uint32_t s_tot, s_j0, s_w;
-  const int t = threadIdx.x;
+  __shared__ uint32_t s_j0, s_w;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t total = *n_items_p;
   const uint32_t n = total < a.cap ? total : a.cap;
   const uint32_t dmask = (1u << a.hwidth) - 1u;
@@ -977,31 +979,33 @@ __global__ void __launch_bounds__(256) k_emit_rows(DupArgs a, const uint32_t* __
   }
   // emission blocks eb = blockIdx.x, + gridDim.x, ...
   for (uint32_t eb = blockIdx.x; eb < n_eblocks; eb += gridDim.x) {
-  const uint64_t o0 = (uint64_t)eb * EXT;
-  if (o0 >= n) {   // no items: zero counts for the first pass's column scan
-    if (a.cnt0) a.cnt0[(uint64_t)eb * 256 + t] = 0u;
-    continue;
-  }
-  const uint64_t o1 = min(o0 + (uint64_t)EXT, (uint64_t)n);
-  if (t == 0) {
-    const uint64_t jlo = min((uint64_t)a.bstart[eb], (uint64_t)a.m - 1);
-    s_j0 = (uint32_t)jlo;
-    s_w = (uint32_t)min((uint64_t)EXT + 1, (uint64_t)a.m - jlo);
-  }
-  __syncthreads();
-  const uint32_t j0 = s_j0, W = s_w;
-  uint64_t run = a.offs[j0];    // item offset of the next (record, row) pair with tiles
-  for (uint32_t c = 0; c < W && run < o1; c += 256) {
-    const uint32_t k = c + t;
-    uint32_t rows = 0;
-    if (k < W) {
+    const uint64_t o0 = (uint64_t)eb * EXT;
+    if (o0 >= n) {   // no items: zero counts for the first pass's column scan
+      if (a.cnt0) a.cnt0[(uint64_t)eb * 256 + t] = 0u;
+      continue;
+    }
+    const uint64_t o1 = min(o0 + (uint64_t)EXT, (uint64_t)n);
+    if (t == 0) {
+      const uint64_t jlo = min((uint64_t)a.bstart[eb], (uint64_t)a.m - 1);
+      s_j0 = (uint32_t)jlo;
+      s_w = (uint32_t)min((uint64_t)EXT + 1, (uint64_t)a.m - jlo);
+    }
+    __syncthreads();
+    const uint32_t j0 = s_j0, W = s_w;
+    for (uint32_t c = 64u * (uint32_t)w; c < W; c += 256) {
+      const uint32_t k = c + (uint32_t)lane;
       const uint64_t j = (uint64_t)j0 + k;
-      const uint32_t rec = a.order[j];
-      s_rec[t] = rec;
-      const uint32_t off = a.offs[j];
+      uint32_t rows = 0, rec = 0, off = 0;
       bool has = false;
-      if ((k == 0 || off < o1) && rec < (uint64_t)a.m)
-        has = j + 1 < (uint64_t)a.m ? a.offs[j + 1] > off : a.rows[rec] > 0;
+      if (k < W) {
+        rec = a.order[j];
+        off = a.offs[j];
+        if ((k == 0 || off < o1) && rec < (uint64_t)a.m)
+          has = j + 1 < (uint64_t)a.m ? a.offs[j + 1] > off : a.rows[rec] > 0;
+      }
+      // the chunk's first item offset (lane 0's record: k = c < W)
+      uint64_t run = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);
+      if (run >= o1) break;   // this and every later chunk start past the block
       if (has) {
         const float4* rp = a.rec + 4 * (uint64_t)rec;
         const float4 q0 = rp[0], q1 = rp[1], q2 = rp[2];
@@ -1024,66 +1028,67 @@ __global__ void __launch_bounds__(256) k_emit_rows(DupArgs a, const uint32_t* __
         const uint32_t v = rec / (uint32_t)a.n;
         s_grow[t] = (v < RB_MAX_VIEWS ? s_vrb[v] : 0u) + (r.x >> 16);
       }
-    }
-    const uint32_t e = block_scan256_total(rows, ws, &s_tot);
-    s_rows[t] = e;
-    if (t == 255) s_rows[256] = e + rows;
-    __syncthreads();
-    const uint32_t R = s_rows[256];
-    for (uint32_t base = 0; base < R && run < o1; base += 256) {
-      const uint32_t i = base + t;
-      s_mark[t] = 0u;
-      __syncthreads();
-      if (rows > 0 && e < base + 256 && e + rows > base) s_mark[(e > base ? e : base) - base] = (uint32_t)t + 1u;
-      __syncthreads();
-      const uint32_t wm = wave_incl_max(s_mark[t]);
-      if ((t & 63) == 63) s_wmax[t >> 6] = wm;
-      __syncthreads();
-      uint32_t own = wm;
-      for (int q = 0; q < (t >> 6); ++q) own = max(own, s_wmax[q]);
-      uint32_t ne = 0, item = 0, rec = 0;
-      if (i < R) {
-        const uint32_t lo = own - 1u;
-        rec = s_rec[lo];
-        Span sp;
-        sp.mx = s_sp[0][lo];  sp.my = s_sp[1][lo];  sp.b = s_sp[2][lo];   sp.det = s_sp[3][lo];
-        sp.ia = s_sp[4][lo];  sp.aR2 = s_sp[5][lo]; sp.ey = s_sp[6][lo];  sp.ex = s_sp[7][lo];
-        sp.yx = s_sp[8][lo];  sp.bx = s_sp[9][lo];  sp.by = s_sp[10][lo]; sp.need = s_sp[11][lo];
-        const uint32_t fl = __float_as_uint(s_sp[12][lo]);
-        sp.ok = (fl & 1u) != 0u;
-        sp.cut = (fl & 2u) != 0u;
-        const uint32_t r0 = s_r0[lo];
-        const int x0 = r0 & 0xffffu, x1 = s_r1[lo] & 0xffffu;
-        const uint32_t dy = i - s_rows[lo];
-        int c0, c1;
-        span_row(sp, (int)(r0 >> 16) + (int)dy, a.tile_w, a.tile_h, x0, x1, c0, c1);
-        if (c1 > c0) {
-          ne = 1;
-          item = ((s_grow[lo] + dy) & 0xffffu) | ((uint32_t)c0 << 16) | ((uint32_t)(c1 - c0 - 1) << 24);
+      s_rec[t] = rec;
+      const uint32_t incl = wave_incl_scan(rows);
+      const uint32_t first = incl - rows;
+      s_first[t] = first;
+      const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+      __builtin_amdgcn_wave_barrier();
+      for (uint32_t base = 0; base < R && run < o1; base += 64) {
+        const uint32_t i = base + (uint32_t)lane;
+        // the pair's record: the last of the chunk starting at or before it
+        // (each record overlapping [base, base + 64) marks its first pair
+        // there, at distinct positions)
+        s_mark[w][lane] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (rows > 0 && first < base + 64 && incl > base) s_mark[w][(first > base ? first : base) - base] = (uint32_t)lane + 1u;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t own = wave_incl_max(s_mark[w][lane]);
+        __builtin_amdgcn_wave_barrier();
+        uint32_t ne = 0, item = 0, irec = 0;
+        if (i < R) {
+          const uint32_t lo = 64u * (uint32_t)w + own - 1u;
+          irec = s_rec[lo];
+          Span sp;
+          sp.mx = s_sp[0][lo];  sp.my = s_sp[1][lo];  sp.b = s_sp[2][lo];   sp.det = s_sp[3][lo];
+          sp.ia = s_sp[4][lo];  sp.aR2 = s_sp[5][lo]; sp.ey = s_sp[6][lo];  sp.ex = s_sp[7][lo];
+          sp.yx = s_sp[8][lo];  sp.bx = s_sp[9][lo];  sp.by = s_sp[10][lo]; sp.need = s_sp[11][lo];
+          const uint32_t fl = __float_as_uint(s_sp[12][lo]);
+          sp.ok = (fl & 1u) != 0u;
+          sp.cut = (fl & 2u) != 0u;
+          const uint32_t r0 = s_r0[lo];
+          const int x0 = r0 & 0xffffu, x1 = s_r1[lo] & 0xffffu;
+          const uint32_t dy = i - s_first[lo];
+          int c0, c1;
+          span_row(sp, (int)(r0 >> 16) + (int)dy, a.tile_w, a.tile_h, x0, x1, c0, c1);
+          if (c1 > c0) {
+            ne = 1;
+            item = ((s_grow[lo] + dy) & 0xffffu) | ((uint32_t)c0 << 16) | ((uint32_t)(c1 - c0 - 1) << 24);
+          }
         }
+        const uint32_t inc2 = wave_incl_scan(ne);
+        const uint64_t pos = run + (inc2 - ne);
+        if (ne && pos >= o0 && pos < o1) {
+          a.keys32[pos] = item;
+          a.vals[pos] = irec;
+          const uint32_t row = item_row(item);
+          atomicAdd(&hist[0][row & dmask], 1u);
+          if (a.hpasses > 1) atomicAdd(&hist[1][(row >> a.hwidth) & dmask], 1u);
+          if (row < (uint32_t)n_rows) atomicAdd(&s_rc[row], 1u);
+        }
+        run += (uint32_t)__builtin_amdgcn_readlane((int)inc2, 63);
       }
-      const uint32_t e2 = block_scan256_total(ne, ws, &s_tot);
-      const uint64_t pos = run + e2;
-      if (ne && pos >= o0 && pos < o1) {
-        a.keys32[pos] = item;
-        a.vals[pos] = rec;
-        const uint32_t row = item_row(item);
-        atomicAdd(&hist[0][row & dmask], 1u);
-        if (a.hpasses > 1) atomicAdd(&hist[1][(row >> a.hwidth) & dmask], 1u);
-        if (row < (uint32_t)n_rows) atomicAdd(&s_rc[row], 1u);
-      }
-      run += s_tot;
-      __syncthreads();
+      // (the wave's record slots are rewritten by its next chunk)
+      __builtin_amdgcn_wave_barrier();
     }
-  }
-  __syncthreads();
-  if (a.cnt0) a.cnt0[(uint64_t)eb * 256 + t] = hist[0][t];
-  uint32_t* hdst = a.hpart + (size_t)(eb % (unsigned)a.hcopies) * a.hpasses * 256;
-  for (int p = 0; p < a.hpasses; ++p) {
-    if (hist[p][t]) atomicAdd(&hdst[p * 256 + t], hist[p][t]);
-    hist[p][t] = 0u;
-  }
-  __syncthreads();
+    __syncthreads();
+    if (a.cnt0) a.cnt0[(uint64_t)eb * 256 + t] = hist[0][t];
+    uint32_t* hdst = a.hpart + (size_t)(eb % (unsigned)a.hcopies) * a.hpasses * 256;
+    for (int p = 0; p < a.hpasses; ++p) {
+      if (hist[p][t]) atomicAdd(&hdst[p * 256 + t], hist[p][t]);
+      hist[p][t] = 0u;
+    }
+    __syncthreads();
   }
   __syncthreads();
   for (int k = t; k < n_rows; k += 256)
