@@ -1268,20 +1268,26 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
   // columns 4l..4l+3, which the padding spreads over the banks
   constexpr int PC = 256 + 8;
   auto pc = [](uint32_t c) { return c + (c >> 5); };
+  // (LDS sized for four workgroups per CU: the end masks and the column
+  // counts share the staging area, and the piece table takes only the
+  // launch's rows)
   __shared__ uint64_t S[4][PC];               // per wave: lanes whose item starts at / covers each column
-  __shared__ uint64_t E[4][PC];               // per wave: lanes whose item ends at each column
   __shared__ uint2 BS[4][PC];                 // per wave and column: (staging base, global base)
   __shared__ union {
     uint2 st[RB_STG + 64];                    // staged placements (record, global position),
                                               // then one spare slot per lane
-    uint32_t cnt[4][PC];                      // per wave: covering lanes per column (before staging)
+    struct {
+      uint64_t e[4][PC];                      // per wave: lanes whose item ends at each column
+      uint32_t cnt[4][PC];                    // per wave: covering lanes per column
+    } c;                                      // (both before staging)
   } SG;
   __shared__ uint32_t gb[256];                // next global position of each column in this piece
   __shared__ uint32_t ws[4];
   __shared__ uint32_t s_info[4];
   __shared__ uint32_t s_tot;
-  __shared__ uint32_t pt[2 * (RB_MAX_ROWS + 1)];   // the piece table
+  extern __shared__ uint32_t pt[];            // the piece table, 2 (R + 1) words
   __shared__ ViewTable vt;
+  auto& E = SG.c.e;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const uint32_t P = ptab[R];
   // every position below the capacity (the usual case): the write-out
@@ -1290,10 +1296,7 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
   for (int k = t; k < 2 * (R + 1); k += 256) pt[k] = ptab[k];
   load_views(cams, n_views, vt);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    S[wv][pc(4 * lane + q)] = 0ull;
-    E[wv][pc(4 * lane + q)] = 0ull;
-  }
+  for (int q = 0; q < 4; ++q) S[wv][pc(4 * lane + q)] = 0ull;
   __syncthreads();
   const uint64_t lt = lanemask_lt();
   // pieces in 8 contiguous chunks, one per XCD (workgroup i runs on XCD
@@ -1332,7 +1335,11 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
         nval = i2 < e ? iv[i2] : 0u;
       }
       const uint32_t x0 = item_x0(key), w = valid ? item_w(key) : 0u;
-      // (this wave's S and E rows are zero here)
+      // (this wave's S row is zero here; its E row shares the staging area,
+      // which every wave has finished reading, and is cleared first)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) E[wv][pc(4 * lane + q)] = 0ull;
+      __builtin_amdgcn_wave_barrier();
       if (valid) {
         atomicOr(reinterpret_cast<unsigned long long*>(&S[wv][pc(x0)]), 1ull << lane);
         if (x0 + w < 256u) atomicOr(reinterpret_cast<unsigned long long*>(&E[wv][pc(x0 + w)]), 1ull << lane);
@@ -1341,13 +1348,11 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
       {
         // inclusive OR prefixes over the columns (lane l: columns 4l..4l+3),
         // then cover = started & ~ended
-        // (E is cleared as it is read: the next group's atomics need it zero)
         uint64_t a[4], b[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           a[q] = S[wv][pc(4 * lane + q)];
           b[q] = E[wv][pc(4 * lane + q)];
-          E[wv][pc(4 * lane + q)] = 0ull;
           if (q > 0) {
             a[q] |= a[q - 1];
             b[q] |= b[q - 1];
@@ -1363,17 +1368,17 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
         for (int q = 0; q < 4; ++q) {
           const uint64_t cov = (a[q] | pa) & ~(b[q] | pb);
           S[wv][pc(4 * lane + q)] = cov;
-          SG.cnt[wv][pc(4 * lane + q)] = (uint32_t)__popcll(cov);
+          SG.c.cnt[wv][pc(4 * lane + q)] = (uint32_t)__popcll(cov);
         }
       }
       __syncthreads();
       uint32_t c0, c1, c2, gc;
       {
         const uint32_t pt_ = pc(t);
-        c0 = SG.cnt[0][pt_];
-        c1 = SG.cnt[1][pt_];
-        c2 = SG.cnt[2][pt_];
-        gc = c0 + c1 + c2 + SG.cnt[3][pt_];
+        c0 = SG.c.cnt[0][pt_];
+        c1 = SG.c.cnt[1][pt_];
+        c2 = SG.c.cnt[2][pt_];
+        gc = c0 + c1 + c2 + SG.c.cnt[3][pt_];
       }
       // staging start of column t: an exclusive scan over the columns (DPP
       // within each wave, the waves' totals through LDS)
@@ -1815,8 +1820,9 @@ static sgs_status bin_rows(const sgs_geom* g, DupArgs a, const BinLayout& L, con
   SGS_LAUNCH_CHECK();
   if (C > 0) {
     const unsigned rgrid = (pgrid + 7u) & ~7u;   // a multiple of 8 (the XCD chunks)
-    k_row_place<<<rgrid, 256, 0, s>>>(ik[0], iv[0], L.ptab, R, nb_shift, cams_dev, n_views, L.pre_col, ranges,
-                                      (uint32_t)T, (uint32_t)C, vals, keys, g->depth, mm, n_inst);
+    const size_t pt_bytes = 2 * ((size_t)R + 1) * sizeof(uint32_t);   // (the piece table)
+    k_row_place<<<rgrid, 256, pt_bytes, s>>>(ik[0], iv[0], L.ptab, R, nb_shift, cams_dev, n_views, L.pre_col,
+                                             ranges, (uint32_t)T, (uint32_t)C, vals, keys, g->depth, mm, n_inst);
     SGS_LAUNCH_CHECK();
   }
   return SGS_OK;
