@@ -426,7 +426,7 @@ def batched(steps: int, warmup: int, small: bool = False):
 
 
 SERVE_RATES = [60, 120, 240, 600]
-OPT_OVER: dict = {}        # option overrides from the command line (--sort-mode)
+OPT_OVER: dict = {}        # option overrides from the command line (--sort-mode, --blend-batch)
 
 
 def serving(duration_s: float, rates):
@@ -493,12 +493,17 @@ def main():
                     help="run one workload only (for profiler runs)")
     ap.add_argument("--sort-mode", type=int, default=None, choices=[0, 1, 2],
                     help="override the library's default sort mode in every workload")
+    ap.add_argument("--blend-batch", type=int, default=None, choices=[64, 128, 256],
+                    help="override the records staged per LDS batch in the blends (default: "
+                         "the library's, 128 forward and 256 backward)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
                          "kernel that scales hardware byte counters)")
     args = ap.parse_args()
     if args.sort_mode is not None:
         OPT_OVER["sort_mode"] = args.sort_mode
+    if args.blend_batch is not None:
+        OPT_OVER["blend_batch"] = args.blend_batch
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
         print("bench.py measures one GPU: this build renders on a single MI355X "
