@@ -1256,6 +1256,7 @@ __global__ void __launch_bounds__(256) k_col_scan(const uint32_t* __restrict__ c
 // placements are staged column by column in LDS and written out in that
 // order (runs of consecutive positions); a group with more than RB_STG
 // placements (or with keys requested) writes them directly.
+template <int NCOL>
 __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ ik, const uint32_t* __restrict__ iv,
                                                    const uint32_t* __restrict__ ptab, int R, int nb_shift,
                                                    const sgs_camera* cams, int n_views,
@@ -1264,13 +1265,15 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
                                                    uint32_t cap, uint32_t* __restrict__ vals,
                                                    uint64_t* __restrict__ keys, const float* __restrict__ depth,
                                                    uint64_t m, const uint32_t* __restrict__ n_total) {
+  // NCOL columns (128 or 256: at least the widest view's tiles per row);
   // per-column arrays are indexed by pc(c) = c + c / 32: lane l scans
-  // columns 4l..4l+3, which the padding spreads over the banks
-  constexpr int PC = 256 + 8;
+  // columns CPL l .. CPL l + CPL - 1, which the padding spreads over the banks
+  constexpr int CPL = NCOL / 64;
+  constexpr int PC = NCOL + NCOL / 32;
   auto pc = [](uint32_t c) { return c + (c >> 5); };
-  // (LDS sized for four workgroups per CU: the end masks and the column
-  // counts share the staging area, and the piece table takes only the
-  // launch's rows)
+  // (LDS sized for four workgroups per CU, five with 128 columns: the end
+  // masks and the column counts share the staging area, and the piece table
+  // takes only the launch's rows)
   __shared__ uint64_t S[4][PC];               // per wave: lanes whose item starts at / covers each column
   __shared__ uint2 BS[4][PC];                 // per wave and column: (staging base, global base)
   __shared__ union {
@@ -1281,7 +1284,6 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
       uint32_t cnt[4][PC];                    // per wave: covering lanes per column
     } c;                                      // (both before staging)
   } SG;
-  __shared__ uint32_t gb[256];                // next global position of each column in this piece
   __shared__ uint32_t ws[4];
   __shared__ uint32_t s_info[4];
   __shared__ uint32_t s_tot;
@@ -1296,9 +1298,10 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
   for (int k = t; k < 2 * (R + 1); k += 256) pt[k] = ptab[k];
   load_views(cams, n_views, vt);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) S[wv][pc(4 * lane + q)] = 0ull;
+  for (int q = 0; q < CPL; ++q) S[wv][pc(CPL * lane + q)] = 0ull;
   __syncthreads();
   const uint64_t lt = lanemask_lt();
+  uint32_t gb = 0;   // thread t < NCOL: next global position of column t in this piece
   // pieces in 8 contiguous chunks, one per XCD (workgroup i runs on XCD
   // i mod 8): neighbouring pieces, whose runs of a column abut in the
   // output, share an L2 and complete each other's lines there
@@ -1318,9 +1321,9 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
     }
     __syncthreads();
     const uint32_t s = s_info[0], e = s_info[1], t0 = s_info[2], tx = s_info[3];
-    {
+    if (t < NCOL) {
       const bool ok = (uint32_t)t < tx && (uint64_t)t0 + t < n_tiles;
-      gb[t] = (ok ? ranges[2 * (uint64_t)(t0 + t)] : 0u) + pre_col[(uint64_t)p * 256 + t];
+      gb = (ok ? ranges[2 * (uint64_t)(t0 + t)] : 0u) + pre_col[(uint64_t)p * 256 + t];
     }
     uint32_t nkey = s + t < e ? ik[s + t] : 0u;
     uint32_t nval = s + t < e ? iv[s + t] : 0u;
@@ -1338,21 +1341,21 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
       // (this wave's S row is zero here; its E row shares the staging area,
       // which every wave has finished reading, and is cleared first)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) E[wv][pc(4 * lane + q)] = 0ull;
+      for (int q = 0; q < CPL; ++q) E[wv][pc(CPL * lane + q)] = 0ull;
       __builtin_amdgcn_wave_barrier();
       if (valid) {
         atomicOr(reinterpret_cast<unsigned long long*>(&S[wv][pc(x0)]), 1ull << lane);
-        if (x0 + w < 256u) atomicOr(reinterpret_cast<unsigned long long*>(&E[wv][pc(x0 + w)]), 1ull << lane);
+        if (x0 + w < (uint32_t)NCOL) atomicOr(reinterpret_cast<unsigned long long*>(&E[wv][pc(x0 + w)]), 1ull << lane);
       }
       __builtin_amdgcn_wave_barrier();
       {
-        // inclusive OR prefixes over the columns (lane l: columns 4l..4l+3),
+        // inclusive OR prefixes over the columns (lane l: its CPL columns),
         // then cover = started & ~ended
-        uint64_t a[4], b[4];
+        uint64_t a[CPL], b[CPL];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          a[q] = S[wv][pc(4 * lane + q)];
-          b[q] = E[wv][pc(4 * lane + q)];
+        for (int q = 0; q < CPL; ++q) {
+          a[q] = S[wv][pc(CPL * lane + q)];
+          b[q] = E[wv][pc(CPL * lane + q)];
           if (q > 0) {
             a[q] |= a[q - 1];
             b[q] |= b[q - 1];
@@ -1360,20 +1363,22 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
         }
         // inclusive OR over the lanes' totals (DPP, per 32-bit half), then
         // the exclusive one from the lane below
-        const uint64_t xa = ((uint64_t)wave_incl_or((uint32_t)(a[3] >> 32)) << 32) | wave_incl_or((uint32_t)a[3]);
-        const uint64_t xb = ((uint64_t)wave_incl_or((uint32_t)(b[3] >> 32)) << 32) | wave_incl_or((uint32_t)b[3]);
+        const uint64_t xa = ((uint64_t)wave_incl_or((uint32_t)(a[CPL - 1] >> 32)) << 32) |
+                            wave_incl_or((uint32_t)a[CPL - 1]);
+        const uint64_t xb = ((uint64_t)wave_incl_or((uint32_t)(b[CPL - 1] >> 32)) << 32) |
+                            wave_incl_or((uint32_t)b[CPL - 1]);
         uint64_t pa = __shfl_up(xa, 1), pb = __shfl_up(xb, 1);
         if (lane == 0) pa = pb = 0ull;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < CPL; ++q) {
           const uint64_t cov = (a[q] | pa) & ~(b[q] | pb);
-          S[wv][pc(4 * lane + q)] = cov;
-          SG.c.cnt[wv][pc(4 * lane + q)] = (uint32_t)__popcll(cov);
+          S[wv][pc(CPL * lane + q)] = cov;
+          SG.c.cnt[wv][pc(CPL * lane + q)] = (uint32_t)__popcll(cov);
         }
       }
       __syncthreads();
-      uint32_t c0, c1, c2, gc;
-      {
+      uint32_t c0 = 0, c1 = 0, c2 = 0, gc = 0;   // (threads past the columns: none)
+      if (t < NCOL) {
         const uint32_t pt_ = pc(t);
         c0 = SG.c.cnt[0][pt_];
         c1 = SG.c.cnt[1][pt_];
@@ -1388,13 +1393,13 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
       uint32_t gs = inc - gc;
       for (int q = 0; q < wv; ++q) gs += ws[q];
       const uint32_t T = ws[0] + ws[1] + ws[2] + ws[3];
-      {
-        const uint32_t g = gb[t], pt_ = pc(t);
+      if (t < NCOL) {
+        const uint32_t g = gb, pt_ = pc(t);
         BS[0][pt_] = make_uint2(gs, g);
         BS[1][pt_] = make_uint2(gs + c0, g + c0);
         BS[2][pt_] = make_uint2(gs + c0 + c1, g + c0 + c1);
         BS[3][pt_] = make_uint2(gs + c0 + c1 + c2, g + c0 + c1 + c2);
-        gb[t] = g + gc;
+        gb = g + gc;
       }
       __syncthreads();
       // (block-uniform, tested once: two loops rather than a test per
@@ -1406,7 +1411,7 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
           uint64_t cv[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const uint32_t c = pc(min(x0 + kk + u, 255u));
+            const uint32_t c = pc(min(x0 + kk + u, (uint32_t)NCOL - 1u));
             bs[u] = BS[wv][c];
             cv[u] = S[wv][c];
           }
@@ -1425,7 +1430,7 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
           uint64_t cv[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const uint32_t c = pc(min(x0 + kk + u, 255u));
+            const uint32_t c = pc(min(x0 + kk + u, (uint32_t)NCOL - 1u));
             bs[u] = BS[wv][c];
             cv[u] = S[wv][c];
           }
@@ -1473,7 +1478,7 @@ __global__ void __launch_bounds__(256) k_row_place(const uint32_t* __restrict__ 
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) S[wv][pc(4 * lane + q)] = 0ull;
+      for (int q = 0; q < CPL; ++q) S[wv][pc(CPL * lane + q)] = 0ull;
       __syncthreads();
     }
   }
@@ -1761,7 +1766,8 @@ constexpr int DEPTH_BITS_WIDE = 30;
 static sgs_status bin_rows(const sgs_geom* g, DupArgs a, const BinLayout& L, const RsScratch& sc_main,
                            const uint32_t* order, int64_t m, int32_t n_views, const sgs_camera* cams_dev,
                            uint64_t T, uint64_t C, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
-                           uint32_t* n_inst, uint32_t* tile_order, int32_t rb_rows, hipStream_t s) {
+                           uint32_t* n_inst, uint32_t* tile_order, int32_t rb_rows, int32_t rb_tx,
+                           hipStream_t s) {
   uint32_t* err = L.misc;
   uint32_t* n_items = L.misc + 1;   // row items (zeroed with misc)
   uint32_t* row_cnt = L.cnt_tile + T;
@@ -1821,8 +1827,16 @@ static sgs_status bin_rows(const sgs_geom* g, DupArgs a, const BinLayout& L, con
   if (C > 0) {
     const unsigned rgrid = (pgrid + 7u) & ~7u;   // a multiple of 8 (the XCD chunks)
     const size_t pt_bytes = 2 * ((size_t)R + 1) * sizeof(uint32_t);   // (the piece table)
-    k_row_place<<<rgrid, 256, pt_bytes, s>>>(ik[0], iv[0], L.ptab, R, nb_shift, cams_dev, n_views, L.pre_col,
-                                             ranges, (uint32_t)T, (uint32_t)C, vals, keys, g->depth, mm, n_inst);
+    // (128 columns when every view's rows have at most 128 tiles: half the
+    // per-column LDS and scan work, five workgroups per CU instead of four)
+    if (rb_tx <= 128)
+      k_row_place<128><<<rgrid, 256, pt_bytes, s>>>(ik[0], iv[0], L.ptab, R, nb_shift, cams_dev, n_views,
+                                                    L.pre_col, ranges, (uint32_t)T, (uint32_t)C, vals, keys,
+                                                    g->depth, mm, n_inst);
+    else
+      k_row_place<256><<<rgrid, 256, pt_bytes, s>>>(ik[0], iv[0], L.ptab, R, nb_shift, cams_dev, n_views,
+                                                    L.pre_col, ranges, (uint32_t)T, (uint32_t)C, vals, keys,
+                                                    g->depth, mm, n_inst);
     SGS_LAUNCH_CHECK();
   }
   return SGS_OK;
@@ -1832,10 +1846,10 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
                            int32_t n_views, int64_t total_tiles, const sgs_options* opt,
                            int64_t cap, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                            uint32_t* n_inst, uint32_t* tile_order, void* scratch, float near_min,
-                           int32_t rb_rows, hipStream_t s) {
+                           int32_t rb_rows, int32_t rb_tx, hipStream_t s) {
   // sort mode 2 runs when the caller found its conditions met (rb_rows > 0:
-  // the global tile rows); otherwise mode 1, in the same (larger) scratch
-  // layout
+  // the global tile rows; rb_tx: the most tiles per row of any view);
+  // otherwise mode 1, in the same (larger) scratch layout
   const int mode = opt->sort_mode == 2 && rb_rows == 0 ? 1 : opt->sort_mode;
   const bool wide = mode >= 1 && opt->depth_digit_bits == 10 && wide_depth((uint64_t)m, near_min);
   const BinLayout L = bin_layout(reinterpret_cast<uintptr_t>(scratch), m, cap, total_tiles, opt->sort_mode);
@@ -1964,7 +1978,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   if (st != SGS_OK) return st;
   const uint32_t* order = dv[0];
   if (mode == 2) return bin_rows(g, a, L, sc_main, order, m, n_views, cams_dev, T, C, keys, vals, ranges, n_inst,
-                                 tile_order, rb_rows, s);
+                                 tile_order, rb_rows, rb_tx, s);
   k_sorted_offsets<<<(unsigned)cdiv(mm, SO_TILE), 256, 0, s>>>(
       order, g->tiles, m, L.offs, n_inst, reinterpret_cast<uint64_t*>(L.so_status + 64), L.so_status, err,
       L.bstart, (uint32_t)L.n_bstart, ex_shift_for(C), nullptr, nullptr);

@@ -20,7 +20,7 @@ size_t bin_sort_scratch_bytes(int64_t m, int64_t cap, int64_t total_tiles, int m
 sgs_status launch_bin_sort(const sgs_geom*, int64_t m, int64_t n, const sgs_camera*, int32_t,
                            int64_t total_tiles, const sgs_options*, int64_t cap, uint64_t*,
                            uint32_t*, uint32_t*, uint32_t*, uint32_t* tile_order, void*,
-                           float near_min, int32_t rb_rows, hipStream_t);
+                           float near_min, int32_t rb_rows, int32_t rb_tx, hipStream_t);
 sgs_status launch_blend_fwd(const sgs_geom*, int64_t, const uint32_t*, int64_t, const uint32_t*,
                             const sgs_schedule*, const sgs_camera*, int32_t, int64_t, int,
                             const sgs_options*, float*, float*, uint32_t*, uint32_t*, uint32_t*,
@@ -302,11 +302,13 @@ sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_hos
   float near_min = cams_host[0].near_z;
   for (int v = 1; v < n_views; ++v) near_min = std::min(near_min, cams_host[v].near_z);
   const int32_t rb_rows = mode == 2 ? rowbin_rows(cams_host, n_views, m == 0 || g->rows) : 0;
+  int32_t rb_tx = 1;   // the most tiles per row of any view (sizes the placement's columns)
+  for (int v = 0; v < n_views; ++v) rb_tx = std::max(rb_tx, cams_host[v].tiles_x);
   sgs_options o = *opt;
   o.sort_mode = mode;
   return sgs::launch_bin_sort(g, m, m / n_views, cams_dev, n_views, tt, &o, inst_capacity, keys,
                               vals, tile_ranges, n_inst_dev, sched ? sched->tile_order : nullptr,
-                              scratch, near_min, rb_rows, (hipStream_t)stream);
+                              scratch, near_min, rb_rows, rb_tx, (hipStream_t)stream);
 }
 
 sgs_status sgs_bin_sort_noalloc(const sgs_geom* g, int64_t m, const sgs_camera* cams_host,
