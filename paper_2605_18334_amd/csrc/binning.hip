@@ -1876,18 +1876,16 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
   zero(n_inst, 1);
   zero(L.misc, 64);
   if (C > 0) {
-    // large mode-1 sorts: the first pass takes scanned offsets and has no
-    // look-back, so its block statuses stay untouched (not cleared)
+    // block statuses of the passes that look back: large sorts take scanned
+    // offsets in their first pass (its statuses stay untouched), and the row
+    // sort of mode 2 runs its own (fewer) passes in the tile sort's layout
     const bool scan0 = mode >= 1 && cdiv(C, (uint64_t)RS_T * RS_IPT) > RS_WIDE_MAX_BLOCKS;
-    const uint64_t words = rs_words(C, L.main_passes);
     const uint64_t head = 64 + (uint64_t)L.main_passes * 256 * (1 + HC);   // counters, histograms
-    const uint64_t st0 = rs_blocks(C) * 256 * 2;                             // pass 0's statuses
-    if (scan0) {
-      zero(L.rs_main, head);
-      zero(L.rs_main + head + st0, words - head - st0);
-    } else {
-      zero(L.rs_main, words);
-    }
+    const uint64_t st0 = rs_blocks(C) * 256 * 2;                             // one pass's statuses
+    const int used = mode == 2 ? rs_passes(tile_bits(rb_rows)) : L.main_passes;
+    const int first = scan0 ? 1 : 0;
+    zero(L.rs_main, head);
+    if (used > first) zero(L.rs_main + head + (uint64_t)first * st0, (uint64_t)(used - first) * st0);
   }
   if (mode >= 1 && m > 0) {
     zero(L.rs_depth, wide ? rs_words((uint64_t)m, 3, 1024) : rs_words((uint64_t)m, 4));
