@@ -170,10 +170,18 @@ __global__ void __launch_bounds__(RS_T) k_os_hist(const K* __restrict__ keys, co
 // levels: k_chunk_scan turns each chunk of EC consecutive blocks into
 // exclusive prefixes within the chunk (one workgroup per chunk, one thread
 // per digit) and stores the chunk totals; k_chunk_totals scans those.  The
-// keys of digit d before block e number cnt[e][d] + tot[e / EC][d].
+// keys of digit d before block e number cnt[e][d] + tot[e / EC][d].  Only
+// the blocks that hold keys (min(*count_p, cap) keys in blocks of 2^shift)
+// have counts: the rest of the capacity's blocks are neither read nor
+// written (no pass block reads them).
 __global__ void __launch_bounds__(256) k_chunk_scan(uint32_t* __restrict__ cnt, uint32_t n,
-                                                    uint32_t* __restrict__ tot) {
+                                                    uint32_t* __restrict__ tot,
+                                                    const uint32_t* __restrict__ count_p, uint32_t cap,
+                                                    int shift) {
   const uint32_t t = threadIdx.x, e0 = blockIdx.x * EC;
+  const uint32_t c = *count_p;
+  const uint64_t keys = c < cap ? c : cap;
+  n = (uint32_t)min((uint64_t)n, (keys + (1ull << shift) - 1) >> shift);
   uint32_t x[EC];
 #pragma unroll
   for (int i = 0; i < EC; ++i) x[i] = e0 + i < n ? cnt[(uint64_t)(e0 + i) * 256 + t] : 0u;
@@ -663,10 +671,7 @@ __global__ void __launch_bounds__(256) k_expand32(DupArgs a) {
   const uint32_t total = *a.n_inst;
   const uint32_t n = total < a.cap ? total : a.cap;
   const uint64_t o0 = (uint64_t)blockIdx.x * EXT;
-  if (o0 >= n) {   // no instances: zero counts for the first pass's column scan
-    if (a.cnt0) a.cnt0[(uint64_t)blockIdx.x * 256 + threadIdx.x] = 0u;
-    return;
-  }
+  if (o0 >= n) return;   // no instances (and no counts: the scan stops before this block)
   const uint64_t o1 = min(o0 + (uint64_t)EXT, (uint64_t)n);
   const int t = threadIdx.x;
   const uint32_t dmask = (1u << a.hwidth) - 1u;
@@ -980,10 +985,7 @@ __global__ void __launch_bounds__(256) k_emit_rows(DupArgs a, const uint32_t* __
   // emission blocks eb = blockIdx.x, + gridDim.x, ...
   for (uint32_t eb = blockIdx.x; eb < n_eblocks; eb += gridDim.x) {
     const uint64_t o0 = (uint64_t)eb * EXT;
-    if (o0 >= n) {   // no items: zero counts for the first pass's column scan
-      if (a.cnt0) a.cnt0[(uint64_t)eb * 256 + t] = 0u;
-      continue;
-    }
+    if (o0 >= n) continue;   // no items (and no counts: the scan stops before this block)
     const uint64_t o1 = min(o0 + (uint64_t)EXT, (uint64_t)n);
     if (t == 0) {
       const uint64_t jlo = min((uint64_t)a.bstart[eb], (uint64_t)a.m - 1);
@@ -1808,7 +1810,7 @@ static sgs_status bin_rows(const sgs_geom* g, DupArgs a, const BinLayout& L, con
     SGS_LAUNCH_CHECK();
     if (scan0) {
       const uint32_t nch = (uint32_t)cdiv(ex_blocks, EC);
-      k_chunk_scan<<<nch, 256, 0, s>>>(L.cnt0, (uint32_t)ex_blocks, L.ctot);
+      k_chunk_scan<<<nch, 256, 0, s>>>(L.cnt0, (uint32_t)ex_blocks, L.ctot, n_items, (uint32_t)C, ex_shift);
       SGS_LAUNCH_CHECK();
       k_chunk_totals<<<256, 256, 0, s>>>(L.ctot, nch);
       SGS_LAUNCH_CHECK();
@@ -2010,7 +2012,7 @@ sgs_status launch_bin_sort(const sgs_geom* g, int64_t m, int64_t n, const sgs_ca
     SGS_LAUNCH_CHECK();
     if (scan0) {
       const uint32_t nch = (uint32_t)cdiv(ex_blocks, EC);
-      k_chunk_scan<<<nch, 256, 0, s>>>(L.cnt0, (uint32_t)ex_blocks, L.ctot);
+      k_chunk_scan<<<nch, 256, 0, s>>>(L.cnt0, (uint32_t)ex_blocks, L.ctot, n_inst, (uint32_t)C, ex_shift);
       SGS_LAUNCH_CHECK();
       k_chunk_totals<<<256, 256, 0, s>>>(L.ctot, nch);
       SGS_LAUNCH_CHECK();
