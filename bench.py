@@ -426,7 +426,8 @@ def batched(steps: int, warmup: int, small: bool = False):
 
 
 SERVE_RATES = [60, 120, 240, 600]
-OPT_OVER: dict = {}        # option overrides from the command line (--sort-mode, --blend-batch)
+OPT_OVER: dict = {}        # option overrides from the command line (--sort-mode, --blend-batch,
+                           # --blend-lists)
 
 
 def serving(duration_s: float, rates):
@@ -496,6 +497,9 @@ def main():
     ap.add_argument("--blend-batch", type=int, default=None, choices=[64, 128, 256],
                     help="override the records staged per LDS batch in the blends (default: "
                          "the library's, 128 forward and 256 backward)")
+    ap.add_argument("--blend-lists", type=int, default=None, choices=[1, 4],
+                    help="override the forward blend's record lists per wave (default: the "
+                         "library's choice from the instance capacity per record)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
                          "kernel that scales hardware byte counters)")
@@ -504,6 +508,8 @@ def main():
         OPT_OVER["sort_mode"] = args.sort_mode
     if args.blend_batch is not None:
         OPT_OVER["blend_batch"] = args.blend_batch
+    if args.blend_lists is not None:
+        OPT_OVER["blend_lists"] = args.blend_lists
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
         print("bench.py measures one GPU: this build renders on a single MI355X "

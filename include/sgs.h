@@ -164,6 +164,14 @@ typedef struct {
                               passes measured slower on gfx950: each pass's
                               LDS ranking grows with the digit).  Same order
                               either way.                                   */
+  int32_t blend_lists;     /* [0] record lists of the forward blend's tiles
+                              (Alg. 1 walks a tile's records front to back;
+                              a list holds the ones whose extent reaches a
+                              pixel block): 1, one per wave's 8x8 block; 4,
+                              one per 4x4 quarter of it (fewer steps where
+                              records are small, each step dearer); 0: 4
+                              when the instance capacity is at most 8 per
+                              record, else 1.  Same images either way.      */
 } sgs_options;
 
 /* Projected per-record data written by sgs_preprocess, record m = v*N + i for

@@ -38,7 +38,8 @@ class Options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("filter_s", C.c_float),
                 ("compensate", C.c_int32), ("guard", C.c_float), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("t_min", C.c_float), ("sort_mode", C.c_int32),
-                ("blend_batch", C.c_int32), ("split_tiles", C.c_int32), ("depth_digit_bits", C.c_int32)]
+                ("blend_batch", C.c_int32), ("split_tiles", C.c_int32), ("depth_digit_bits", C.c_int32),
+                ("blend_lists", C.c_int32)]
 
 
 class Geom(C.Structure):

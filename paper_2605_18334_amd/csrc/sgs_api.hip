@@ -47,7 +47,8 @@ bool options_ok(const sgs_options* o) {
          o->guard > 0.0f && o->alpha_min > 0.0f && o->alpha_min < o->alpha_max &&
          o->alpha_max < 1.0f && o->t_min > 0.0f && o->t_min < 1.0f &&
          (o->sort_mode >= -1 && o->sort_mode <= 2) && o->split_tiles >= -1 &&
-         (o->depth_digit_bits == 0 || o->depth_digit_bits == 8 || o->depth_digit_bits == 10);
+         (o->depth_digit_bits == 0 || o->depth_digit_bits == 8 || o->depth_digit_bits == 10) &&
+         (o->blend_lists == 0 || o->blend_lists == 1 || o->blend_lists == 4);
 }
 
 bool params_ok(const sgs_params* p) {
@@ -125,6 +126,7 @@ void sgs_default_options(sgs_options* o) {
   o->blend_batch = 0;
   o->split_tiles = -1;
   o->depth_digit_bits = 0;
+  o->blend_lists = 0;
 }
 
 size_t sgs_struct_size(int32_t which) {

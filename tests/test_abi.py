@@ -46,7 +46,7 @@ def test_default_options_and_status_strings():
     _abi, lib = _lib()
     o = _abi.default_options()
     assert (o.tile_w, o.tile_h, o.blend_batch, o.sort_mode, o.compensate) == (16, 16, 0, -1, 1)
-    assert o.split_tiles == -1 and o.depth_digit_bits == 0
+    assert o.split_tiles == -1 and o.depth_digit_bits == 0 and o.blend_lists == 0
     assert o.alpha_min == pytest.approx(1 / 255) and o.alpha_max == pytest.approx(0.99)
     assert o.t_min == pytest.approx(1e-4) and o.filter_s == pytest.approx(0.3)
     assert lib.sgs_status_string(0) == b"ok"
@@ -139,7 +139,7 @@ def test_options_are_validated_on_the_host():
     assert lib.sgs_camera_layout(cams, 1, C.byref(ok), C.byref(tt), C.byref(tp)) == 0
     assert (tt.value, tp.value) == (4 * 3, 64 * 48)
     for bad in (dict(tile_w=32), dict(blend_batch=100), dict(sort_mode=3), dict(sort_mode=-2), dict(split_tiles=-2),
-                dict(alpha_min=0.0), dict(t_min=1.0), dict(depth_digit_bits=11)):
+                dict(alpha_min=0.0), dict(t_min=1.0), dict(depth_digit_bits=11), dict(blend_lists=2)):
         o = _abi.default_options(**bad)
         assert lib.sgs_camera_layout(cams, 1, C.byref(o), C.byref(tt), C.byref(tp)) == 1, bad
 

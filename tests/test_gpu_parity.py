@@ -299,6 +299,39 @@ def test_tile_shapes_and_batches_give_identical_images(tile, batch):
     np.testing.assert_array_equal(_np(a.out_T), _np(b.out_T))
 
 
+@pytest.mark.parametrize("case", ["tiny", "ragged_enhanced", "small_many"])
+@pytest.mark.parametrize("tile,batch,sched", [((16, 16), 0, "split"), ((16, 16), 64, "order"),
+                                              ((16, 16), 256, "persistent"), ((16, 8), 0, "order"),
+                                              ((8, 8), 128, "none")])
+def test_blend_lists_give_identical_outputs(case, tile, batch, sched):
+    """Quarter lists (blend_lists 4) and wave lists (1) give every pixel the
+    same records in the same order: colour, transmittance, last contributor
+    and composited count agree bit for bit, for each tile shape, batch size
+    and tile schedule (split tiles, a tile order, the persistent queue)."""
+    P = _P()
+    if case == "tiny":
+        sc, pose = S.tiny_config()
+    elif case == "ragged_enhanced":
+        sc = S.blobs_scene(13, 1500, 1, enhanced=True)
+        pose = S.Pose(S.look_at_gl((0.5, 0.3, 7.0), up=(0, 1, 0)), 97, 45)
+    else:   # many small Gaussians: short quarter lists, several batches per tile
+        sc = S.clusters_scene(21, 20000, 0)
+        pose = S.Pose(S.look_at_gl((0.0, 0.0, 15.0), up=(0, 1, 0)), 160, 120)
+    gs = P.GaussianSet.from_scene(sc)
+    out = []
+    for ql in (1, 4):
+        o = P.default_options(tile_w=tile[0], tile_h=tile[1], blend_batch=batch, blend_lists=ql,
+                              split_tiles=-1 if sched == "split" else 0)
+        R = P.Renderer(gs, P.CameraBatch.from_poses([pose], o), o, count=True,
+                       tile_order=sched != "none", persistent=sched == "persistent")
+        R.forward()
+        torch.cuda.synchronize()
+        out.append([_np(x).copy() for x in (R.out_rgb, R.out_T, R.out_last, R.bufs["count"])])
+    assert int(out[0][3].sum()) > 0
+    for x, y in zip(*out):
+        np.testing.assert_array_equal(x, y)
+
+
 @pytest.mark.parametrize("case", ["tiny", "ragged_enhanced"])
 @pytest.mark.parametrize("split", [1, 5, 1 << 20])
 def test_split_tiles_give_identical_outputs(case, split):
