@@ -427,7 +427,7 @@ def batched(steps: int, warmup: int, small: bool = False):
 
 SERVE_RATES = [60, 120, 240, 600]
 OPT_OVER: dict = {}        # option overrides from the command line (--sort-mode, --blend-batch,
-                           # --blend-lists)
+                           # --blend-lists, --split-tiles)
 
 
 def serving(duration_s: float, rates):
@@ -500,6 +500,9 @@ def main():
     ap.add_argument("--blend-lists", type=int, default=None, choices=[1, 4],
                     help="override the forward blend's record lists per wave (default: the "
                          "library's choice from the instance capacity per record)")
+    ap.add_argument("--split-tiles", type=int, default=None,
+                    help="override how many of the longest tiles the blends split into quarters "
+                         "(default: the library's, total tiles / 128; 0: none)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
                          "kernel that scales hardware byte counters)")
@@ -510,6 +513,8 @@ def main():
         OPT_OVER["blend_batch"] = args.blend_batch
     if args.blend_lists is not None:
         OPT_OVER["blend_lists"] = args.blend_lists
+    if args.split_tiles is not None:
+        OPT_OVER["split_tiles"] = args.split_tiles
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
         print("bench.py measures one GPU: this build renders on a single MI355X "
