@@ -121,8 +121,11 @@ typedef struct {
   int64_t pix_base;        /* first pixel of this view in the output planes */
 } sgs_camera;
 
-/* Instance capacity from which sort_mode -1 runs mode 2. */
-#define SGS_AUTO_ROWBIN_CAPACITY ((int64_t)1 << 22)
+/* Instance capacity from which sort_mode -1 runs mode 2 (393,216: on
+ * clustered scenes at 1280x720 the two modes cross between 0.32M and 0.37M
+ * instances of capacity; mode 2 ran 0.2-1.2% faster from 0.37M to 0.96M and
+ * far faster at 65M, mode 1 0.8-1.8% faster below 0.32M). */
+#define SGS_AUTO_ROWBIN_CAPACITY ((int64_t)3 << 17)
 
 /* Pipeline options; sgs_default_options fills the values in brackets. */
 typedef struct {
@@ -335,9 +338,10 @@ sgs_status sgs_bin_sort(const sgs_geom* g, int64_t m, const sgs_camera* cams_hos
  * call itself allocates nothing (no hipMalloc, no allocating library
  * routine); its first call on a device looks up the array's address there.
  *  - ECAPACITY when sgs_bin_sort_scratch_bytes(m, inst_capacity, tiles, opt)
- *    exceeds SGS_NOALLOC_SCRATCH_BYTES (about 2M records and 4M instances
- *    fit; the 300k-Gaussian 1280x720 frame needs 13 MiB), checked before any
- *    work is enqueued.
+ *    exceeds SGS_NOALLOC_SCRATCH_BYTES (at 3600 tiles about 1.19M records
+ *    with twice as many instances of capacity fit, 1.27M in sort mode 1; the
+ *    300k-Gaussian 1280x720 frame needs 20.3 MiB, 14.5 MiB in mode 1),
+ *    checked before any work is enqueued.
  *  - Every call on one device shares that device's array and clears what it
  *    needs at its start (on the stream, with a fill kernel).  Calls that
  *    overlap in time on one device race on it: serialise them (one stream, or

@@ -176,7 +176,7 @@ def test_package_never_reaches_the_oracle():
 
 
 def test_bin_sort_mode_choice_on_the_host():
-    """sgs_bin_sort_mode (no GPU): auto picks row binning from 2^22 instances
+    """sgs_bin_sort_mode (no GPU): auto picks row binning from 3 * 2^17 instances
     of capacity, the tile-key sort below; row binning needs the row counts,
     at most 256 tiles per row and 1024 tile rows, else the tile-key sort
     runs; explicit modes are kept; bad arguments give -1."""
@@ -187,7 +187,7 @@ def test_bin_sort_mode_choice_on_the_host():
         cams[k].width, cams[k].height, cams[k].fx, cams[k].fy = 1600, 1064, 900.0, 900.0
     tt, tp = C.c_int64(), C.c_int64()
     assert lib.sgs_camera_layout(cams, 2, C.byref(o), C.byref(tt), C.byref(tp)) == 0
-    big, small = 1 << 22, (1 << 22) - 1
+    big, small = 3 << 17, (3 << 17) - 1
     assert lib.sgs_bin_sort_mode(C.byref(o), big, cams, 2, 1) == 2
     assert lib.sgs_bin_sort_mode(C.byref(o), small, cams, 2, 1) == 1
     assert lib.sgs_bin_sort_mode(C.byref(o), big, cams, 2, 0) == 1          # no row counts
