@@ -640,11 +640,14 @@ __device__ __forceinline__ void fwd_quad(const BlendArgs& a, int tile, int quart
 // registers; six waves per SIMD measured fastest for it (the compiler's own
 // choice, four, was slower than the wave lists); fewer where the enhanced
 // opacity, the counters or 256-record batches would spill at six (8x8 tiles:
-// their LDS already allows fewer).
+// their LDS already allows fewer).  The plain wave-list kernel of 16x16
+// tiles fits 64 registers without spilling: eight waves per SIMD (1M
+// forward blend 189 -> 177 us); its enhanced and counting variants would
+// spill there.
 template <int TW, int TH, int B, bool ENH, bool CNT, bool QL>
 __global__ void __launch_bounds__(TW * TH)
     __attribute__((amdgpu_waves_per_eu(QL && TW * TH >= 128 ? (B > 128 || (ENH && CNT) ? 4 : (ENH || CNT ? 5 : 6))
-                                                            : 1)))
+                                                            : (!QL && !ENH && !CNT && TW * TH == 256 ? 8 : 1))))
     k_blend_fwd(BlendArgs a) {
   __shared__ Stage<TW, TH, B, ENH, QL ? TW * TH / 16 : TW * TH / 64> S;
   __shared__ uint32_t s_next;
